@@ -1,0 +1,109 @@
+"""FP64 CPU oracle of the probing fit and of the fitted inverse (test infrastructure only).
+
+Basis (paper Sec. 1.2, eq. (1) and the expansion H^-1 = sum_i c_i B_i):
+elementary operators of product form, a smooth function of position times a
+Fourier multiplier, quantised as in eq. (1) (the multiplier acts first, the
+position factor multiplies the result):
+
+    B_(a,q) v = P_a(x~) * Re IFFT( rho^q * FFT(v) ),
+
+with ``P_a`` a tensor product of Legendre polynomials in the cell-centre
+coordinates ``x~ = -1 + (2i+1)/N`` of each model axis, ``rho = |k| h / pi`` the
+wavenumber normalised to 1 at the Nyquist frequency of each axis, and a
+periodic FFT on the model grid.
+
+Fit (Sec. 1.3): with x_t = H y_t, minimise over c the stacked residual
+||sum_i c_i B_i x_t - y_t|| over all trials t (the normal equations of this
+least-squares problem are the paper's M c = (B x)^T y with
+M_ij = x^T B_i^T B_j x).  Solved here by Householder QR of the stacked matrix.
+
+Fast application (Sec. 1.4, last paragraph): out = sum_i c_i B_i img.
+"""
+import numpy as np
+
+
+def legendre(deg, t):
+    """P_deg(t) by Bonnet's recurrence (n+1) P_{n+1} = (2n+1) t P_n - n P_{n-1}."""
+    t = np.asarray(t, dtype=np.float64)
+    p0 = np.ones_like(t)
+    if deg == 0:
+        return p0
+    p1 = t.copy()
+    for n in range(1, deg):
+        p0, p1 = p1, ((2 * n + 1) * t * p1 - n * p0) / (n + 1)
+    return p1
+
+
+def cell_centres(n):
+    """x~_i = -1 + (2 i + 1) / n, the cell centres of [-1, 1]."""
+    return -1.0 + (2.0 * np.arange(n) + 1.0) / n
+
+
+def position_factor(degs, shape):
+    """prod_axes P_{deg_axis}(x~_axis) on a grid of the given numpy shape."""
+    out = np.ones(shape)
+    for ax, (deg, n) in enumerate(zip(degs, shape)):
+        out = out * legendre(deg, cell_centres(n)).reshape(
+            [-1 if k == ax else 1 for k in range(len(shape))])
+    return out
+
+
+def rho(shape, h):
+    """|k| h / pi on the FFT grid, k_axis = 2 pi fftfreq(N_axis, h)."""
+    k2 = np.zeros(shape)
+    for ax, n in enumerate(shape):
+        k = 2.0 * np.pi * np.fft.fftfreq(n, d=h)
+        k2 = k2 + (k ** 2).reshape([-1 if j == ax else 1 for j in range(len(shape))])
+    return np.sqrt(k2) * h / np.pi
+
+
+def basis_list(legendre_degs, qs):
+    """Index i <-> (a, q), position factor outer, power of rho inner."""
+    return [(tuple(a), int(q)) for a in legendre_degs for q in qs]
+
+
+def apply_basis(v, h, legendre_degs, qs):
+    """All B_i v, shape (p,) + v.shape."""
+    v = np.asarray(v, dtype=np.float64)
+    r = rho(v.shape, h)
+    V = np.fft.fftn(v)
+    out = []
+    for a, q in basis_list(legendre_degs, qs):
+        filt = np.fft.ifftn(V * r ** q).real
+        out.append(position_factor(a, v.shape) * filt)
+    return np.stack(out)
+
+
+def fit(ys, xs, h, legendre_degs, qs, rank_tol=1e-12):
+    """Least-squares coefficients c with y_t ~ sum_i c_i B_i x_t for all t.
+
+    Returns (c, relres, rank_deficient): relres = ||A c - b|| / ||b|| over the
+    stacked system; when sigma_min / sigma_max < rank_tol the minimum-norm
+    solution is returned and rank_deficient is True.
+    """
+    A = np.concatenate([apply_basis(x, h, legendre_degs, qs).reshape(-1, np.size(x)).T
+                        for x in xs], axis=0)
+    b = np.concatenate([np.asarray(y, dtype=np.float64).ravel() for y in ys])
+    sv = np.linalg.svd(A, compute_uv=False)
+    deficient = bool(sv[-1] <= rank_tol * sv[0])
+    if deficient:
+        c = np.linalg.lstsq(A, b, rcond=rank_tol)[0]
+    else:
+        Q, R = np.linalg.qr(A)
+        c = np.linalg.solve(R, Q.T @ b)
+    relres = float(np.linalg.norm(A @ c - b) / np.linalg.norm(b))
+    return c, relres, deficient
+
+
+def gram(xs, ys, h, legendre_degs, qs):
+    """M = A^T A and r = A^T b of the stacked system (the paper's M and (Bx)^T y)."""
+    A = np.concatenate([apply_basis(x, h, legendre_degs, qs).reshape(-1, np.size(x)).T
+                        for x in xs], axis=0)
+    b = np.concatenate([np.asarray(y, dtype=np.float64).ravel() for y in ys])
+    return A.T @ A, A.T @ b
+
+
+def apply_Hinv(c, img, h, legendre_degs, qs):
+    """sum_i c_i B_i img."""
+    Bv = apply_basis(img, h, legendre_degs, qs)
+    return np.tensordot(np.asarray(c, dtype=np.float64), Bv, axes=1)
