@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput of the matrix-probing pass on one MI355X.
+
+Workload (default): the 512 x 256 plain FP32 configuration -- propagation
+grid 552 x 296 (20 absorbing cells per side), 64 surface sources, 256
+receivers, 12 Hz Ricker, dt = 0.8 ms, 3000 steps, FP32 fields, full FP32 g
+history, FP64 imaging; 2 random wavepacket trial functions; p = 20 basis terms
+(Legendre in depth, degrees 0-4, times rho^0..3); the fitted inverse applied to
+the remigrated image of a synthetic reflectivity by FFT multipliers.
+
+One step = the whole probing pass on inputs resident in HBM: set the
+background (drops the resident background wavefield), x_t = H y_t for both
+trials (the first computes and keeps the background, the second reuses it),
+the least-squares fit, and the fitted inverse applied to the image.
+value = apply_H propagation-grid cell-steps of the step / step time.
+
+Prints one JSON line (see the keys below).  --gpus must be 1.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def _cpu_shot(args):
+    """Oracle apply_H of one shot over the first `nsteps` steps (CPU baseline leg)."""
+    shot, nsteps = args
+    import fixtures as F
+    from oracle import Problem
+    w = F.c2().with_(nt=nsteps)
+    c = F.medium(w)
+    y = F.trials(w, c)[0]
+    P = Problem(w, c)
+    t = time.perf_counter()
+    P.apply_H(y, shots=[shot])
+    return time.perf_counter() - t
+
+
+def cpu_baseline(nsteps, workers):
+    """The FP64 oracle on a bounded sample of the workload, one shot per process."""
+    import multiprocessing as mp
+    import fixtures as F
+    w = F.c2()
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        times = pool.map(_cpu_shot, [(s, nsteps) for s in range(workers)])
+    wall = max(times)                      # the workers run concurrently
+    cell_steps = w.prop_cells * nsteps * workers
+    return {"value": cell_steps / wall / 1e9, "unit": "Gcell-steps/s", "cores": workers,
+            "kind": "oracle",
+            "sample": f"{workers} shots x {nsteps} of {w.nt} steps of apply_H (forward + adjoint), "
+                      f"FP64 numpy, one process per shot, slowest worker {wall:.1f} s"}
+
+
+def kernel_bytes(kind, w):
+    """Algorithmic HBM bytes of one launch (one time step over all shots) of a sweep kernel.
+
+    Streaming model per propagation cell-step and shot (FP32): fused forward
+    reads u, u-, du, du-, kappa, dm and writes u+, du+ (32 B) and writes g on
+    the model cells (4 B); the Born-only forward reads du, du-, kappa, dm and
+    writes du+ (20 B) and reads g (4 B per model cell); the background-only
+    sweep moves 16 B plus the g write; the adjoint reads nu, nu-, kappa and
+    writes nu+ (16 B) and, per model cell, reads g (4 B) and updates the FP64
+    image (16 B).
+    """
+    s = 4
+    prop, model, ns = w.prop_cells, w.model_cells, w.ns
+    per = {"fused": 8 * s * prop + s * model,
+           "born": 5 * s * prop + s * model,
+           "background": 4 * s * prop + s * model,
+           "adjoint": 4 * s * prop + (s + 16) * model}[kind]
+    return per * ns
+
+
+def traffic_for(kind, w):
+    """Measured HBM bytes per launch from the committed counter summary, if current."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_1101_3615_amd", "csrc", "wave2d.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    k = rec.get("kernels", {}).get(kind)
+    if not k or rec.get("wave2d_sha256") != digest or rec.get("workload") != w.name:
+        return None
+    return k.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=300, help="time steps of the CPU-baseline sample")
+    ap.add_argument("--cpu-workers", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (shots would shard "
+              "across GPUs with one all-reduce of the image; that path is not built)", file=sys.stderr)
+        sys.exit(2)
+
+    # CPU baseline first: forked workers must not inherit an initialised GPU runtime
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps, args.cpu_workers)
+
+    import numpy as np
+    import torch
+
+    import fixtures as F
+    import paper_1101_3615_amd as M
+
+    w = F.c2()
+    c = F.medium(w)
+    ys = F.trials(w, c)
+    refl = F.reflectivity(w, c)
+    dev = torch.device("cuda:0")
+    c_dev = torch.from_numpy(c).to(dev)
+    y_dev = [torch.from_numpy(y).to(dev) for y in ys]
+    P = M.Problem.from_spec(w, timing=True)
+    P.set_background(c_dev)
+    img = P.apply_H(torch.from_numpy(refl).to(dev))     # input of the fitted inverse
+    B = M.Basis(w.legendre, w.qs, w.ndim)
+    xs = [torch.empty_like(img) for _ in ys]
+    out = torch.empty_like(img)
+    torch.cuda.synchronize()
+
+    def step():
+        P.set_background(c_dev)
+        for y, x in zip(y_dev, xs):
+            P.apply_H(y, out=x)
+        coef, relres = M.probe_fit(P, B, y_dev, xs)
+        M.apply_Hinv(P, B, coef, img, out=out)
+        return relres
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    P.stats()                                   # restart the sweep timers
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        relres = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = P.stats()
+    ms_per_step = 1e3 * wall / args.steps
+    cell_steps = len(ys) * w.cell_steps
+    value = cell_steps / (wall / args.steps) / 1e9
+
+    # dominant kernel: the sweep kind with the most device time in the timed region
+    kind = max(st["ms_sweep"], key=lambda k: st["ms_sweep"][k])
+    launches = st["launches_sweep"][kind]
+    avg_s = st["ms_sweep"][kind] / 1e3 / max(launches, 1)
+    alg = kernel_bytes(kind, w)
+    achieved = alg / avg_s / 1e9
+    traffic = traffic_for(kind, w)
+    sweeps = {k: {"ms": round(st["ms_sweep"][k], 3), "launches": st["launches_sweep"][k],
+                  "us_per_launch": round(1e3 * st["ms_sweep"][k] / max(st["launches_sweep"][k], 1), 3),
+                  "alg_GBs": round(kernel_bytes(k, w) / (st["ms_sweep"][k] / 1e3 / max(st["launches_sweep"][k], 1)) / 1e9, 1)
+                  if st["launches_sweep"][k] else None}
+              for k in st["ms_sweep"]}
+    line = {
+        "metric": "Gcell-steps/s for H=F*F (fraction of HBM roofline); served p50/p99 latency",
+        "value": round(value, 3),
+        "unit": "Gcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "model_grid": [w.nx, w.nz], "prop_grid": list(reversed(w.prop_shape)),
+                   "shots": w.ns, "receivers": w.nr, "steps": w.nt, "trials": len(ys), "p": w.p,
+                   "snapshots": "fp32 full g history", "image": "fp64",
+                   "apply_H_cell_steps_per_step": cell_steps},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": kind,
+                     "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 3)},
+        "cpu_baseline": cpu,
+        "sweeps": sweeps,
+        "fit_relres": relres,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

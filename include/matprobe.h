@@ -1,0 +1,196 @@
+/*
+ * matprobe: the normal operator of the acoustic wave equation and its probed
+ * inverse, on one MI355X (gfx950).
+ *
+ * The operators follow the problem statement of Demanet et al., "Matrix
+ * probing: a randomized preconditioner for the wave-equation Hessian":
+ *   F      demigration, the Frechet derivative of the modelling map at the
+ *          background m0 = 1/c^2 (Sec. 1.1; the linearised wave equation of
+ *          Sec. 2);
+ *   F*     migration, its adjoint, computed by reverse-time propagation
+ *          (Sec. 1.1);
+ *   H      the normal operator F*F (Sec. 1.1), stacked over shots (Sec. 2);
+ *   fit    least-squares coefficients of H^-1 ~ sum_i c_i B_i from x_t = H y_t
+ *          (Sec. 1.3, expansion H^-1 = sum c_i B_i of Sec. 1.2);
+ *   Hinv   the fast application of the fitted series (end of Sec. 1.4).
+ *
+ * Discretisation (fixed by this library, identical in its CPU reference):
+ *   - model grid nx x nz (x ny in 3D), spacing h; an absorbing layer of nb
+ *     cells on every side gives the propagation grid;
+ *   - 8th-order central Laplacian, zero outside the propagation grid;
+ *   - damped leapfrog u+ = a (2u + kappa (L u + f)) - b u-, kappa = c^2 dt^2,
+ *     a = 1/(1 + eta dt/2), b = (1 - eta dt/2) a, eta quadratic in the layer
+ *     with eta_max = 3 c_max ln(1/R) / (2 nb h), zero in the model region;
+ *   - point source w(t_n) / h^ndim at one cell, w a Ricker wavelet of peak
+ *     frequency f_peak delayed by t0 (Sec. 2);
+ *   - F is the exact derivative of this scheme with respect to m, F* its exact
+ *     transpose; inner products are plain sums (Sec. 1.1).
+ *
+ * Layouts (all caller buffers are dense, C order, in the context's field
+ * precision unless stated otherwise):
+ *   model vector   [nz][ny][nx]   (ny = 1 in 2D), row iz = 0 is the surface
+ *   data           [ns][nt][nr],  d[s][n][r] = du^{n+1}(receiver r)
+ *   positions      int32 [count][ndim] model-grid indices (ix, [iy,] iz)
+ *
+ * Ownership: the caller owns every buffer passed in; pointers named *_dev
+ * are device pointers, everything else is host memory.  The library owns the
+ * context's internal device memory (wavefields, snapshot stores, images,
+ * workspaces, the cached background), allocates it lazily within the budget
+ * and frees it in mp_destroy.
+ *
+ * Ordering: calls are enqueued on the given HIP stream (a hipStream_t; NULL is
+ * the default stream) and return before the device finishes, except
+ * mp_set_background and mp_probe_fit, which synchronise that stream.  One
+ * context must not be used from two host threads at once.
+ *
+ * Errors: every call returns MP_OK or a negative code; mp_last_error() gives a
+ * message for the calling thread.  After MP_EDEVICE the context is poisoned and
+ * every later call on it returns MP_EDEVICE.
+ */
+#ifndef MATPROBE_H
+#define MATPROBE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MP_OK 0
+#define MP_EINVAL (-1)       /* bad shape, index, pointer, option, or CFL violated */
+#define MP_ENOMEM (-2)       /* budget or device memory exhausted; nothing launched */
+#define MP_EDEVICE (-3)      /* HIP error; the context is poisoned */
+#define MP_ESTATE (-4)       /* no background set */
+#define MP_ENUMERIC (-5)     /* non-finite input/output or rank-deficient fit */
+#define MP_EUNSUPPORTED (-6) /* valid request outside what this build implements */
+
+#define MP_F32 1
+#define MP_F64 2
+
+#define MP_SNAP_FULL 0      /* keep every background time level */
+#define MP_SNAP_CKPT_F32 1  /* two-level FP32 checkpoints every k steps, recompute */
+#define MP_SNAP_CKPT_BF16 2 /* BF16 checkpoints (level and increment) with FP32 scales */
+
+#define MP_OP_F 1
+#define MP_OP_FADJ 2
+#define MP_OP_H 3
+#define MP_OP_FIT 4
+#define MP_OP_HINV 5
+
+typedef struct mp_ctx mp_ctx;
+typedef struct mp_basis mp_basis;
+
+typedef struct mp_grid {
+  int ndim;   /* 2 or 3 */
+  int n[3];   /* model cells nx, ny, nz (ny = 1 in 2D) */
+  double h;   /* grid spacing [m] */
+  int nb;     /* absorbing cells on each side; a multiple of 4 */
+} mp_grid;
+
+typedef struct mp_acq {
+  int ns;          /* shots */
+  const int* src;  /* host int32 [ns][ndim]: source cell of each shot */
+  int nr;          /* receivers, shared by every shot */
+  const int* rec;  /* host int32 [nr][ndim]: receiver cells, pairwise distinct */
+  double f_peak;   /* Ricker peak frequency [Hz] */
+  double t0;       /* wavelet delay [s] */
+  double dt;       /* time step [s] */
+  int nt;          /* time steps */
+} mp_acq;
+
+typedef struct mp_opts {
+  int dtype;           /* MP_F32 or MP_F64: field, data and model precision */
+  int snap;            /* MP_SNAP_* */
+  int ckpt_every;      /* k for the checkpoint modes (>= 1) */
+  size_t budget_bytes; /* device-memory budget of the context; 0 = 90% of free memory */
+  double sponge_R;     /* nominal reflection coefficient of the layer (0 < R < 1) */
+  int timing;          /* 1: record HIP events around every sweep (read by mp_last_stats) */
+} mp_opts;
+
+#define MP_SWEEP_FUSED 0       /* forward: background and Born fields together */
+#define MP_SWEEP_BORN 1        /* forward: Born field from the resident background */
+#define MP_SWEEP_BACKGROUND 2  /* forward: background field only (store or recompute) */
+#define MP_SWEEP_ADJOINT 3     /* reverse: adjoint field and imaging */
+
+typedef struct mp_stats {
+  double cell_steps;      /* propagation-grid cell-steps of the last operator call */
+  int waves;              /* shot waves the last call was split into */
+  int background_cached;  /* 1 if the last call reused the resident background */
+  size_t bytes_reserved;  /* device memory the context holds */
+  /* with mp_opts.timing: device time of the sweeps enqueued since the previous
+   * mp_last_stats call, per sweep kind MP_SWEEP_*, from HIP events recorded on
+   * the calls' streams around each sweep (one kernel launch per time step) */
+  double ms_sweep[4];
+  long long launches_sweep[4];
+} mp_stats;
+
+/* Create a context for one grid and acquisition.  Validates every index and
+ * option; allocates only small tables.  *out receives the context. */
+int mp_create(const mp_grid* g, const mp_acq* a, const mp_opts* o, mp_ctx** out);
+void mp_destroy(mp_ctx* ctx);
+
+/* Set the background velocity c [m/s] (device, model layout, field precision;
+ * m0 = 1/c^2).  Checks the CFL bound c_max dt / h <= 2 / sqrt(ndim 2048/315)
+ * (MP_EINVAL) and finiteness (MP_ENUMERIC), builds the damping profile and
+ * drops any cached background wavefield.  Synchronises the stream. */
+int mp_set_background(mp_ctx* ctx, const void* c_dev, void* stream);
+
+/* Device bytes an operator needs with the current settings (MP_OP_*),
+ * counting the context's resident state; used for admission control. */
+int mp_footprint(const mp_ctx* ctx, int op, size_t* bytes);
+
+/* F: model perturbation dm_dev -> data d_dev (overwritten), Sec. 1.1 / Sec. 2. */
+int mp_apply_F(mp_ctx* ctx, const void* dm_dev, void* d_dev, void* stream);
+
+/* F*: data d_dev -> image img_dev (overwritten); the exact transpose of F. */
+int mp_apply_Fadj(mp_ctx* ctx, const void* d_dev, void* img_dev, void* stream);
+
+/* H = F*F: out_dev = F*(F dm_dev), fused (the data stay internal).  The
+ * image is accumulated in FP64 and rounded once to the field precision. */
+int mp_apply_H(mp_ctx* ctx, const void* dm_dev, void* out_dev, void* stream);
+
+/* Drop the cached background wavefield and free the memory it holds. */
+int mp_release_cache(mp_ctx* ctx);
+
+/* Probing basis (Sec. 1.2, eq. (1); Sec. 1.3): element i = a * nq + q is
+ * B_i v = P_a(x~) * Re IFFT(rho^q FFT v), P_a = prod over axes of Legendre
+ * polynomials of degree degs[a][axis] in the cell centres x~ = -1 + (2i+1)/N,
+ * rho = |k| h / pi, periodic FFT on the model grid.
+ * degs: host int32 [na][ndim] in axis order (x, [y,] z); qs: host int32 [nq]. */
+typedef struct mp_basis_desc {
+  int ndim;
+  int na;
+  const int* degs;
+  int nq;
+  const int* qs;
+} mp_basis_desc;
+
+int mp_basis_create(const mp_basis_desc* desc, mp_basis** out);
+void mp_basis_destroy(mp_basis* b);
+
+/* Least-squares fit of c (host, FP64, p = na * nq entries) minimising
+ * sum_t || sum_i c_i B_i x_t - y_t ||^2 over T trials (Sec. 1.3).
+ * y_dev[t], x_dev[t]: device model vectors in the field precision (x_t = H y_t).
+ * The stacked system is solved on the device in FP64 by shifted
+ * Cholesky-QR (three passes), its Gram products on the FP64 matrix cores.
+ * *relres = ||A c - b|| / ||b||.  Model sizes must be powers of two
+ * (MP_EUNSUPPORTED otherwise).  Returns MP_ENUMERIC when the system is
+ * numerically rank deficient.  Synchronises the stream. */
+int mp_probe_fit(mp_ctx* ctx, const mp_basis* basis, int T, const void* const* y_dev,
+                 const void* const* x_dev, double* c, double* relres, void* stream);
+
+/* out_dev = sum_i c_i B_i img_dev (c: host FP64 [p]); end of Sec. 1.4. */
+int mp_apply_Hinv(mp_ctx* ctx, const mp_basis* basis, const double* c, const void* img_dev,
+                  void* out_dev, void* stream);
+
+/* Statistics of the last operator call; with timing enabled, waits for the
+ * recorded events and restarts the timing accumulation. */
+int mp_last_stats(const mp_ctx* ctx, mp_stats* out);
+const char* mp_strerror(int code);
+const char* mp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MATPROBE_H */

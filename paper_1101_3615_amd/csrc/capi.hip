@@ -1,0 +1,271 @@
+// The C ABI: argument validation, error state, context lifetime.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+#include <string>
+#include <utility>
+
+#include "runtime.h"
+#include "symbol.h"
+#include "tables.h"
+
+namespace mp {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int DevBuf::ensure(size_t bytes, Budget* budget, const char* what) {
+  if (bytes <= n_ && p_) return MP_OK;
+  release();
+  if (bytes == 0) return MP_OK;
+  if (budget && budget->used + bytes > budget->limit) {
+    set_error(std::string("device-memory budget exceeded allocating ") + what + " (" +
+              std::to_string(bytes) + " bytes, " + std::to_string(budget->used) + " of " +
+              std::to_string(budget->limit) + " in use)");
+    return MP_ENOMEM;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error(std::string("hipMalloc failed for ") + what + ": " + hipGetErrorString(e));
+    return MP_ENOMEM;
+  }
+  p_ = p;
+  n_ = bytes;
+  b_ = budget;
+  if (b_) b_->used += bytes;
+  return MP_OK;
+}
+
+void DevBuf::release() {
+  if (p_) {
+    (void)hipFree(p_);
+    if (b_) b_->used -= n_;
+  }
+  p_ = nullptr;
+  n_ = 0;
+  b_ = nullptr;
+}
+
+}  // namespace mp
+
+using namespace mp;
+
+static int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+static int guard(mp_ctx* ctx) {
+  if (!ctx) return fail(MP_EINVAL, "null context");
+  if (ctx->poisoned) return fail(MP_EDEVICE, "context poisoned by an earlier device error");
+  return MP_OK;
+}
+
+static int finish(mp_ctx* ctx, int rc) {
+  if (rc == MP_EDEVICE) ctx->poisoned = true;
+  return rc;
+}
+
+extern "C" {
+
+const char* mp_strerror(int code) {
+  switch (code) {
+    case MP_OK: return "ok";
+    case MP_EINVAL: return "invalid argument";
+    case MP_ENOMEM: return "out of device memory or budget";
+    case MP_EDEVICE: return "device error";
+    case MP_ESTATE: return "no background set";
+    case MP_ENUMERIC: return "numerical failure";
+    case MP_EUNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+  }
+}
+
+const char* mp_last_error(void) { return g_err.c_str(); }
+
+int mp_create(const mp_grid* g, const mp_acq* a, const mp_opts* o, mp_ctx** out) {
+  if (!g || !a || !o || !out) return fail(MP_EINVAL, "null argument");
+  *out = nullptr;
+  if (g->ndim != 2 && g->ndim != 3) return fail(MP_EINVAL, "ndim must be 2 or 3");
+  const int nd = g->ndim;
+  const int nx = g->n[0], ny = (nd == 3) ? g->n[1] : 1, nz = g->n[2];
+  if (nd == 2 && g->n[1] != 1) return fail(MP_EINVAL, "2D grids need n[1] == 1");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(MP_EINVAL, "grid sizes must be positive");
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(MP_EINVAL, "h must be positive");
+  if (g->nb < 0 || g->nb % 4 != 0) return fail(MP_EINVAL, "nb must be a non-negative multiple of 4");
+  if (a->ns < 1 || !a->src) return fail(MP_EINVAL, "need at least one source");
+  if (a->nr < 1 || !a->rec) return fail(MP_EINVAL, "need at least one receiver");
+  if (a->nt < 1) return fail(MP_EINVAL, "nt must be positive");
+  if (!(a->dt > 0.0) || !(a->f_peak > 0.0) || !std::isfinite(a->t0))
+    return fail(MP_EINVAL, "dt and f_peak must be positive, t0 finite");
+  if (o->dtype != MP_F32 && o->dtype != MP_F64) return fail(MP_EINVAL, "dtype must be MP_F32 or MP_F64");
+  if (o->snap != MP_SNAP_FULL && o->snap != MP_SNAP_CKPT_F32 && o->snap != MP_SNAP_CKPT_BF16)
+    return fail(MP_EINVAL, "unknown snapshot mode");
+  if (o->snap != MP_SNAP_FULL && o->ckpt_every < 1) return fail(MP_EINVAL, "ckpt_every must be >= 1");
+  if (!(o->sponge_R > 0.0 && o->sponge_R < 1.0)) return fail(MP_EINVAL, "sponge_R must be in (0, 1)");
+  auto inside = [&](const int* p) {
+    if (p[0] < 0 || p[0] >= nx) return false;
+    if (nd == 3 && (p[1] < 0 || p[1] >= ny)) return false;
+    const int z = p[nd - 1];
+    return z >= 0 && z < nz;
+  };
+  for (int s = 0; s < a->ns; ++s)
+    if (!inside(a->src + (size_t)s * nd)) return fail(MP_EINVAL, "source " + std::to_string(s) + " outside the model grid");
+  std::set<std::vector<int>> seen;
+  for (int r = 0; r < a->nr; ++r) {
+    const int* p = a->rec + (size_t)r * nd;
+    if (!inside(p)) return fail(MP_EINVAL, "receiver " + std::to_string(r) + " outside the model grid");
+    if (!seen.insert(std::vector<int>(p, p + nd)).second)
+      return fail(MP_EINVAL, "receivers must occupy distinct cells");
+  }
+  if (nd == 3) return fail(MP_EUNSUPPORTED, "3D grids are not built yet");
+  if (o->snap != MP_SNAP_FULL) return fail(MP_EUNSUPPORTED, "checkpoint snapshot modes are not built yet");
+
+  mp_ctx* ctx = new mp_ctx();
+  Config& c = ctx->cfg;
+  c.ndim = nd;
+  c.nx = nx;
+  c.ny = ny;
+  c.nz = nz;
+  c.nb = g->nb;
+  c.h = g->h;
+  c.ns = a->ns;
+  c.nr = a->nr;
+  c.src.assign(a->src, a->src + (size_t)a->ns * nd);
+  c.rec.assign(a->rec, a->rec + (size_t)a->nr * nd);
+  c.f_peak = a->f_peak;
+  c.t0 = a->t0;
+  c.dt = a->dt;
+  c.nt = a->nt;
+  c.dtype = o->dtype;
+  c.snap = o->snap;
+  c.ckpt_every = o->ckpt_every;
+  c.sponge_R = o->sponge_R;
+  c.timing = o->timing ? 1 : 0;
+  size_t freeb = 0, total = 0;
+  hipError_t e = hipMemGetInfo(&freeb, &total);
+  if (e != hipSuccess) {
+    delete ctx;
+    return fail(MP_EDEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+  }
+  const size_t cap = (size_t)(0.9 * (double)freeb);
+  ctx->budget.limit = (o->budget_bytes == 0) ? cap : std::min(o->budget_bytes, cap);
+  ctx->eng = make_engine_2d(c, &ctx->budget);
+  if (!ctx->eng) {
+    delete ctx;
+    return MP_ENOMEM;
+  }
+  *out = ctx;
+  return MP_OK;
+}
+
+void mp_destroy(mp_ctx* ctx) {
+  if (!ctx) return;
+  symbol_release(ctx);
+  delete ctx->eng;
+  delete ctx;
+}
+
+int mp_set_background(mp_ctx* ctx, const void* c_dev, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!c_dev) return fail(MP_EINVAL, "null velocity");
+  rc = ctx->eng->set_background(c_dev, (hipStream_t)stream);
+  if (rc == MP_OK) ctx->has_bg = true;
+  return finish(ctx, rc);
+}
+
+int mp_footprint(const mp_ctx* ctx, int op, size_t* bytes) {
+  if (!ctx || !bytes) return fail(MP_EINVAL, "null argument");
+  if (op < MP_OP_F || op > MP_OP_HINV) return fail(MP_EINVAL, "unknown op");
+  return ctx->eng->footprint(op, bytes);
+}
+
+int mp_apply_F(mp_ctx* ctx, const void* dm, void* d, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!dm || !d) return fail(MP_EINVAL, "null buffer");
+  if (!ctx->has_bg) return fail(MP_ESTATE, "no background set");
+  return finish(ctx, ctx->eng->apply_F(dm, d, (hipStream_t)stream));
+}
+
+int mp_apply_Fadj(mp_ctx* ctx, const void* d, void* img, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!d || !img) return fail(MP_EINVAL, "null buffer");
+  if (!ctx->has_bg) return fail(MP_ESTATE, "no background set");
+  return finish(ctx, ctx->eng->apply_Fadj(d, img, (hipStream_t)stream));
+}
+
+int mp_apply_H(mp_ctx* ctx, const void* dm, void* out, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!dm || !out) return fail(MP_EINVAL, "null buffer");
+  if (!ctx->has_bg) return fail(MP_ESTATE, "no background set");
+  return finish(ctx, ctx->eng->apply_H(dm, out, (hipStream_t)stream));
+}
+
+int mp_release_cache(mp_ctx* ctx) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  return ctx->eng->release_cache();
+}
+
+int mp_last_stats(const mp_ctx* ctx, mp_stats* out) {
+  if (!ctx || !out) return fail(MP_EINVAL, "null argument");
+  const int rc = ctx->eng->collect_timing();
+  if (rc) return rc;
+  *out = ctx->eng->stats;
+  out->bytes_reserved = ctx->budget.used;
+  return MP_OK;
+}
+
+int mp_basis_create(const mp_basis_desc* d, mp_basis** out) {
+  if (!d || !out) return fail(MP_EINVAL, "null argument");
+  *out = nullptr;
+  if (d->ndim != 2 && d->ndim != 3) return fail(MP_EINVAL, "ndim must be 2 or 3");
+  if (d->na < 1 || d->nq < 1 || !d->degs || !d->qs) return fail(MP_EINVAL, "empty basis");
+  for (int i = 0; i < d->na * d->ndim; ++i)
+    if (d->degs[i] < 0 || d->degs[i] > 16) return fail(MP_EINVAL, "Legendre degrees must be in [0, 16]");
+  for (int i = 0; i < d->nq; ++i)
+    if (d->qs[i] < 0 || d->qs[i] > 8) return fail(MP_EINVAL, "powers of rho must be in [0, 8]");
+  if (d->na * d->nq > 64) return fail(MP_EUNSUPPORTED, "at most 64 basis terms");
+  mp_basis* b = new mp_basis();
+  b->b.ndim = d->ndim;
+  b->b.degs.assign(d->degs, d->degs + (size_t)d->na * d->ndim);
+  b->b.qs.assign(d->qs, d->qs + d->nq);
+  *out = b;
+  return MP_OK;
+}
+
+void mp_basis_destroy(mp_basis* b) { delete b; }
+
+int mp_probe_fit(mp_ctx* ctx, const mp_basis* basis, int T, const void* const* y, const void* const* x,
+                 double* c, double* relres, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!basis || !y || !x || !c || T < 1) return fail(MP_EINVAL, "bad probe_fit arguments");
+  if (basis->b.ndim != ctx->cfg.ndim) return fail(MP_EINVAL, "basis dimension differs from the grid");
+  for (int t = 0; t < T; ++t)
+    if (!y[t] || !x[t]) return fail(MP_EINVAL, "null trial buffer");
+  return finish(ctx, symbol_fit(ctx, basis->b, T, y, x, c, relres, (hipStream_t)stream));
+}
+
+int mp_apply_Hinv(mp_ctx* ctx, const mp_basis* basis, const double* c, const void* img, void* out,
+                  void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!basis || !c || !img || !out) return fail(MP_EINVAL, "bad apply_Hinv arguments");
+  if (basis->b.ndim != ctx->cfg.ndim) return fail(MP_EINVAL, "basis dimension differs from the grid");
+  for (int i = 0; i < basis->b.na() * basis->b.nq(); ++i)
+    if (!std::isfinite(c[i])) return fail(MP_ENUMERIC, "non-finite coefficient");
+  return finish(ctx, symbol_apply(ctx, basis->b, c, img, out, (hipStream_t)stream));
+}
+
+}  // extern "C"

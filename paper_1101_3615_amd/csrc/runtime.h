@@ -1,0 +1,103 @@
+// Host runtime: context, device memory accounting, error state.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "../../include/matprobe.h"
+
+namespace mp {
+
+void set_error(const std::string& msg);
+
+// Owning device allocation charged against a budget.
+class Budget;
+class DevBuf {
+ public:
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void* get() const { return p_; }
+  template <typename U>
+  U* as() const { return static_cast<U*>(p_); }
+  size_t bytes() const { return n_; }
+  // (Re)allocate to at least `bytes`; keeps the old block if large enough.
+  int ensure(size_t bytes, Budget* budget, const char* what);
+  void release();
+
+ private:
+  void* p_ = nullptr;
+  size_t n_ = 0;
+  Budget* b_ = nullptr;
+};
+
+class Budget {
+ public:
+  size_t limit = 0;
+  size_t used = 0;
+};
+
+struct Config {
+  int ndim;
+  int nx, ny, nz, nb;
+  double h;
+  int ns, nr;
+  std::vector<int> src;   // [ns][ndim]  (x, [y,] z)
+  std::vector<int> rec;   // [nr][ndim]
+  double f_peak, t0, dt;
+  int nt;
+  int dtype, snap, ckpt_every;
+  double sponge_R;
+  int timing;
+  long long prop_cells() const {
+    long long c = (long long)(nx + 2 * nb) * (nz + 2 * nb);
+    if (ndim == 3) c *= (ny + 2 * nb);
+    return c;
+  }
+  long long model_cells() const { return (long long)nx * ny * nz; }
+};
+
+// One precision/dimension specialisation of the operators.
+class Engine {
+ public:
+  virtual ~Engine() = default;
+  virtual int set_background(const void* c, hipStream_t s) = 0;
+  virtual int apply_F(const void* dm, void* d, hipStream_t s) = 0;
+  virtual int apply_Fadj(const void* d, void* img, hipStream_t s) = 0;
+  virtual int apply_H(const void* dm, void* out, hipStream_t s) = 0;
+  virtual int footprint(int op, size_t* bytes) const = 0;
+  virtual int release_cache() = 0;
+  virtual size_t reserved() const = 0;
+  // Wait for the timing events of the last call and fold them into stats.
+  virtual int collect_timing() = 0;
+  mp_stats stats{};
+};
+
+Engine* make_engine_2d(const Config& c, Budget* b);
+
+// probing basis
+struct Basis {
+  int ndim;
+  std::vector<int> degs;  // [na][ndim], axis order (x, [y,] z)
+  std::vector<int> qs;
+  int na() const { return (int)(degs.size() / ndim); }
+  int nq() const { return (int)qs.size(); }
+};
+
+}  // namespace mp
+
+struct mp_ctx {
+  mp::Config cfg;
+  mp::Budget budget;
+  mp::Engine* eng = nullptr;
+  bool poisoned = false;
+  bool has_bg = false;
+  void* symbol_ws = nullptr;   // probing workspace (owned by symbol.hip)
+};
+
+struct mp_basis {
+  mp::Basis b;
+};

@@ -1,0 +1,198 @@
+"""Python binding of the operators: argument marshalling only.
+
+Every step of F, F*, H, the probing fit and the fitted inverse runs in the HIP
+kernels of libmatprobe.so; torch provides device memory and the stream.
+Arrays use numpy axis order (z, [y,] x); positions are (x, [y,] z) model-grid
+indices like the C ABI.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DT = {"f32": (L.MP_F32, torch.float32), "f64": (L.MP_F64, torch.float64)}
+_SNAP = {"full": L.MP_SNAP_FULL, "ckpt_f32": L.MP_SNAP_CKPT_F32, "ckpt_bf16": L.MP_SNAP_CKPT_BF16}
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """One grid, acquisition and background; owns an mp_ctx."""
+
+    def __init__(self, *, ndim, nx, nz, ny=1, h, nb, src, rec, f_peak, t0, dt, nt,
+                 dtype="f32", snap="full", ckpt_every=0, budget_bytes=0, sponge_R=1e-3,
+                 timing=False, device="cuda:0"):
+        lib = L.lib()
+        self.ndim = int(ndim)
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.nt = int(nt)
+        self.device = torch.device(device)
+        self.dtype_code, self.torch_dtype = _DT[dtype]
+        self.src = np.ascontiguousarray(src, dtype=np.int32)
+        self.rec = np.ascontiguousarray(rec, dtype=np.int32)
+        self.ns = int(self.src.shape[0])
+        self.nr = int(self.rec.shape[0])
+        g = L.Grid(self.ndim, (ctypes.c_int * 3)(self.nx, self.ny, self.nz), float(h), int(nb))
+        a = L.Acq(self.ns, self.src.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), self.nr,
+                  self.rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), float(f_peak), float(t0),
+                  float(dt), self.nt)
+        o = L.Opts(self.dtype_code, _SNAP[snap], int(ckpt_every), int(budget_bytes), float(sponge_R),
+                   1 if timing else 0)
+        ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(lib.mp_create(ctypes.byref(g), ctypes.byref(a), ctypes.byref(o), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self._lib = lib
+
+    @classmethod
+    def from_spec(cls, w, **kw):
+        """Build from any object carrying the workload attributes (ndim, nx, ...)."""
+        args = dict(ndim=w.ndim, nx=w.nx, nz=w.nz, ny=w.ny, h=w.h, nb=w.nb, src=w.src, rec=w.rec,
+                    f_peak=w.f_peak, t0=w.wavelet_t0, dt=w.dt, nt=w.nt, dtype=w.dtype,
+                    snap=w.snap, ckpt_every=w.ckpt_every, sponge_R=w.sponge_R)
+        args.update(kw)
+        return cls(**args)
+
+    @property
+    def model_shape(self):
+        return (self.nz, self.nx) if self.ndim == 2 else (self.nz, self.ny, self.nx)
+
+    @property
+    def data_shape(self):
+        return (self.ns, self.nt, self.nr)
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self._lib.mp_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _model(self, t, name):
+        if not isinstance(t, torch.Tensor):
+            t = torch.as_tensor(np.asarray(t))
+        t = t.to(device=self.device, dtype=self.torch_dtype).contiguous()
+        if tuple(t.shape) != self.model_shape:
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {self.model_shape}")
+        return t
+
+    def set_background(self, c, stream=None):
+        c = self._model(c, "c")
+        self._c = c
+        L.check(self._lib.mp_set_background(self._ctx, _ptr(c), _stream(stream)))
+
+    def apply_F(self, dm, out=None, stream=None):
+        dm = self._model(dm, "dm")
+        d = out if out is not None else torch.empty(self.data_shape, dtype=self.torch_dtype,
+                                                    device=self.device)
+        L.check(self._lib.mp_apply_F(self._ctx, _ptr(dm), _ptr(d), _stream(stream)))
+        return d
+
+    def apply_Fadj(self, d, out=None, stream=None):
+        if not isinstance(d, torch.Tensor):
+            d = torch.as_tensor(np.asarray(d))
+        d = d.to(device=self.device, dtype=self.torch_dtype).contiguous()
+        if tuple(d.shape) != self.data_shape:
+            raise ValueError(f"d has shape {tuple(d.shape)}, expected {self.data_shape}")
+        img = out if out is not None else torch.empty(self.model_shape, dtype=self.torch_dtype,
+                                                      device=self.device)
+        L.check(self._lib.mp_apply_Fadj(self._ctx, _ptr(d), _ptr(img), _stream(stream)))
+        return img
+
+    def apply_H(self, dm, out=None, stream=None):
+        dm = self._model(dm, "dm")
+        o = out if out is not None else torch.empty(self.model_shape, dtype=self.torch_dtype,
+                                                    device=self.device)
+        L.check(self._lib.mp_apply_H(self._ctx, _ptr(dm), _ptr(o), _stream(stream)))
+        return o
+
+    def footprint(self, op="H"):
+        code = {"F": L.MP_OP_F, "Fadj": L.MP_OP_FADJ, "H": L.MP_OP_H, "fit": L.MP_OP_FIT,
+                "Hinv": L.MP_OP_HINV}[op]
+        b = ctypes.c_size_t()
+        L.check(self._lib.mp_footprint(self._ctx, code, ctypes.byref(b)))
+        return b.value
+
+    def release_cache(self):
+        L.check(self._lib.mp_release_cache(self._ctx))
+
+    def stats(self):
+        s = L.Stats()
+        L.check(self._lib.mp_last_stats(self._ctx, ctypes.byref(s)))
+        return dict(cell_steps=s.cell_steps, waves=s.waves,
+                    background_cached=bool(s.background_cached), bytes_reserved=s.bytes_reserved,
+                    ms_sweep={k: s.ms_sweep[i] for i, k in enumerate(L.SWEEP_KINDS)},
+                    launches_sweep={k: s.launches_sweep[i] for i, k in enumerate(L.SWEEP_KINDS)})
+
+
+class Basis:
+    """Probing basis: Legendre position factors (numpy axis order) x powers of rho."""
+
+    def __init__(self, legendre, qs, ndim):
+        lib = L.lib()
+        self.legendre = [tuple(int(v) for v in a) for a in legendre]
+        self.qs = [int(q) for q in qs]
+        self.ndim = int(ndim)
+        # C ABI takes degrees in axis order (x, [y,] z)
+        degs = np.ascontiguousarray([list(reversed(a)) for a in self.legendre], dtype=np.int32)
+        qs_arr = np.ascontiguousarray(self.qs, dtype=np.int32)
+        d = L.BasisDesc(self.ndim, len(self.legendre), degs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                        len(self.qs), qs_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+        h = ctypes.c_void_p()
+        L.check(lib.mp_basis_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    @property
+    def p(self):
+        return len(self.legendre) * len(self.qs)
+
+    def __del__(self):
+        try:
+            if self._h.value:
+                self._lib.mp_basis_destroy(self._h)
+        except Exception:
+            pass
+
+
+def probe_fit(problem, basis, ys, xs, stream=None):
+    """Least-squares symbol coefficients c (numpy float64) and the relative residual."""
+    ys = [problem._model(y, "y") for y in ys]
+    xs = [problem._model(x, "x") for x in xs]
+    T = len(ys)
+    yp = (ctypes.c_void_p * T)(*[y.data_ptr() for y in ys])
+    xp = (ctypes.c_void_p * T)(*[x.data_ptr() for x in xs])
+    c = np.zeros(basis.p, dtype=np.float64)
+    rel = ctypes.c_double()
+    rc = problem._lib.mp_probe_fit(problem._ctx, basis._h, T, yp, xp,
+                                   c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(rel),
+                                   _stream(stream))
+    if rc == L.MP_ENUMERIC:
+        L.check(rc)
+    L.check(rc)
+    return c, rel.value
+
+
+def apply_Hinv(problem, basis, c, img, out=None, stream=None):
+    img = problem._model(img, "img")
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    if c.shape != (basis.p,):
+        raise ValueError(f"c has shape {c.shape}, expected ({basis.p},)")
+    o = out if out is not None else torch.empty_like(img)
+    L.check(problem._lib.mp_apply_Hinv(problem._ctx, basis._h,
+                                       c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       _ptr(img), _ptr(o), _stream(stream)))
+    return o

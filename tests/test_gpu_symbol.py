@@ -1,0 +1,111 @@
+"""Parity of the probing fit and of the fitted-inverse application (HIP, via the C ABI)."""
+import numpy as np
+import pytest
+
+import fixtures as F
+from oracle import symbol as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1101_3615_amd as M
+    return M
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def _problem(M, w):
+    P = M.Problem.from_spec(w)
+    return P
+
+
+@pytest.mark.parametrize("dtype,shape", [("f64", (32, 64)), ("f32", (64, 128)), ("f64", (128, 16))])
+def test_apply_Hinv_matches_oracle(dtype, shape):
+    M = _gpu()
+    nz, nx = shape
+    w = F.tiny(n=8, dtype=dtype).with_(nx=nx, nz=nz)
+    P = _problem(M, w)
+    leg = [(0, 0), (1, 0), (2, 1), (0, 3)]
+    qs = (0, 1, 2, 3)
+    B = M.Basis(leg, qs, 2)
+    rng = np.random.default_rng(5)
+    c = rng.standard_normal(B.p)
+    img = F.normal_field(shape, 11)
+    got = M.apply_Hinv(P, B, c, torch.from_numpy(img)).cpu().numpy()
+    ref = S.apply_Hinv(c, img, w.h, leg, qs)
+    assert rel(got, ref) <= (1e-13 if dtype == "f64" else 1e-6)
+
+
+def test_single_multiplier_terms():
+    """B_(P0,q) alone: the FFT, the |k| table and the normalisation of each power."""
+    M = _gpu()
+    w = F.tiny(n=8, dtype="f64").with_(nx=64, nz=32)
+    P = _problem(M, w)
+    img = F.normal_field((32, 64), 12)
+    for q in range(4):
+        B = M.Basis([(0, 0)], (q,), 2)
+        got = M.apply_Hinv(P, B, np.array([1.0]), torch.from_numpy(img)).cpu().numpy()
+        ref = S.apply_basis(img, w.h, [(0, 0)], (q,))[0]
+        assert rel(got, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("ntrial", [1, 2])
+def test_probe_fit_exact_recovery(ntrial):
+    """y = sum_i c_i B_i x exactly -> the GPU fit returns c to 1e-10 (Sec. 1.3)."""
+    M = _gpu()
+    w = F.tiny(n=8, dtype="f64").with_(nx=128, nz=64)
+    P = _problem(M, w)
+    leg = [(a, 0) for a in range(5)]
+    qs = (0, 1, 2, 3)
+    B = M.Basis(leg, qs, 2)
+    rng = np.random.default_rng(9)
+    ctrue = rng.standard_normal(B.p)
+    xs = [F.normal_field((64, 128), 40 + t).astype(np.float64) for t in range(ntrial)]
+    ys = [S.apply_Hinv(ctrue, x, w.h, leg, qs) for x in xs]
+    c, relres = M.probe_fit(P, B, [torch.from_numpy(y) for y in ys], [torch.from_numpy(x) for x in xs])
+    assert np.max(np.abs(c - ctrue)) <= 1e-10 * np.max(np.abs(ctrue))
+    assert relres < 1e-10
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_probe_fit_matches_oracle_least_squares(dtype):
+    M = _gpu()
+    w = F.tiny(n=8, dtype=dtype).with_(nx=64, nz=64)
+    P = _problem(M, w)
+    leg = [(0, 0), (1, 0), (2, 0)]
+    qs = (0, 1, 2, 3)
+    B = M.Basis(leg, qs, 2)
+    xs = [F.normal_field((64, 64), 60 + t) for t in range(2)]
+    ys = [F.normal_field((64, 64), 70 + t) for t in range(2)]
+    c, relres = M.probe_fit(P, B, [torch.from_numpy(y) for y in ys], [torch.from_numpy(x) for x in xs])
+    cref, rref, _ = S.fit([y.astype(np.float64) for y in ys], [x.astype(np.float64) for x in xs], w.h, leg, qs)
+    assert rel(c, cref) <= 1e-10
+    assert abs(relres - rref) <= 1e-10 * rref
+
+
+def test_probe_fit_rank_deficient():
+    M = _gpu()
+    w = F.tiny(n=8, dtype="f64").with_(nx=32, nz=32)
+    P = _problem(M, w)
+    B = M.Basis([(0, 0), (0, 0)], (0,), 2)        # the same column twice
+    x = F.normal_field((32, 32), 80)
+    y = F.normal_field((32, 32), 81)
+    with pytest.raises(M.MatprobeError) as e:
+        M.probe_fit(P, B, [torch.from_numpy(y)], [torch.from_numpy(x)])
+    assert e.value.code == -5
+
+
+def test_non_power_of_two_rejected():
+    M = _gpu()
+    w = F.tiny(n=8, dtype="f64").with_(nx=48, nz=32)
+    P = _problem(M, w)
+    B = M.Basis([(0, 0)], (0,), 2)
+    with pytest.raises(M.MatprobeError) as e:
+        M.apply_Hinv(P, B, np.array([1.0]), torch.zeros(32, 48, dtype=torch.float64))
+    assert e.value.code == -6
