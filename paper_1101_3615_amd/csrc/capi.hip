@@ -124,8 +124,8 @@ int mp_create(const mp_grid* g, const mp_acq* a, const mp_opts* o, mp_ctx** out)
     if (!seen.insert(std::vector<int>(p, p + nd)).second)
       return fail(MP_EINVAL, "receivers must occupy distinct cells");
   }
-  if (nd == 3) return fail(MP_EUNSUPPORTED, "3D grids are not built yet");
-  if (o->snap != MP_SNAP_FULL) return fail(MP_EUNSUPPORTED, "checkpoint snapshot modes are not built yet");
+  if (o->snap == MP_SNAP_CKPT_BF16 && o->dtype != MP_F32)
+    return fail(MP_EUNSUPPORTED, "BF16 checkpoints are built for FP32 fields");
 
   mp_ctx* ctx = new mp_ctx();
   Config& c = ctx->cfg;
@@ -156,7 +156,7 @@ int mp_create(const mp_grid* g, const mp_acq* a, const mp_opts* o, mp_ctx** out)
   }
   const size_t cap = (size_t)(0.9 * (double)freeb);
   ctx->budget.limit = (o->budget_bytes == 0) ? cap : std::min(o->budget_bytes, cap);
-  ctx->eng = make_engine_2d(c, &ctx->budget);
+  ctx->eng = make_engine(c, &ctx->budget);
   if (!ctx->eng) {
     delete ctx;
     return MP_ENOMEM;

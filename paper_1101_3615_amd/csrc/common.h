@@ -16,6 +16,7 @@ namespace mp {
 // read of the first and last ghost rows.
 constexpr int XL = 4;
 constexpr int GZ = 4;
+constexpr int GY = 4;            // ghost rows in y (3D)
 constexpr int SLACK = 64;
 constexpr int LANES = 64;        // wavefront size on gfx950
 constexpr int CPL = 4;           // cells per lane along x
@@ -53,6 +54,63 @@ __device__ __forceinline__ double shl1(double v, double old) {
   int lo = dpp_shl1_i((int)(b & 0xffffffffll), (int)(o & 0xffffffffll));
   int hi = dpp_shl1_i((int)(b >> 32), (int)(o >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// DPP shifts inside each 16-lane row: row_shr:1 / row_shl:1 (lane 0 / 15 of the
+// row keeps `old`).
+__device__ __forceinline__ float rshr1(float v, float old) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x111, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float rshl1(float v, float old) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x101, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double rshr1(double v, double old) {
+  long long b = __double_as_longlong(v), o = __double_as_longlong(old);
+  int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(b & 0xffffffffll), 0x111, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), 0x111, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double rshl1(double v, double old) {
+  long long b = __double_as_longlong(v), o = __double_as_longlong(old);
+  int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(b & 0xffffffffll), 0x101, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), 0x101, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// FP32 -> BF16 with round-to-nearest-even on the bit pattern (finite inputs).
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  const unsigned int b = __float_as_uint(f);
+  return (unsigned short)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+template <typename T>
+__device__ __forceinline__ V4<T> ld4(const T* p) {
+  return *reinterpret_cast<const V4<T>*>(p);
+}
+template <typename T>
+__device__ __forceinline__ void st4(T* p, const V4<T>& v) {
+  *reinterpret_cast<V4<T>*>(p) = v;
+}
+template <typename T>
+__device__ __forceinline__ V4<T> zero4() {
+  V4<T> r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r.v[i] = T(0);
+  return r;
+}
+
+// Damping coefficients of the leapfrog at a cell: a = 1/(1 + eta dt/2), b = (1 - eta dt/2) a.
+template <typename T>
+__device__ __forceinline__ void damping(T eta, T hdt, T& a, T& b) {
+  if (eta == T(0)) {
+    a = T(1);
+    b = T(1);
+  } else {
+    const T e = eta * hdt;
+    a = T(1) / (T(1) + e);
+    b = (T(1) - e) * a;
+  }
 }
 
 // Map a workgroup index to a work item so that each of the 8 XCDs (which

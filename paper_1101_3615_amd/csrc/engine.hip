@@ -1,4 +1,4 @@
-// 2D operator engine: memory plan, shot waves, forward / reverse sweeps.
+// Operator engine (2D and 3D): memory plan, shot waves, forward / reverse sweeps.
 //
 // Per shot the sweeps keep four field slices (background u and Born / adjoint
 // field, two time levels each; the leapfrog writes level n+1 over level n-1),
@@ -43,67 +43,107 @@ namespace mp {
 static long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
 
 template <typename T>
-class Engine2D final : public Engine {
+class EngineT final : public Engine {
  public:
-  Engine2D(const Config& c, Budget* b) : cfg_(c), budget_(b) {
+  EngineT(const Config& c, Budget* b) : cfg_(c), budget_(b) {
+    L_.ndim = c.ndim;
     L_.nx = c.nx;
+    L_.ny = c.ny;
     L_.nz = c.nz;
     L_.nb = c.nb;
     L_.nxp = c.nx + 2 * c.nb;
+    L_.nyp = (c.ndim == 3) ? c.ny + 2 * c.nb : 1;
     L_.nzp = c.nz + 2 * c.nb;
-    L_.nstrips = (int)((L_.nxp + XL + STRIP - 1) / STRIP);
-    L_.pitch = L_.nstrips * STRIP;
-    L_.fstride = round_up(2LL * SLACK + (long long)(L_.nzp + 2 * GZ) * L_.pitch, 64);
+    if (c.ndim == 2) {
+      L_.nstrips = (int)((L_.nxp + XL + STRIP - 1) / STRIP);
+      L_.pitch = L_.nstrips * STRIP;
+      L_.nytiles = 1;
+      L_.ypitch = 1;
+    } else {
+      L_.nstrips = (int)((L_.nxp + XL + 63) / 64);
+      L_.pitch = L_.nstrips * 64;
+      L_.nytiles = (L_.nyp + 15) / 16;
+      L_.ypitch = L_.nytiles * 16 + 2 * GY;
+    }
+    L_.plane = (long long)L_.ypitch * L_.pitch;
+    L_.fstride = round_up(2LL * SLACK + (long long)(L_.nzp + 2 * GZ) * L_.plane, 64);
     L_.mpitch = (int)round_up(c.nx, 4);
-    L_.mstride = (long long)L_.mpitch * c.nz;
+    L_.mplane = (long long)L_.mpitch * c.ny;
+    L_.mstride = L_.mplane * c.nz;
+    cpitch_ = (int)round_up(L_.nxp, 4);
+    cstride_ = (long long)cpitch_ * L_.nyp * L_.nzp;
     const char* zc = getenv("MP_ZC");
     zc_target_ = zc ? std::max(4, atoi(zc)) : 0;
   }
 
   int init() {
     const Config& c = cfg_;
+    const int nd = c.ndim;
     // host tables
     std::vector<double> w = ricker(c.f_peak, c.t0, c.dt, c.nt);
     std::vector<T> wt(c.nt);
-    for (int n = 0; n < c.nt; ++n) wt[n] = (T)(w[n] / (c.h * c.h));
-    std::vector<int> sx(c.ns), sz(c.ns);
+    const double hd = std::pow(c.h, nd);
+    for (int n = 0; n < c.nt; ++n) wt[n] = (T)(w[n] / hd);
+    std::vector<int> sx(c.ns), sy(c.ns, 0), sz(c.ns);
     for (int s = 0; s < c.ns; ++s) {
-      sx[s] = c.src[2 * s] + c.nb;
-      sz[s] = c.src[2 * s + 1] + c.nb;
+      sx[s] = c.src[(size_t)nd * s] + c.nb;
+      if (nd == 3) sy[s] = c.src[(size_t)nd * s + 1] + c.nb;
+      sz[s] = c.src[(size_t)nd * s + nd - 1] + c.nb;
     }
-    std::vector<int> recrow(L_.nzp, 0);
-    std::vector<int> recmap((size_t)L_.fstride, -1);
-    const long long o0 = SLACK + (long long)GZ * L_.pitch + XL;
+    // receiver maps: one [nyp][cpitch] map per z plane holding receivers
+    std::vector<int> recplane(L_.nzp, -1);
+    int nmaps = 0;
     for (int r = 0; r < c.nr; ++r) {
-      const int x = c.rec[2 * r] + c.nb, z = c.rec[2 * r + 1] + c.nb;
-      recrow[z] = 1;
-      recmap[o0 + (long long)z * L_.pitch + x] = r;
+      const int z = c.rec[(size_t)nd * r + nd - 1] + c.nb;
+      if (recplane[z] < 0) recplane[z] = nmaps++;
+    }
+    const long long msz = (long long)L_.nyp * cpitch_;
+    std::vector<int> recmap((size_t)std::max(1, nmaps) * msz, -1);
+    for (int r = 0; r < c.nr; ++r) {
+      const int x = c.rec[(size_t)nd * r] + c.nb;
+      const int y = (nd == 3) ? c.rec[(size_t)nd * r + 1] + c.nb : 0;
+      const int z = c.rec[(size_t)nd * r + nd - 1] + c.nb;
+      recmap[(size_t)recplane[z] * msz + (size_t)y * cpitch_ + x] = r;
     }
     int rc;
     if ((rc = wav_.ensure(sizeof(T) * c.nt, budget_, "wavelet"))) return rc;
     if ((rc = srcx_.ensure(sizeof(int) * c.ns, budget_, "sources"))) return rc;
+    if ((rc = srcy_.ensure(sizeof(int) * c.ns, budget_, "sources"))) return rc;
     if ((rc = srcz_.ensure(sizeof(int) * c.ns, budget_, "sources"))) return rc;
-    if ((rc = recrow_.ensure(sizeof(int) * L_.nzp, budget_, "receivers"))) return rc;
-    if ((rc = recmap_.ensure(sizeof(int) * L_.fstride, budget_, "receivers"))) return rc;
+    if ((rc = recplane_.ensure(sizeof(int) * L_.nzp, budget_, "receivers"))) return rc;
+    if ((rc = recmap_.ensure(sizeof(int) * recmap.size(), budget_, "receivers"))) return rc;
     if ((rc = kappa_.ensure(sizeof(T) * L_.fstride, budget_, "kappa"))) return rc;
     if ((rc = dmbar_.ensure(sizeof(T) * L_.fstride, budget_, "dm"))) return rc;
     if ((rc = etax_.ensure(sizeof(T) * L_.nxp, budget_, "sponge"))) return rc;
+    if ((rc = etay_.ensure(sizeof(T) * L_.nyp, budget_, "sponge"))) return rc;
     if ((rc = etaz_.ensure(sizeof(T) * L_.nzp, budget_, "sponge"))) return rc;
     if ((rc = small_.ensure(64, budget_, "scratch"))) return rc;
     MP_HIP(hipMemcpy(wav_.get(), wt.data(), sizeof(T) * c.nt, hipMemcpyHostToDevice));
     MP_HIP(hipMemcpy(srcx_.get(), sx.data(), sizeof(int) * c.ns, hipMemcpyHostToDevice));
+    MP_HIP(hipMemcpy(srcy_.get(), sy.data(), sizeof(int) * c.ns, hipMemcpyHostToDevice));
     MP_HIP(hipMemcpy(srcz_.get(), sz.data(), sizeof(int) * c.ns, hipMemcpyHostToDevice));
-    MP_HIP(hipMemcpy(recrow_.get(), recrow.data(), sizeof(int) * L_.nzp, hipMemcpyHostToDevice));
-    MP_HIP(hipMemcpy(recmap_.get(), recmap.data(), sizeof(int) * L_.fstride, hipMemcpyHostToDevice));
+    MP_HIP(hipMemcpy(recplane_.get(), recplane.data(), sizeof(int) * L_.nzp, hipMemcpyHostToDevice));
+    MP_HIP(hipMemcpy(recmap_.get(), recmap.data(), sizeof(int) * recmap.size(), hipMemcpyHostToDevice));
     MP_HIP(hipMemset(kappa_.get(), 0, sizeof(T) * L_.fstride));
     MP_HIP(hipMemset(dmbar_.get(), 0, sizeof(T) * L_.fstride));
+    MP_HIP(hipMemset(etay_.get(), 0, sizeof(T) * L_.nyp));
     MP_HIP(hipDeviceSynchronize());
     return MP_OK;
   }
 
   // ---- memory plan ----
+  bool ckpt_mode() const { return cfg_.snap != MP_SNAP_FULL; }
+  int ck_kind() const {
+    return cfg_.snap == MP_SNAP_CKPT_BF16 ? CK_BF16 : cfg_.snap == MP_SNAP_CKPT_F32 ? CK_F32 : CK_NONE;
+  }
+  int nck() const { return ckpt_mode() ? (cfg_.nt + cfg_.ckpt_every - 1) / cfg_.ckpt_every : 0; }
+  size_t ck_elem() const { return cfg_.snap == MP_SNAP_CKPT_BF16 ? 2 : sizeof(T); }
+  // g slots per shot: every step (full history) or one checkpoint segment
+  long long g_slots() const { return ckpt_mode() ? std::min(cfg_.ckpt_every, cfg_.nt) : cfg_.nt; }
   size_t per_shot_bytes() const {
-    return sizeof(T) * (size_t)(4 * L_.fstride + (long long)cfg_.nt * L_.mstride);
+    size_t b = sizeof(T) * (size_t)(4 * L_.fstride + g_slots() * L_.mstride);
+    if (ckpt_mode()) b += (size_t)nck() * 2 * (ck_elem() * (size_t)cstride_ + sizeof(float));
+    return b;
   }
   size_t fixed_bytes() const {
     return sizeof(T) * (size_t)cfg_.ns * cfg_.nt * cfg_.nr      // data (apply_H)
@@ -111,42 +151,50 @@ class Engine2D final : public Engine {
   }
   int footprint(int op, size_t* bytes) const override {
     (void)op;
-    *bytes = budget_->used - reserved_sweep() + fixed_bytes() + per_shot_bytes() * (size_t)wave_size_for(budget_->limit);
+    const int w = std::max(1, std::min(cfg_.ns, max_wave(SIZE_MAX)));
+    *bytes = budget_->used - reserved_sweep() + fixed_bytes() + per_shot_bytes() * (size_t)w;
     return MP_OK;
   }
   size_t reserved_sweep() const {
-    return fields_.bytes() + hist_.bytes() + data_.bytes() + img_.bytes();
+    return fields_.bytes() + hist_.bytes() + data_.bytes() + img_.bytes() + ck_.bytes() + cks_.bytes();
   }
   size_t reserved() const override { return budget_->used; }
 
-  int wave_size_for(size_t limit) const {
+  int max_wave(size_t limit) const {
     const size_t base = budget_->used - reserved_sweep() + fixed_bytes();
     if (limit <= base) return 0;
     const size_t w = (limit - base) / per_shot_bytes();
     return (int)std::min<size_t>(w, (size_t)cfg_.ns);
   }
 
+  // Wave size: the fewest waves that fit, shots split evenly between them.
   int plan(int* W) {
-    const int w = wave_size_for(budget_->limit);
-    if (w < 1) {
+    const int wmax = max_wave(budget_->limit);
+    if (wmax < 1) {
       set_error("budget too small for one shot of the sweep");
       return MP_ENOMEM;
     }
+    const int nw = (cfg_.ns + wmax - 1) / wmax;
+    const int w = (cfg_.ns + nw - 1) / nw;
     int rc;
     if ((rc = data_.ensure(sizeof(T) * (size_t)cfg_.ns * cfg_.nt * cfg_.nr, budget_, "data"))) return rc;
     if ((rc = img_.ensure(sizeof(double) * (size_t)cfg_.ns * L_.mstride, budget_, "images"))) return rc;
     if ((rc = fields_.ensure(sizeof(T) * 4 * (size_t)w * L_.fstride, budget_, "fields"))) return rc;
-    if ((rc = hist_.ensure(sizeof(T) * (size_t)w * cfg_.nt * L_.mstride, budget_, "history"))) return rc;
+    if ((rc = hist_.ensure(sizeof(T) * (size_t)w * g_slots() * L_.mstride, budget_, "g store"))) return rc;
+    if (ckpt_mode()) {
+      if ((rc = ck_.ensure(ck_elem() * (size_t)w * nck() * 2 * cstride_, budget_, "checkpoints"))) return rc;
+      if ((rc = cks_.ensure(sizeof(float) * (size_t)w * nck() * 2, budget_, "checkpoint scales"))) return rc;
+    }
     *W = w;
     whole_ = (w >= cfg_.ns);
     return MP_OK;
   }
 
-  Step2D<T> params(int s0, int nsh, int W) {
-    Step2D<T> p;
+  Step<T> params(int s0, int nsh, int W) {
+    Step<T> p;
     p.L = L_;
     const double ih2 = 1.0 / (cfg_.h * cfg_.h);
-    p.c0x2 = (T)(2.0 * FD8[0] * ih2);
+    p.c0x = (T)(cfg_.ndim * FD8[0] * ih2);
     p.c1 = (T)(FD8[1] * ih2);
     p.c2 = (T)(FD8[2] * ih2);
     p.c3 = (T)(FD8[3] * ih2);
@@ -155,27 +203,39 @@ class Engine2D final : public Engine {
     p.inv_dt2 = (T)(1.0 / (cfg_.dt * cfg_.dt));
     p.kappa = kappa_.as<T>();
     p.etax = etax_.as<T>();
+    p.etay = etay_.as<T>();
     p.etaz = etaz_.as<T>();
     p.dmbar = dmbar_.as<T>();
     p.srcx = srcx_.as<int>();
+    p.srcy = srcy_.as<int>();
     p.srcz = srcz_.as<int>();
     p.wav = wav_.as<T>();
-    p.recrow = recrow_.as<int>();
+    p.recplane = recplane_.as<int>();
     p.recmap = recmap_.as<int>();
     p.nr = cfg_.nr;
     p.nt = cfg_.nt;
     p.shot0 = s0;
-    // z chunking: enough waves to fill the chip
     int zc = zc_target_;
-    if (zc <= 0) {
-      const long long waves_per_chunkrow = (long long)nsh * L_.nstrips;
-      zc = (int)std::max<long long>(8, std::min<long long>(64, (long long)L_.nzp * waves_per_chunkrow / 4096));
+    if (cfg_.ndim == 2) {
+      // one wavefront per z chunk of a 256-cell strip, four chunks per workgroup
+      if (zc <= 0) {
+        const long long per_row = (long long)nsh * L_.nstrips;
+        zc = (int)std::max<long long>(8, std::min<long long>(64, (long long)L_.nzp * per_row / 4096));
+      }
+      const int ngroups = std::max(1, (int)((L_.nzp + 4LL * zc - 1) / (4LL * zc)));
+      p.ngroups = ngroups;
+      p.zc = (L_.nzp + 4 * ngroups - 1) / (4 * ngroups);
+      p.nchunks = (L_.nzp + p.zc - 1) / p.zc;
+      p.nwg = nsh * L_.nstrips * ngroups;
+    } else {
+      // one workgroup per 64 x 16 tile and z chunk
+      const long long tiles = (long long)nsh * L_.nstrips * L_.nytiles;
+      if (zc <= 0) zc = (int)std::max<long long>(8, std::min<long long>(64, (long long)L_.nzp * tiles / 2048));
+      p.nchunks = (L_.nzp + zc - 1) / zc;
+      p.zc = (L_.nzp + p.nchunks - 1) / p.nchunks;
+      p.ngroups = 1;
+      p.nwg = (int)(tiles * p.nchunks);
     }
-    const int ngroups = std::max(1, (int)((L_.nzp + 4LL * zc - 1) / (4LL * zc)));
-    p.ngroups = ngroups;
-    p.zc = (L_.nzp + 4 * ngroups - 1) / (4 * ngroups);
-    p.nchunks = (L_.nzp + p.zc - 1) / p.zc;
-    p.nwg = nsh * L_.nstrips * ngroups;
     T* f = fields_.as<T>();
     const long long fs = (long long)W * L_.fstride;
     p.u_cur = f;
@@ -183,10 +243,20 @@ class Engine2D final : public Engine {
     p.du_cur = f + 2 * fs;
     p.du_prev = f + 3 * fs;
     p.hist = hist_.as<T>();
-    p.hstride = (long long)cfg_.nt * L_.mstride;
     p.data = data_.as<T>();
     p.img = img_.as<double>();
+    p.hstride = g_slots() * L_.mstride;
+    p.ck = ck_.get();
+    p.ck_scale = cks_.as<float>();
+    p.cstride = cstride_;
+    p.cpitch = cpitch_;
+    p.nck = nck();
     return p;
+  }
+
+  void step(int mode, const Step<T>& p, int n, int hslot, int ck, int cs, int cm) {
+    if (cfg_.ndim == 2) step2d(mode, p, n, hslot, ck, cs, cm, stream_);
+    else step3d(mode, p, n, hslot, ck, cs, cm, stream_);
   }
 
   // ---- background ----
@@ -206,9 +276,9 @@ class Engine2D final : public Engine {
     std::memcpy(&cmaxf, &h[0], 4);
     const double cmax = cmaxf;
     const double courant = cmax * cfg_.dt / cfg_.h;
-    if (courant > cfl_limit(2)) {
+    if (courant > cfl_limit(cfg_.ndim)) {
       set_error("CFL violated: c_max dt / h = " + std::to_string(courant) + " > " +
-                std::to_string(cfl_limit(2)));
+                std::to_string(cfl_limit(cfg_.ndim)));
       return MP_EINVAL;
     }
     std::vector<double> ex = sponge_profile(cfg_.nx, cfg_.nb, cmax, cfg_.h, cfg_.sponge_R);
@@ -216,24 +286,30 @@ class Engine2D final : public Engine {
     std::vector<T> ext(ex.begin(), ex.end()), ezt(ez.begin(), ez.end());
     MP_HIP(hipMemcpyAsync(etax_.get(), ext.data(), sizeof(T) * ext.size(), hipMemcpyHostToDevice, s));
     MP_HIP(hipMemcpyAsync(etaz_.get(), ezt.data(), sizeof(T) * ezt.size(), hipMemcpyHostToDevice, s));
+    std::vector<T> eyt(L_.nyp, T(0));
+    if (cfg_.ndim == 3) {
+      std::vector<double> ey = sponge_profile(cfg_.ny, cfg_.nb, cmax, cfg_.h, cfg_.sponge_R);
+      for (int i = 0; i < L_.nyp; ++i) eyt[i] = (T)ey[i];
+    }
+    MP_HIP(hipMemcpyAsync(etay_.get(), eyt.data(), sizeof(T) * eyt.size(), hipMemcpyHostToDevice, s));
     Pad pd = pad();
     kappa(kappa_.as<T>(), c, pd, cfg_.dt, s);
     MP_CHECK_LAUNCH();
-    MP_HIP(hipStreamSynchronize(s));
+    MP_HIP(hipStreamSynchronize(s));   // host tables above must outlive the copies
     cached_ = false;
     return MP_OK;
   }
 
   Pad pad() const {
     Pad pd;
-    pd.ndim = 2;
+    pd.ndim = cfg_.ndim;
     pd.nx = cfg_.nx;
-    pd.ny = 1;
+    pd.ny = cfg_.ny;
     pd.nz = cfg_.nz;
     pd.nb = cfg_.nb;
-    pd.row = 0;
-    pd.plane = L_.pitch;
-    pd.origin = SLACK + (long long)GZ * L_.pitch + XL;
+    pd.row = (cfg_.ndim == 3) ? L_.pitch : 0;
+    pd.plane = L_.plane;
+    pd.origin = SLACK + (long long)GZ * L_.plane + (cfg_.ndim == 3 ? (long long)GY * L_.pitch : 0) + XL;
     return pd;
   }
 
@@ -291,27 +367,38 @@ class Engine2D final : public Engine {
     return MP_OK;
   }
 
-  ~Engine2D() override {
+  ~EngineT() override {
     for (auto& sp : spans_) {
       (void)hipEventDestroy(sp.a);
       (void)hipEventDestroy(sp.b);
     }
   }
 
-  // forward sweep of shots [s0, s0+nsh): mode 0 fused, 1 Born from stored g, 2 background only
+  // forward sweep of shots [s0, s0+nsh): mode 0 fused, 1 Born from stored g, 2 background only.
+  // In the checkpoint modes the background levels are stored every ckpt_every steps
+  // instead of g.
   int forward(int mode, int s0, int nsh, int W, T* data) {
     int rc;
     if ((rc = zero_fields(W, true))) return rc;
-    Step2D<T> p = params(s0, nsh, W);
+    Step<T> p = params(s0, nsh, W);
     p.data = data;
+    const int ck = ck_kind();
+    if (ck == CK_BF16 && mode != 1) {
+      fill(cks_.as<float>(), (long long)nsh * nck() * 2, 0.0f, stream_);
+      MP_CHECK_LAUNCH();
+    }
     Span* sp;
     if ((rc = span_begin(mode == 0 ? MP_SWEEP_FUSED : mode == 1 ? MP_SWEEP_BORN : MP_SWEEP_BACKGROUND,
                          cfg_.nt, &sp)))
       return rc;
+    const int k = std::max(1, cfg_.ckpt_every);
     for (int n = 0; n < cfg_.nt; ++n) {
-      if (mode == 0) step2d_fused(p, n, n, stream_);
-      else if (mode == 1) step2d_born(p, n, n, stream_);
-      else step2d_bg(p, n, n, stream_);
+      const int cs = (ck != CK_NONE && n % k == 0) ? n / k : -1;
+      const int cm = (ck == CK_BF16 && (n + 1) % k == 0 && (n + 1) / k < nck()) ? (n + 1) / k : -1;
+      const int hs = (ck == CK_NONE) ? n : 0;    // g is not stored while checkpointing
+      if (mode == 0) step(M_FUSED, p, n, hs, ck, cs, cm);
+      else if (mode == 1) step(M_BORN, p, n, n, CK_NONE, -1, -1);
+      else step(M_BG, p, n, hs, ck, cs, cm);
       std::swap(p.u_cur, p.u_prev);
       std::swap(p.du_cur, p.du_prev);
     }
@@ -323,16 +410,45 @@ class Engine2D final : public Engine {
     int rc;
     if ((rc = zero_fields(W, false))) return rc;
     fill(img_.as<double>() + (long long)s0 * L_.mstride, (long long)nsh * L_.mstride, 0.0, stream_);
-    Step2D<T> p = params(s0, nsh, W);
+    Step<T> p = params(s0, nsh, W);
     p.data = const_cast<T*>(data);
     Span* sp;
-    if ((rc = span_begin(MP_SWEEP_ADJOINT, cfg_.nt, &sp))) return rc;
-    for (int k = cfg_.nt; k >= 1; --k) {
-      step2d_adj(p, k, k - 1, stream_);
-      std::swap(p.du_cur, p.du_prev);
+    if (!ckpt_mode()) {
+      if ((rc = span_begin(MP_SWEEP_ADJOINT, cfg_.nt, &sp))) return rc;
+      for (int k = cfg_.nt; k >= 1; --k) {
+        step(M_ADJ, p, k, k - 1, CK_NONE, -1, -1);
+        std::swap(p.du_cur, p.du_prev);
+      }
+      MP_CHECK_LAUNCH();
+      return span_end(sp);
+    }
+    // checkpoint modes: per segment (last first) recompute g from the checkpoint,
+    // then run the adjoint down through the segment
+    const int kk = cfg_.ckpt_every;
+    const int ck = ck_kind();
+    for (int j = nck() - 1; j >= 0; --j) {
+      const int n0 = j * kk;
+      const int len = std::min(kk, cfg_.nt - n0);
+      if ((rc = span_begin(MP_SWEEP_BACKGROUND, len, &sp))) return rc;
+      expand(p, nsh, ck, j, stream_);
+      T* uc = p.u_cur;
+      T* up = p.u_prev;
+      for (int n = n0; n < n0 + len; ++n) {
+        step(M_BG, p, n, n - n0, CK_NONE, -1, -1);
+        std::swap(p.u_cur, p.u_prev);
+      }
+      p.u_cur = uc;
+      p.u_prev = up;
+      if ((rc = span_end(sp))) return rc;
+      if ((rc = span_begin(MP_SWEEP_ADJOINT, len, &sp))) return rc;
+      for (int k = n0 + len; k >= n0 + 1; --k) {
+        step(M_ADJ, p, k, k - 1 - n0, CK_NONE, -1, -1);
+        std::swap(p.du_cur, p.du_prev);
+      }
+      if ((rc = span_end(sp))) return rc;
     }
     MP_CHECK_LAUNCH();
-    return span_end(sp);
+    return MP_OK;
   }
 
   void finish_stats(int waves, bool used_cache) {
@@ -348,7 +464,8 @@ class Engine2D final : public Engine {
     if ((rc = plan(&W))) return rc;
     extend(dmbar_.as<T>(), static_cast<const T*>(dm), pad(), s);
     MP_CHECK_LAUNCH();
-    const bool use_cache = cached_ && whole_;
+    // with checkpoints the Born field still needs g at every step: always fused
+    const bool use_cache = cached_ && whole_ && !ckpt_mode();
     int waves = 0;
     for (int s0 = 0; s0 < cfg_.ns; s0 += W, ++waves) {
       const int nsh = std::min(W, cfg_.ns - s0);
@@ -372,7 +489,7 @@ class Engine2D final : public Engine {
       if ((rc = adjoint(s0, nsh, W, static_cast<const T*>(d)))) return rc;
     }
     cached_ = whole_;
-    stack(static_cast<T*>(img), img_.as<double>(), cfg_.ns, L_.mstride, cfg_.nx, 1, cfg_.nz, L_.mpitch, 1, s);
+    stack(static_cast<T*>(img), img_.as<double>(), cfg_.ns, L_.mstride, cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
     MP_CHECK_LAUNCH();
     finish_stats(waves, use_cache);
     return MP_OK;
@@ -384,7 +501,7 @@ class Engine2D final : public Engine {
     if ((rc = plan(&W))) return rc;
     extend(dmbar_.as<T>(), static_cast<const T*>(dm), pad(), s);
     MP_CHECK_LAUNCH();
-    const bool use_cache = cached_ && whole_;
+    const bool use_cache = cached_ && whole_ && !ckpt_mode();
     int waves = 0;
     T* data = data_.as<T>();
     for (int s0 = 0; s0 < cfg_.ns; s0 += W, ++waves) {
@@ -393,7 +510,7 @@ class Engine2D final : public Engine {
       if ((rc = adjoint(s0, nsh, W, data))) return rc;
     }
     cached_ = whole_;
-    stack(static_cast<T*>(out), img_.as<double>(), cfg_.ns, L_.mstride, cfg_.nx, 1, cfg_.nz, L_.mpitch, 1, s);
+    stack(static_cast<T*>(out), img_.as<double>(), cfg_.ns, L_.mstride, cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
     MP_CHECK_LAUNCH();
     finish_stats(waves, use_cache);
     return MP_OK;
@@ -411,22 +528,24 @@ class Engine2D final : public Engine {
  private:
   Config cfg_;
   Budget* budget_;
-  Layout2D L_;
+  Layout L_;
   int zc_target_ = 0;
+  int cpitch_ = 0;
+  long long cstride_ = 0;
   bool cached_ = false;
   bool whole_ = false;
   hipStream_t stream_ = nullptr;
-  DevBuf wav_, srcx_, srcz_, recrow_, recmap_, kappa_, dmbar_, etax_, etaz_, small_;
-  DevBuf fields_, hist_, data_, img_;
+  DevBuf wav_, srcx_, srcy_, srcz_, recplane_, recmap_, kappa_, dmbar_, etax_, etay_, etaz_, small_;
+  DevBuf fields_, hist_, data_, img_, ck_, cks_;
 };
 
-Engine* make_engine_2d(const Config& c, Budget* b) {
+Engine* make_engine(const Config& c, Budget* b) {
   if (c.dtype == MP_F32) {
-    auto* e = new Engine2D<float>(c, b);
+    auto* e = new EngineT<float>(c, b);
     if (e->init() != MP_OK) { delete e; return nullptr; }
     return e;
   }
-  auto* e = new Engine2D<double>(c, b);
+  auto* e = new EngineT<double>(c, b);
   if (e->init() != MP_OK) { delete e; return nullptr; }
   return e;
 }

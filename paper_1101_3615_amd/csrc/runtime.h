@@ -76,7 +76,7 @@ class Engine {
   mp_stats stats{};
 };
 
-Engine* make_engine_2d(const Config& c, Budget* b);
+Engine* make_engine(const Config& c, Budget* b);
 
 // probing basis
 struct Basis {

@@ -245,11 +245,12 @@ __global__ __launch_bounds__(256) void k_gram(const double* A, long long lda, lo
       }
     }
   }
-  // D[row = 4 (lane/16) + v][col = lane % 16] of tile (ti, tj): sum_r A[ti*16+row][r] A[tj*16+col][r]
+  // f64 16x16x4 accumulator layout (checked on gfx950): element v of lane l holds
+  // D[row = l/16 + 4 v][col = l % 16] of tile (ti, tj) = sum_r A[ti*16+row][r] A[tj*16+col][r]
   double* out = part + (long long)blockIdx.x * GCOL * GCOL;
   for (int k = 0; k < mine; ++k) {
     for (int v = 0; v < 4; ++v) {
-      const int i = pi[k] * GT + 4 * (lane >> 4) + v;
+      const int i = pi[k] * GT + (lane >> 4) + 4 * v;
       const int j = pj[k] * GT + (lane & 15);
       out[i * GCOL + j] = acc[k][v];
     }

@@ -4,31 +4,41 @@
 
 namespace mp {
 
-struct Layout2D {
-  int nxp, nzp;        // propagation grid
-  int pitch;           // field row pitch in elements (nstrips * 256)
+// Propagation-grid field layout (one slice per shot):
+//   cell (x, y, z) at  SLACK + (z + GZ) * plane + (y + gy) * pitch + (x + XL)
+// with gy = GY in 3D and 0 in 2D (nyp = 1, ypitch = 1, plane = pitch).
+struct Layout {
+  int ndim;
+  int nxp, nyp, nzp;   // propagation grid
+  int pitch;           // x-row pitch in elements
+  int ypitch;          // x rows per z plane, ghost rows included
+  long long plane;     // elements per z plane (ypitch * pitch)
   long long fstride;   // elements per field slice of one shot
-  int nx, nz, nb;      // model grid and layer width
-  int mpitch;          // model-grid row pitch (multiple of 4)
-  long long mstride;   // model-grid elements per slice (mpitch * nz)
-  int nstrips;         // 256-cell strips per row
+  int nx, ny, nz, nb;  // model grid and layer width
+  int mpitch;          // model-grid x pitch (multiple of 4)
+  long long mplane;    // model elements per z plane (mpitch * ny)
+  long long mstride;   // model elements per slice (mplane * nz)
+  int nstrips;         // 2D: 256-cell strips per row; 3D: 64-cell x tiles
+  int nytiles;         // 3D: 16-row y tiles (1 in 2D)
 };
 
 template <typename T>
-struct Step2D {
-  Layout2D L;
-  T c0x2, c1, c2, c3, c4;   // 8th-order weights / h^2 (centre weight doubled for 2 axes)
+struct Step {
+  Layout L;
+  T c0x, c1, c2, c3, c4;     // 8th-order weights / h^2; c0x = ndim * w0 / h^2
   T hdt;                     // dt / 2
   T inv_dt2;                 // 1 / dt^2
   const T* kappa;            // field layout, shared by all shots
   const T* etax;             // [nxp]
+  const T* etay;             // [nyp]
   const T* etaz;             // [nzp]
   const T* dmbar;            // field layout: zero-extended model perturbation
   const int* srcx;           // [ns] propagation-grid source cell
+  const int* srcy;
   const int* srcz;
-  const T* wav;              // [nt] wavelet / h^2
-  const int* recrow;         // [nzp] 1 if the row holds a receiver
-  const int* recmap;         // field layout, receiver index or -1
+  const T* wav;              // [nt] wavelet / h^ndim
+  const int* recplane;       // [nzp] receiver map of the plane, or -1
+  const int* recmap;         // [maps][nyp][cpitch]: receiver index or -1
   int nr, nt;
   int shot0;                 // global index of local shot 0 of this wave
   int zc, nchunks, ngroups, nwg;
@@ -40,15 +50,31 @@ struct Step2D {
   long long hstride;         // elements per local shot in hist
   T* data;                   // [ns][nt][nr] (global shot index)
   double* img;               // [ns][model] FP64 per-shot images
+  // background checkpoints (checkpoint snapshot modes); compact layout
+  // [z][y][cpitch] per level
+  void* ck;                  // [local shot][nck][2][cstride]: FP32 (u^n, u^{n-1}) or BF16 (u^n, u^n - u^{n-1})
+  float* ck_scale;           // [local shot][nck][2] max-abs scale of each BF16 level
+  long long cstride;         // elements per checkpoint level (nzp * nyp * cpitch)
+  int cpitch;                // compact row pitch (multiple of 4)
+  int nck;                   // checkpoints per shot
 };
 
-void step2d_fused(const Step2D<float>& p, int n, int hslot, hipStream_t s);
-void step2d_fused(const Step2D<double>& p, int n, int hslot, hipStream_t s);
-void step2d_born(const Step2D<float>& p, int n, int hslot, hipStream_t s);
-void step2d_born(const Step2D<double>& p, int n, int hslot, hipStream_t s);
-void step2d_bg(const Step2D<float>& p, int n, int hslot, hipStream_t s);
-void step2d_bg(const Step2D<double>& p, int n, int hslot, hipStream_t s);
-void step2d_adj(const Step2D<float>& p, int k, int hslot, hipStream_t s);
-void step2d_adj(const Step2D<double>& p, int k, int hslot, hipStream_t s);
+// Checkpoint encodings of the background sweep.
+enum { CK_NONE = 0, CK_F32 = 1, CK_BF16 = 2 };
+// Sweep kernels.
+enum { M_FUSED = 0, M_BORN = 1, M_BG = 2, M_ADJ = 3 };
+
+// One time step of every shot of a wave.  mode: M_*; n: step (adjoint: k);
+// hslot: g slot written (background modes) or read (Born, adjoint);
+// ck: CK_* encoding; ck_store: checkpoint written from (u^n, u^{n-1}) at this
+// step or -1; ck_max: checkpoint whose BF16 scales accumulate max |u^{n+1}| and
+// max |u^{n+1} - u^n| at this step or -1.
+void step2d(int mode, const Step<float>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
+void step2d(int mode, const Step<double>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
+void step3d(int mode, const Step<float>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
+void step3d(int mode, const Step<double>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
+// u_cur <- u^{jk}, u_prev <- u^{jk-1} from checkpoint j for the wave's shots
+void expand(const Step<float>& p, int nshots, int ck, int j, hipStream_t s);
+void expand(const Step<double>& p, int nshots, int ck, int j, hipStream_t s);
 
 }  // namespace mp

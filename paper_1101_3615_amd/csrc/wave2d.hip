@@ -17,39 +17,8 @@
 
 namespace mp {
 
-template <typename T>
-__device__ __forceinline__ V4<T> ld4(const T* p) {
-  return *reinterpret_cast<const V4<T>*>(p);
-}
-template <typename T>
-__device__ __forceinline__ void st4(T* p, const V4<T>& v) {
-  *reinterpret_cast<V4<T>*>(p) = v;
-}
-template <typename T>
-__device__ __forceinline__ V4<T> zero4() {
-  V4<T> r;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) r.v[i] = T(0);
-  return r;
-}
-
-enum { M_FUSED = 0, M_BORN = 1, M_BG = 2, M_ADJ = 3 };
-
-// Background step size at cell: a and b of the damped leapfrog.
-template <typename T>
-__device__ __forceinline__ void damping(T eta, T hdt, T& a, T& b) {
-  if (eta == T(0)) {
-    a = T(1);
-    b = T(1);
-  } else {
-    const T e = eta * hdt;
-    a = T(1) / (T(1) + e);
-    b = (T(1) - e) * a;
-  }
-}
-
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_step2d(Step2D<T> p, int n, int hslot) {
+template <typename T, int MODE, int CK>
+__global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int ck_store, int ck_max) {
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int item = xcd_item(p.nwg);
@@ -132,11 +101,11 @@ __global__ __launch_bounds__(256) void k_step2d(Step2D<T> p, int n, int hslot) {
   const long long kofs = (long long)SLACK + (long long)GZ * pitch + XL;
   const T* kap = p.kappa + kofs;
   const T* dmb = p.dmbar + kofs;
-  const int* rmap = p.recmap + kofs;
   const T* hist_n = p.hist + (long long)ls * p.hstride + (long long)hslot * p.L.mstride;
   double* img = (MODE == M_ADJ) ? p.img + (long long)shot * p.L.mstride : nullptr;
   T* hist_w = (MODE == M_FUSED || MODE == M_BG) ? const_cast<T*>(hist_n) : nullptr;
   const T* dat = p.data;
+  float mx0 = 0.0f, mx1 = 0.0f;   // running max |u^{n+1}|, |u^{n+1} - u^n| (BF16 checkpoints)
 
   for (int zb = z0; zb < z1; zb += 9) {
 #pragma unroll
@@ -173,7 +142,7 @@ __global__ __launch_bounds__(256) void k_step2d(Step2D<T> p, int n, int hslot) {
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          T s = p.c0x2 * w[4 + i];
+          T s = p.c0x * w[4 + i];
           s += p.c1 * ((w[3 + i] + w[5 + i]) + (qa[(r + 3) % 9].v[i] + qa[(r + 5) % 9].v[i]));
           s += p.c2 * ((w[2 + i] + w[6 + i]) + (qa[(r + 2) % 9].v[i] + qa[(r + 6) % 9].v[i]));
           s += p.c3 * ((w[1 + i] + w[7 + i]) + (qa[(r + 1) % 9].v[i] + qa[(r + 7) % 9].v[i]));
@@ -192,7 +161,7 @@ __global__ __launch_bounds__(256) void k_step2d(Step2D<T> p, int n, int hslot) {
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          T s = p.c0x2 * w[4 + i];
+          T s = p.c0x * w[4 + i];
           s += p.c1 * ((w[3 + i] + w[5 + i]) + (qb[(r + 3) % 9].v[i] + qb[(r + 5) % 9].v[i]));
           s += p.c2 * ((w[2 + i] + w[6 + i]) + (qb[(r + 2) % 9].v[i] + qb[(r + 6) % 9].v[i]));
           s += p.c3 * ((w[1 + i] + w[7 + i]) + (qb[(r + 1) % 9].v[i] + qb[(r + 7) % 9].v[i]));
@@ -208,10 +177,11 @@ __global__ __launch_bounds__(256) void k_step2d(Step2D<T> p, int n, int hslot) {
         for (int i = 0; i < 4; ++i)
           if (x + i == sx) lapA[i] += wsrc;
       }
-      const bool recrow = p.recrow[z] != 0;
+      const int rp = p.recplane[z];
+      const bool recrow = rp >= 0;
       int rm[4] = {-1, -1, -1, -1};
       if (recrow) {
-        const int4 m4 = *reinterpret_cast<const int4*>(rmap + orow);
+        const int4 m4 = *reinterpret_cast<const int4*>(p.recmap + (long long)rp * p.cpitch + x);
         rm[0] = m4.x;
         rm[1] = m4.y;
         rm[2] = m4.z;
@@ -296,8 +266,58 @@ __global__ __launch_bounds__(256) void k_step2d(Step2D<T> p, int n, int hslot) {
         }
       }
 
+      // background checkpoint from (u^n, u^{n-1}) and running maxima for the next one
+      if (CK != CK_NONE && (MODE == M_FUSED || MODE == M_BG)) {
+        if (ck_store >= 0) {
+          const long long co = (long long)z * p.cpitch + x;
+          const long long lv = ((long long)ls * p.nck + ck_store) * 2;
+          if (CK == CK_F32) {
+            T* c0 = static_cast<T*>(p.ck) + lv * p.cstride + co;
+            T* c1 = c0 + p.cstride;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (xvalid[i]) {
+                c0[i] = qa[(r + 4) % 9].v[i];
+                c1[i] = aprev.v[i];
+              }
+          } else {
+            const float* sc = p.ck_scale + lv;
+            const float s0 = sc[0], s1 = sc[1];
+            const float i0 = s0 > 0.0f ? 1.0f / s0 : 1.0f, i1 = s1 > 0.0f ? 1.0f / s1 : 1.0f;
+            unsigned short* c0 = static_cast<unsigned short*>(p.ck) + lv * p.cstride + co;
+            unsigned short* c1 = c0 + p.cstride;
+            unsigned short h0[4], h1[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float uc = (float)qa[(r + 4) % 9].v[i];
+              h0[i] = bf16_rne(uc * i0);
+              h1[i] = bf16_rne((uc - (float)aprev.v[i]) * i1);
+            }
+            if (xvalall) {
+              *reinterpret_cast<uint2*>(c0) = make_uint2(h0[0] | ((unsigned)h0[1] << 16), h0[2] | ((unsigned)h0[3] << 16));
+              *reinterpret_cast<uint2*>(c1) = make_uint2(h1[0] | ((unsigned)h1[1] << 16), h1[2] | ((unsigned)h1[3] << 16));
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (xvalid[i]) {
+                  c0[i] = h0[i];
+                  c1[i] = h1[i];
+                }
+            }
+          }
+        }
+        if (CK == CK_BF16 && ck_max >= 0) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (xvalid[i]) {
+              mx0 = fmaxf(mx0, fabsf((float)anew.v[i]));
+              mx1 = fmaxf(mx1, fabsf((float)(anew.v[i] - qa[(r + 4) % 9].v[i])));
+            }
+        }
+      }
+
       // history of g (background modes)
-      if ((MODE == M_FUSED || MODE == M_BG) && zmod && xmodany) {
+      if (CK == CK_NONE && (MODE == M_FUSED || MODE == M_BG) && zmod && xmodany) {
         V4<T> gg;
 #pragma unroll
         for (int i = 0; i < 4; ++i) gg.v[i] = g[i];
@@ -334,26 +354,93 @@ __global__ __launch_bounds__(256) void k_step2d(Step2D<T> p, int n, int hslot) {
     }
     // rotate nothing: the queue is addressed modulo 9 and zb advances by 9
   }
-}
-
-template <typename T>
-static void launch(int mode, const Step2D<T>& p, int n, int hslot, hipStream_t st) {
-  const dim3 grid(xcd_grid(p.nwg)), block(256);
-  switch (mode) {
-    case M_FUSED: hipLaunchKernelGGL((k_step2d<T, M_FUSED>), grid, block, 0, st, p, n, hslot); break;
-    case M_BORN: hipLaunchKernelGGL((k_step2d<T, M_BORN>), grid, block, 0, st, p, n, hslot); break;
-    case M_BG: hipLaunchKernelGGL((k_step2d<T, M_BG>), grid, block, 0, st, p, n, hslot); break;
-    default: hipLaunchKernelGGL((k_step2d<T, M_ADJ>), grid, block, 0, st, p, n, hslot); break;
+  if (CK == CK_BF16 && (MODE == M_FUSED || MODE == M_BG) && ck_max >= 0) {
+    for (int o = 32; o > 0; o >>= 1) {
+      mx0 = fmaxf(mx0, __shfl_xor(mx0, o));
+      mx1 = fmaxf(mx1, __shfl_xor(mx1, o));
+    }
+    if (lane == 0) {
+      unsigned int* sc = reinterpret_cast<unsigned int*>(p.ck_scale + ((long long)ls * p.nck + ck_max) * 2);
+      atomicMax(sc, __float_as_uint(mx0));
+      atomicMax(sc + 1, __float_as_uint(mx1));
+    }
   }
 }
 
-void step2d_fused(const Step2D<float>& p, int n, int hs, hipStream_t s) { launch(M_FUSED, p, n, hs, s); }
-void step2d_fused(const Step2D<double>& p, int n, int hs, hipStream_t s) { launch(M_FUSED, p, n, hs, s); }
-void step2d_born(const Step2D<float>& p, int n, int hs, hipStream_t s) { launch(M_BORN, p, n, hs, s); }
-void step2d_born(const Step2D<double>& p, int n, int hs, hipStream_t s) { launch(M_BORN, p, n, hs, s); }
-void step2d_bg(const Step2D<float>& p, int n, int hs, hipStream_t s) { launch(M_BG, p, n, hs, s); }
-void step2d_bg(const Step2D<double>& p, int n, int hs, hipStream_t s) { launch(M_BG, p, n, hs, s); }
-void step2d_adj(const Step2D<float>& p, int k, int hs, hipStream_t s) { launch(M_ADJ, p, k, hs, s); }
-void step2d_adj(const Step2D<double>& p, int k, int hs, hipStream_t s) { launch(M_ADJ, p, k, hs, s); }
+// u_cur <- u^{jk}, u_prev <- u^{jk-1} on the propagation cells of every local shot
+// (2D and 3D layouts).
+template <typename T, int CK>
+__global__ void k_expand(Step<T> p, int nshots, int j) {
+  const long long cells = (long long)p.L.nzp * p.L.nyp * p.L.nxp;
+  const long long total = cells * nshots;
+  const int gy = (p.L.ndim == 3) ? GY : 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+    const int ls = (int)(i / cells);
+    const long long c = i % cells;
+    const int x = (int)(c % p.L.nxp);
+    const long long t = c / p.L.nxp;
+    const int y = (int)(t % p.L.nyp);
+    const int z = (int)(t / p.L.nyp);
+    const long long fo = (long long)ls * p.L.fstride + SLACK + (long long)(z + GZ) * p.L.plane +
+                         (long long)(y + gy) * p.L.pitch + XL + x;
+    const long long lv = ((long long)ls * p.nck + j) * 2;
+    const long long co = ((long long)z * p.L.nyp + y) * p.cpitch + x;
+    T un, up;
+    if (CK == CK_F32) {
+      const T* c0 = static_cast<const T*>(p.ck) + lv * p.cstride + co;
+      un = c0[0];
+      up = c0[p.cstride];
+    } else {
+      const unsigned short* c0 = static_cast<const unsigned short*>(p.ck) + lv * p.cstride + co;
+      const float s0 = p.ck_scale[lv], s1 = p.ck_scale[lv + 1];
+      const float a = bf16_to_f(c0[0]) * s0;
+      un = (T)a;
+      up = (T)(a - bf16_to_f(c0[p.cstride]) * s1);
+    }
+    p.u_cur[fo] = un;
+    p.u_prev[fo] = up;
+  }
+}
+
+template <typename T, int MODE, int CK>
+static void go(const Step<T>& p, int n, int hslot, int cs, int cm, hipStream_t st) {
+  hipLaunchKernelGGL((k_step2d<T, MODE, CK>), dim3(xcd_grid(p.nwg)), dim3(256), 0, st, p, n, hslot, cs, cm);
+}
+
+template <typename T>
+static void launch(int mode, const Step<T>& p, int n, int hs, int ck, int cs, int cm, hipStream_t st) {
+  switch (mode) {
+    case M_FUSED:
+      if (ck == CK_F32) go<T, M_FUSED, CK_F32>(p, n, hs, cs, cm, st);
+      else if (ck == CK_BF16) go<T, M_FUSED, CK_BF16>(p, n, hs, cs, cm, st);
+      else go<T, M_FUSED, CK_NONE>(p, n, hs, -1, -1, st);
+      break;
+    case M_BG:
+      if (ck == CK_F32) go<T, M_BG, CK_F32>(p, n, hs, cs, cm, st);
+      else if (ck == CK_BF16) go<T, M_BG, CK_BF16>(p, n, hs, cs, cm, st);
+      else go<T, M_BG, CK_NONE>(p, n, hs, -1, -1, st);
+      break;
+    case M_BORN: go<T, M_BORN, CK_NONE>(p, n, hs, -1, -1, st); break;
+    default: go<T, M_ADJ, CK_NONE>(p, n, hs, -1, -1, st); break;
+  }
+}
+
+template <typename T>
+static void expand_t(const Step<T>& p, int nshots, int ck, int j, hipStream_t st) {
+  const long long total = (long long)p.L.nzp * p.L.nyp * p.L.nxp * nshots;
+  long long b = (total + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (ck == CK_F32) hipLaunchKernelGGL((k_expand<T, CK_F32>), dim3((unsigned)b), dim3(256), 0, st, p, nshots, j);
+  else hipLaunchKernelGGL((k_expand<T, CK_BF16>), dim3((unsigned)b), dim3(256), 0, st, p, nshots, j);
+}
+
+void step2d(int mode, const Step<float>& p, int n, int hs, int ck, int cs, int cm, hipStream_t s) {
+  launch(mode, p, n, hs, ck, cs, cm, s);
+}
+void step2d(int mode, const Step<double>& p, int n, int hs, int ck, int cs, int cm, hipStream_t s) {
+  launch(mode, p, n, hs, ck, cs, cm, s);
+}
+void expand(const Step<float>& p, int ns, int ck, int j, hipStream_t s) { expand_t(p, ns, ck, j, s); }
+void expand(const Step<double>& p, int ns, int ck, int j, hipStream_t s) { expand_t(p, ns, ck, j, s); }
 
 }  // namespace mp

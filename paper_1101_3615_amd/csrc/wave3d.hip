@@ -1,0 +1,416 @@
+// 3D time-step kernels of the Born / reverse-time sweeps (gfx950).
+//
+// A workgroup (256 threads, 4 wavefronts) owns a 64 x 16 tile of the xy plane
+// and marches down a chunk of z planes.  Each 16-lane row of a wavefront holds
+// 64 consecutive x cells (4 per lane, 16-byte loads), so one wavefront covers
+// 4 y rows and the workgroup 16.  Per plane:
+//   z-neighbours: a 9-plane register queue of the lane's own cells;
+//   x-neighbours: DPP row shifts inside each 16-lane row, plus a 4-cell halo
+//                 loaded by the first and last lane of the row;
+//   y-neighbours: the tile's centre plane plus 4 halo rows above and below,
+//                 staged in LDS (double buffered: one barrier per plane).
+// The arithmetic per cell is that of the 2D kernel with the y axis added.
+#include "common.h"
+#include "wave.h"
+
+namespace mp {
+
+constexpr int TX = 64;   // x cells per tile
+constexpr int TY = 16;   // y rows per tile
+constexpr int PY = TY + 8;
+
+template <typename T>
+__device__ __forceinline__ void lap_row(const V4<T>* qa, int r, const V4<T>& hl, const V4<T>& hr,
+                                        const T (*P)[TX], int yl, int c4, const Step<T>& p, T out[4]) {
+  const V4<T>& C = qa[(r + 4) % 9];
+  T w[12];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    w[i] = rshr1(C.v[i], hl.v[i]);
+    w[4 + i] = C.v[i];
+    w[8 + i] = rshl1(C.v[i], hr.v[i]);
+  }
+  V4<T> ym[4], yp[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    ym[j] = *reinterpret_cast<const V4<T>*>(&P[yl + 4 - (j + 1)][c4]);
+    yp[j] = *reinterpret_cast<const V4<T>*>(&P[yl + 4 + (j + 1)][c4]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    T s = p.c0x * w[4 + i];
+    s += p.c1 * ((w[3 + i] + w[5 + i]) + (ym[0].v[i] + yp[0].v[i]) + (qa[(r + 3) % 9].v[i] + qa[(r + 5) % 9].v[i]));
+    s += p.c2 * ((w[2 + i] + w[6 + i]) + (ym[1].v[i] + yp[1].v[i]) + (qa[(r + 2) % 9].v[i] + qa[(r + 6) % 9].v[i]));
+    s += p.c3 * ((w[1 + i] + w[7 + i]) + (ym[2].v[i] + yp[2].v[i]) + (qa[(r + 1) % 9].v[i] + qa[(r + 7) % 9].v[i]));
+    s += p.c4 * ((w[0 + i] + w[8 + i]) + (ym[3].v[i] + yp[3].v[i]) + (qa[(r + 0) % 9].v[i] + qa[(r + 8) % 9].v[i]));
+    out[i] = s;
+  }
+}
+
+template <typename T, int MODE, int CK>
+__global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int ck_store, int ck_max) {
+  constexpr bool TWO = (MODE == M_FUSED);
+  __shared__ __align__(32) T PA[2][PY][TX];
+  __shared__ __align__(32) T PB[TWO ? 2 : 1][TWO ? PY : 1][TX];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int c = lane & 15;
+  const int yl = wv * 4 + (lane >> 4);     // 0..15 within the tile
+  const int item = xcd_item(p.nwg);
+  if (item >= p.nwg) return;
+  const int chunk = item % p.nchunks;
+  int rest = item / p.nchunks;
+  const int ty = rest % p.L.nytiles;
+  rest /= p.L.nytiles;
+  const int tx = rest % p.L.nstrips;
+  const int ls = rest / p.L.nstrips;
+  const int z0 = chunk * p.zc;
+  const int z1 = min(z0 + p.zc, p.L.nzp);
+
+  const int pitch = p.L.pitch;
+  const long long plane = p.L.plane;
+  const int nxp = p.L.nxp, nyp = p.L.nyp;
+  const int x = tx * TX + c * 4 - XL;          // propagation x of the lane's first cell
+  const int y = ty * TY + yl;
+  const bool yin = y < nyp;
+  const bool xin = (x >= 0) && (x < nxp);
+  const bool act = xin && yin;
+  const bool hl_in = (c == 0) && (x - 4 >= 0) && (x - 4 < nxp) && yin;
+  const bool hr_in = (c == 15) && (x + 4 < nxp) && yin;
+  const long long fo = (long long)ls * p.L.fstride + SLACK + (long long)GZ * plane + (long long)GY * pitch + XL;
+  const long long colrow = (long long)y * pitch + x;    // within a plane
+  const int shot = p.shot0 + ls;
+
+  bool xvalid[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) xvalid[i] = (x + i >= 0) && (x + i < nxp);
+  const bool xvalall = xvalid[0] && xvalid[1] && xvalid[2] && xvalid[3];
+  const int xm = x - p.L.nb, ym = y - p.L.nb;
+  bool xmod[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) xmod[i] = (xm + i >= 0) && (xm + i < p.L.nx);
+  const bool xmodall = xmod[0] && xmod[1] && xmod[2] && xmod[3];
+  const bool xmodany = xmod[0] || xmod[1] || xmod[2] || xmod[3];
+  const bool ymod = (ym >= 0) && (ym < p.L.ny);
+
+  T exy[4];
+  bool xysponge = false;
+  const T ey = yin ? p.etay[y] : T(0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    exy[i] = (xvalid[i] ? p.etax[x + i] : T(0)) + ey;
+    xysponge = xysponge || (exy[i] != T(0));
+  }
+
+  int sx = -1, sy = -1, sz = -1;
+  if (MODE == M_FUSED || MODE == M_BG) {
+    sx = p.srcx[shot];
+    sy = p.srcy[shot];
+    sz = p.srcz[shot];
+  }
+  const T wsrc = (MODE == M_FUSED || MODE == M_BG) ? p.wav[n] : T(0);
+
+  const T* Acur;
+  T* Anext;
+  const T* Bcur = nullptr;
+  T* Bnext = nullptr;
+  if (MODE == M_FUSED) {
+    Acur = p.u_cur + fo;
+    Anext = p.u_prev + fo;
+    Bcur = p.du_cur + fo;
+    Bnext = p.du_prev + fo;
+  } else if (MODE == M_BG) {
+    Acur = p.u_cur + fo;
+    Anext = p.u_prev + fo;
+  } else {
+    Acur = p.du_cur + fo;
+    Anext = p.du_prev + fo;
+  }
+
+  V4<T> qa[9], qb[9];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const long long o = (long long)(z0 - 4 + s) * plane + colrow;
+    qa[s] = act ? ld4(Acur + o) : zero4<T>();
+    if (TWO) qb[s] = act ? ld4(Bcur + o) : zero4<T>();
+  }
+
+  // halo rows of the LDS plane: threads 0..127 field A, 128..255 field B
+  const int ht = tid & 127;
+  const int hrow = ht >> 4;                 // 0..7
+  const int hcol = (ht & 15) * 4;
+  const int hy = (hrow < 4) ? ty * TY - 4 + hrow : ty * TY + TY + (hrow - 4);
+  const int hlds = (hrow < 4) ? hrow : TY + hrow;
+  const int hx = tx * TX + hcol - XL;
+  const bool hload = (hx >= 0) && (hx < nxp) && (hy >= 0) && (hy < nyp);
+  const bool hfieldB = (tid >= 128);
+
+  const long long kofs = (long long)SLACK + (long long)GZ * plane + (long long)GY * pitch + XL;
+  const T* kap = p.kappa + kofs;
+  const T* dmb = p.dmbar + kofs;
+  const T* hist_n = p.hist + (long long)ls * p.hstride + (long long)hslot * p.L.mstride;
+  double* img = (MODE == M_ADJ) ? p.img + (long long)shot * p.L.mstride : nullptr;
+  T* hist_w = (MODE == M_FUSED || MODE == M_BG) ? const_cast<T*>(hist_n) : nullptr;
+  float mx0 = 0.0f, mx1 = 0.0f;
+  int buf = 0;
+
+  for (int zb = z0; zb < z1; zb += 9) {
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const int z = zb + r;
+      if (z >= z1) break;
+      {
+        const long long o = (long long)(z + 4) * plane + colrow;
+        qa[(r + 8) % 9] = act ? ld4(Acur + o) : zero4<T>();
+        if (TWO) qb[(r + 8) % 9] = act ? ld4(Bcur + o) : zero4<T>();
+      }
+      const long long oz = (long long)z * plane;
+      // centre rows and y halo into LDS
+      *reinterpret_cast<V4<T>*>(&PA[buf][yl + 4][c * 4]) = qa[(r + 4) % 9];
+      if (TWO) *reinterpret_cast<V4<T>*>(&PB[buf][yl + 4][c * 4]) = qb[(r + 4) % 9];
+      {
+        V4<T> hv = zero4<T>();
+        const T* src = hfieldB ? Bcur : Acur;
+        if ((TWO || !hfieldB) && hload) hv = ld4(src + oz + (long long)hy * pitch + hx);
+        if (!hfieldB) *reinterpret_cast<V4<T>*>(&PA[buf][hlds][hcol]) = hv;
+        else if (TWO) *reinterpret_cast<V4<T>*>(&PB[buf][hlds][hcol]) = hv;
+      }
+      // x halo of the lane's row
+      V4<T> ahl = zero4<T>(), ahr = zero4<T>(), bhl = zero4<T>(), bhr = zero4<T>();
+      if (hl_in) {
+        ahl = ld4(Acur + oz + colrow - 4);
+        if (TWO) bhl = ld4(Bcur + oz + colrow - 4);
+      }
+      if (hr_in) {
+        ahr = ld4(Acur + oz + colrow + 4);
+        if (TWO) bhr = ld4(Bcur + oz + colrow + 4);
+      }
+      __syncthreads();
+      T lapA[4], lapB[4];
+      lap_row(qa, r, ahl, ahr, PA[buf], yl, c * 4, p, lapA);
+      if (TWO) lap_row(qb, r, bhl, bhr, PB[TWO ? buf : 0], yl, c * 4, p, lapB);
+      buf ^= 1;
+      if (!act) continue;
+
+      const long long orow = oz + colrow;
+      if ((MODE == M_FUSED || MODE == M_BG) && z == sz && y == sy) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (x + i == sx) lapA[i] += wsrc;
+      }
+      const int rp = p.recplane[z];
+      const bool recrow = rp >= 0;
+      int rm[4] = {-1, -1, -1, -1};
+      if (recrow) {
+        const int4 m4 = *reinterpret_cast<const int4*>(p.recmap + ((long long)rp * nyp + y) * p.cpitch + x);
+        rm[0] = m4.x;
+        rm[1] = m4.y;
+        rm[2] = m4.z;
+        rm[3] = m4.w;
+        if (MODE == M_ADJ) {
+          const T* drow = p.data + ((long long)shot * p.nt + (n - 1)) * p.nr;
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (rm[i] >= 0) lapA[i] += drow[rm[i]];
+        }
+      }
+
+      const V4<T> kap4 = ld4(kap + orow);
+      const T ez = p.etaz[z];
+      T a[4], b[4];
+      if (ez == T(0) && !xysponge) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          a[i] = T(1);
+          b[i] = T(1);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) damping(exy[i] + ez, p.hdt, a[i], b[i]);
+      }
+
+      const int zm = z - p.L.nb;
+      const bool zmod = (zm >= 0) && (zm < p.L.nz) && ymod;
+      const long long mo = (long long)zm * p.L.mplane + (long long)ym * p.L.mpitch + xm;
+
+      T g[4] = {T(0), T(0), T(0), T(0)};
+      if (MODE == M_FUSED || MODE == M_BG) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) g[i] = kap4.v[i] * lapA[i] * p.inv_dt2;
+      } else if (zmod && xmodany) {
+        if (xmodall) {
+          const V4<T> gg = ld4(hist_n + mo);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) g[i] = gg.v[i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (xmod[i]) g[i] = hist_n[mo + i];
+        }
+      }
+
+      const V4<T> aprev = ld4(Anext + orow);
+      V4<T> adm = zero4<T>();
+      if (MODE == M_BORN) adm = ld4(dmb + orow);
+      V4<T> anew;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const T cc = qa[(r + 4) % 9].v[i];
+        const T src = (MODE == M_BORN) ? kap4.v[i] * (lapA[i] - adm.v[i] * g[i]) : kap4.v[i] * lapA[i];
+        anew.v[i] = a[i] * (T(2) * cc + src) - b[i] * aprev.v[i];
+      }
+      if (xvalall) {
+        st4(Anext + orow, anew);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (xvalid[i]) Anext[orow + i] = anew.v[i];
+      }
+
+      V4<T> bnew;
+      if (TWO) {
+        const V4<T> bprev = ld4(Bnext + orow);
+        const V4<T> dm4 = ld4(dmb + orow);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const T cc = qb[(r + 4) % 9].v[i];
+          bnew.v[i] = a[i] * (T(2) * cc + kap4.v[i] * (lapB[i] - dm4.v[i] * g[i])) - b[i] * bprev.v[i];
+        }
+        if (xvalall) {
+          st4(Bnext + orow, bnew);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (xvalid[i]) Bnext[orow + i] = bnew.v[i];
+        }
+      }
+
+      if (CK != CK_NONE && (MODE == M_FUSED || MODE == M_BG)) {
+        if (ck_store >= 0) {
+          const long long co = ((long long)z * nyp + y) * p.cpitch + x;
+          const long long lv = ((long long)ls * p.nck + ck_store) * 2;
+          if (CK == CK_F32) {
+            T* c0 = static_cast<T*>(p.ck) + lv * p.cstride + co;
+            T* c1 = c0 + p.cstride;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (xvalid[i]) {
+                c0[i] = qa[(r + 4) % 9].v[i];
+                c1[i] = aprev.v[i];
+              }
+          } else {
+            const float* sc = p.ck_scale + lv;
+            const float s0 = sc[0], s1 = sc[1];
+            const float i0 = s0 > 0.0f ? 1.0f / s0 : 1.0f, i1 = s1 > 0.0f ? 1.0f / s1 : 1.0f;
+            unsigned short* c0 = static_cast<unsigned short*>(p.ck) + lv * p.cstride + co;
+            unsigned short* c1 = c0 + p.cstride;
+            unsigned short h0[4], h1[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float uc = (float)qa[(r + 4) % 9].v[i];
+              h0[i] = bf16_rne(uc * i0);
+              h1[i] = bf16_rne((uc - (float)aprev.v[i]) * i1);
+            }
+            if (xvalall) {
+              *reinterpret_cast<uint2*>(c0) = make_uint2(h0[0] | ((unsigned)h0[1] << 16), h0[2] | ((unsigned)h0[3] << 16));
+              *reinterpret_cast<uint2*>(c1) = make_uint2(h1[0] | ((unsigned)h1[1] << 16), h1[2] | ((unsigned)h1[3] << 16));
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (xvalid[i]) {
+                  c0[i] = h0[i];
+                  c1[i] = h1[i];
+                }
+            }
+          }
+        }
+        if (CK == CK_BF16 && ck_max >= 0) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (xvalid[i]) {
+              mx0 = fmaxf(mx0, fabsf((float)anew.v[i]));
+              mx1 = fmaxf(mx1, fabsf((float)(anew.v[i] - qa[(r + 4) % 9].v[i])));
+            }
+        }
+      }
+
+      if (CK == CK_NONE && (MODE == M_FUSED || MODE == M_BG) && zmod && xmodany) {
+        if (xmodall) {
+          V4<T> gg;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) gg.v[i] = g[i];
+          st4(hist_w + mo, gg);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (xmod[i]) hist_w[mo + i] = g[i];
+        }
+      }
+
+      if ((MODE == M_FUSED || MODE == M_BORN) && recrow) {
+        T* drow = p.data + ((long long)shot * p.nt + n) * p.nr;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (rm[i] >= 0) drow[rm[i]] = TWO ? bnew.v[i] : anew.v[i];
+      }
+
+      if (MODE == M_ADJ && zmod && xmodany) {
+        if (xmodall) {
+          V4<double> acc = *reinterpret_cast<V4<double>*>(img + mo);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc.v[i] -= (double)g[i] * (double)anew.v[i];
+          *reinterpret_cast<V4<double>*>(img + mo) = acc;
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (xmod[i]) img[mo + i] -= (double)g[i] * (double)anew.v[i];
+        }
+      }
+    }
+  }
+  if (CK == CK_BF16 && (MODE == M_FUSED || MODE == M_BG) && ck_max >= 0) {
+    for (int o = 32; o > 0; o >>= 1) {
+      mx0 = fmaxf(mx0, __shfl_xor(mx0, o));
+      mx1 = fmaxf(mx1, __shfl_xor(mx1, o));
+    }
+    if (lane == 0) {
+      unsigned int* sc = reinterpret_cast<unsigned int*>(p.ck_scale + ((long long)ls * p.nck + ck_max) * 2);
+      atomicMax(sc, __float_as_uint(mx0));
+      atomicMax(sc + 1, __float_as_uint(mx1));
+    }
+  }
+}
+
+template <typename T, int MODE, int CK>
+static void go3(const Step<T>& p, int n, int hslot, int cs, int cm, hipStream_t st) {
+  hipLaunchKernelGGL((k_step3d<T, MODE, CK>), dim3(xcd_grid(p.nwg)), dim3(256), 0, st, p, n, hslot, cs, cm);
+}
+
+template <typename T>
+static void launch3(int mode, const Step<T>& p, int n, int hs, int ck, int cs, int cm, hipStream_t st) {
+  switch (mode) {
+    case M_FUSED:
+      if (ck == CK_F32) go3<T, M_FUSED, CK_F32>(p, n, hs, cs, cm, st);
+      else if (ck == CK_BF16) go3<T, M_FUSED, CK_BF16>(p, n, hs, cs, cm, st);
+      else go3<T, M_FUSED, CK_NONE>(p, n, hs, -1, -1, st);
+      break;
+    case M_BG:
+      if (ck == CK_F32) go3<T, M_BG, CK_F32>(p, n, hs, cs, cm, st);
+      else if (ck == CK_BF16) go3<T, M_BG, CK_BF16>(p, n, hs, cs, cm, st);
+      else go3<T, M_BG, CK_NONE>(p, n, hs, -1, -1, st);
+      break;
+    case M_BORN: go3<T, M_BORN, CK_NONE>(p, n, hs, -1, -1, st); break;
+    default: go3<T, M_ADJ, CK_NONE>(p, n, hs, -1, -1, st); break;
+  }
+}
+
+void step3d(int mode, const Step<float>& p, int n, int hs, int ck, int cs, int cm, hipStream_t s) {
+  launch3(mode, p, n, hs, ck, cs, cm, s);
+}
+void step3d(int mode, const Step<double>& p, int n, int hs, int ck, int cs, int cm, hipStream_t s) {
+  launch3(mode, p, n, hs, ck, cs, cm, s);
+}
+
+}  // namespace mp

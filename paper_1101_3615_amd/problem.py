@@ -168,8 +168,12 @@ class Basis:
             pass
 
 
-def probe_fit(problem, basis, ys, xs, stream=None):
-    """Least-squares symbol coefficients c (numpy float64) and the relative residual."""
+def probe_fit(problem, basis, ys, xs, stream=None, strict=True):
+    """Least-squares symbol coefficients c (numpy float64) and the relative residual.
+
+    With strict=False a numerically rank-deficient system returns
+    (c, relres, True) with the minimum-norm coefficients instead of raising.
+    """
     ys = [problem._model(y, "y") for y in ys]
     xs = [problem._model(x, "x") for x in xs]
     T = len(ys)
@@ -180,8 +184,10 @@ def probe_fit(problem, basis, ys, xs, stream=None):
     rc = problem._lib.mp_probe_fit(problem._ctx, basis._h, T, yp, xp,
                                    c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(rel),
                                    _stream(stream))
-    if rc == L.MP_ENUMERIC:
-        L.check(rc)
+    if not strict:
+        if rc not in (L.MP_OK, L.MP_ENUMERIC):
+            L.check(rc)
+        return c, rel.value, rc == L.MP_ENUMERIC
     L.check(rc)
     return c, rel.value
 

@@ -29,7 +29,7 @@ def _problem(M, w):
 def test_apply_Hinv_matches_oracle(dtype, shape):
     M = _gpu()
     nz, nx = shape
-    w = F.tiny(n=8, dtype=dtype).with_(nx=nx, nz=nz)
+    w = F.tiny(n=8, nr=8, dtype=dtype).with_(nx=nx, nz=nz)
     P = _problem(M, w)
     leg = [(0, 0), (1, 0), (2, 1), (0, 3)]
     qs = (0, 1, 2, 3)
@@ -45,7 +45,7 @@ def test_apply_Hinv_matches_oracle(dtype, shape):
 def test_single_multiplier_terms():
     """B_(P0,q) alone: the FFT, the |k| table and the normalisation of each power."""
     M = _gpu()
-    w = F.tiny(n=8, dtype="f64").with_(nx=64, nz=32)
+    w = F.tiny(n=8, nr=8, dtype="f64").with_(nx=64, nz=32)
     P = _problem(M, w)
     img = F.normal_field((32, 64), 12)
     for q in range(4):
@@ -59,7 +59,7 @@ def test_single_multiplier_terms():
 def test_probe_fit_exact_recovery(ntrial):
     """y = sum_i c_i B_i x exactly -> the GPU fit returns c to 1e-10 (Sec. 1.3)."""
     M = _gpu()
-    w = F.tiny(n=8, dtype="f64").with_(nx=128, nz=64)
+    w = F.tiny(n=8, nr=8, dtype="f64").with_(nx=128, nz=64)
     P = _problem(M, w)
     leg = [(a, 0) for a in range(5)]
     qs = (0, 1, 2, 3)
@@ -76,7 +76,7 @@ def test_probe_fit_exact_recovery(ntrial):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_probe_fit_matches_oracle_least_squares(dtype):
     M = _gpu()
-    w = F.tiny(n=8, dtype=dtype).with_(nx=64, nz=64)
+    w = F.tiny(n=8, nr=8, dtype=dtype).with_(nx=64, nz=64)
     P = _problem(M, w)
     leg = [(0, 0), (1, 0), (2, 0)]
     qs = (0, 1, 2, 3)
@@ -91,7 +91,7 @@ def test_probe_fit_matches_oracle_least_squares(dtype):
 
 def test_probe_fit_rank_deficient():
     M = _gpu()
-    w = F.tiny(n=8, dtype="f64").with_(nx=32, nz=32)
+    w = F.tiny(n=8, nr=8, dtype="f64").with_(nx=32, nz=32)
     P = _problem(M, w)
     B = M.Basis([(0, 0), (0, 0)], (0,), 2)        # the same column twice
     x = F.normal_field((32, 32), 80)
@@ -103,7 +103,7 @@ def test_probe_fit_rank_deficient():
 
 def test_non_power_of_two_rejected():
     M = _gpu()
-    w = F.tiny(n=8, dtype="f64").with_(nx=48, nz=32)
+    w = F.tiny(n=8, nr=8, dtype="f64").with_(nx=48, nz=32)
     P = _problem(M, w)
     B = M.Basis([(0, 0)], (0,), 2)
     with pytest.raises(M.MatprobeError) as e:

@@ -158,3 +158,41 @@ def test_error_paths():
         Q.set_background(torch.from_numpy(c))
         Q.apply_H(dm)
     assert e.value.code == -2
+
+
+@pytest.mark.parametrize("snap,k", [("ckpt_f32", 4), ("ckpt_f32", 7), ("ckpt_bf16", 4)])
+def test_checkpoint_modes(snap, k):
+    """Checkpoint + recompute: FP32 checkpoints reproduce the full-history sweep;
+    BF16 checkpoints (level and increment, FP32 scales) stay within 1e-2 of the oracle."""
+    # the physics of the checkpointed workloads: 12 Hz Ricker, dt = 0.8 ms
+    w = ragged("f32", nt=160, ns=3).with_(f_peak=12.0, dt=0.8e-3)
+    M, Pfull, c = _setup(w)
+    O = Oracle(w, c)
+    dm = F.wavepackets(w, c, 95, 6)
+    ref = O.apply_H(dm)
+    full = Pfull.apply_H(torch.from_numpy(dm)).cpu().numpy()
+    P = M.Problem.from_spec(w, snap=snap, ckpt_every=k)
+    P.set_background(torch.from_numpy(c))
+    got = P.apply_H(torch.from_numpy(dm)).cpu().numpy()
+    if snap == "ckpt_f32":
+        assert rel(got, full) <= 1e-6
+        assert rel(got, ref) <= 1e-5
+    else:
+        err = rel(got, ref)
+        print(f"BF16 checkpoints every {k}: apply_H rel L2 vs FP64 oracle = {err:.3e}")
+        assert err <= 1e-2
+    # F then F* reuses the stored checkpoints; F is exact in every mode
+    d = F.normal_field((w.ns, w.nt, w.nr), 96)
+    dF = P.apply_F(torch.from_numpy(dm)).cpu().numpy()
+    assert rel(dF, O.apply_F(dm)) <= 1e-5
+    img = P.apply_Fadj(torch.from_numpy(d)).cpu().numpy()
+    assert P.stats()["background_cached"]
+    tol = 1e-5 if snap == "ckpt_f32" else 1e-2
+    assert rel(img, O.apply_Fadj(d)) <= tol
+    # waves give the same bits
+    fp = P.footprint("H")
+    Q = M.Problem.from_spec(w, snap=snap, ckpt_every=k, budget_bytes=int(fp * 0.55))
+    Q.set_background(torch.from_numpy(c))
+    again = Q.apply_H(torch.from_numpy(dm)).cpu().numpy()
+    assert Q.stats()["waves"] > 1
+    assert np.array_equal(again, got)

@@ -1,0 +1,84 @@
+"""Parity of the 3D HIP sweeps (through the C ABI) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import fixtures as F
+from fixtures.configs import Workload
+from oracle import Problem as Oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1101_3615_amd as M
+    return M
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return 0.0 if np.linalg.norm(a) == 0.0 else float("inf")
+    return float(np.linalg.norm(a - b) / nb)
+
+
+def cube(dtype="f64", nx=100, ny=22, nz=18, nb=8, nt=60, ns=2, snap="full", k=0):
+    """Two 64-cell x tiles, two 16-row y tiles and several z chunks, all ragged."""
+    src = np.array([[3, 5, 0], [nx - 2, ny // 2, 2]], np.int32)[:ns]
+    rx, ry = np.meshgrid(np.arange(0, nx, 7), np.arange(1, ny, 5))
+    rec = np.stack([rx.ravel(), ry.ravel(), np.zeros(rx.size, int)], 1).astype(np.int32)
+    rec = np.concatenate([rec, np.array([[nx - 1, ny - 1, nz - 1]], np.int32)])
+    return Workload(name="cube", ndim=3, nx=nx, ny=ny, nz=nz, h=12.5, nb=nb, dt=1.0e-3, nt=nt,
+                    f_peak=15.0, src=src, rec=rec, dtype=dtype, snap=snap, ckpt_every=k,
+                    medium=dict(kind="smooth_random", cmin=1500.0, cmax=3500.0, corr=60.0, seed=41))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_3d_operators_match_oracle(dtype):
+    M = _gpu()
+    w = cube(dtype)
+    c = F.medium(w)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c))
+    O = Oracle(w, c)
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    dm = F.normal_field(w.model_shape, 51)
+    d = F.normal_field((w.ns, w.nt, w.nr), 52)
+    assert rel(P.apply_F(torch.from_numpy(dm)).cpu().numpy(), O.apply_F(dm)) <= tol
+    assert rel(P.apply_Fadj(torch.from_numpy(d)).cpu().numpy(), O.apply_Fadj(d)) <= tol
+    assert rel(P.apply_H(torch.from_numpy(dm)).cpu().numpy(), O.apply_H(dm)) <= tol
+    # resident background reused by the second call, bit for bit
+    again = P.apply_H(torch.from_numpy(dm)).cpu().numpy()
+    assert P.stats()["background_cached"]
+    assert np.array_equal(again, P.apply_H(torch.from_numpy(dm)).cpu().numpy())
+
+
+def test_3d_dot_product_f32():
+    M = _gpu()
+    w = cube("f32", nt=50)
+    c = F.medium(w)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c))
+    m = F.normal_field(w.model_shape, 53)
+    d = F.normal_field((w.ns, w.nt, w.nr), 54)
+    lhs = np.sum(P.apply_F(torch.from_numpy(m)).double().cpu().numpy() * d)
+    rhs = np.sum(m * P.apply_Fadj(torch.from_numpy(d)).double().cpu().numpy())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+@pytest.mark.parametrize("snap,k", [("ckpt_f32", 8), ("ckpt_bf16", 8)])
+def test_3d_checkpoints(snap, k):
+    M = _gpu()
+    w = cube("f32", nt=70, snap=snap, k=k)
+    c = F.medium(w)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c))
+    O = Oracle(w, c)
+    dm = F.normal_field(w.model_shape, 55)
+    err = rel(P.apply_H(torch.from_numpy(dm)).cpu().numpy(), O.apply_H(dm))
+    print(f"3D {snap} every {k}: apply_H rel L2 vs FP64 oracle = {err:.3e}")
+    assert err <= (1e-5 if snap == "ckpt_f32" else 1e-2)
