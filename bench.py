@@ -96,6 +96,50 @@ def traffic_for(kind, w):
     return k.get("bytes_per_launch")
 
 
+KIND_OF_MODE = {"0": "fused", "1": "born", "2": "background", "3": "adjoint"}
+
+
+def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, workload):
+    """profiles/traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
+    this benchmark and of the copy probe: per sweep kernel, HBM bytes per launch =
+    mean counter (KiB) x 1024 x (copy bytes / the copy kernel's reading of the same
+    counter)."""
+    import csv
+    import glob
+    import re
+
+    def means(d):
+        f = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+        acc = {}
+        for r in csv.DictReader(open(f)):
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    copy_bytes = copy_mib * (1 << 20)
+    cf = [v for k, v in means(copy_fetch_dir).items() if "copyBuffer" in k][0]
+    cw = [v for k, v in means(copy_write_dir).items() if "copyBuffer" in k][0]
+    f_fac = copy_bytes / (cf * 1024.0)
+    w_fac = copy_bytes / (cw * 1024.0)
+    fe, wr = means(fetch_dir), means(write_dir)
+    kernels = {}
+    for name in fe:
+        m = re.search(r"k_step(\d)d<float, (\d), (\d)>", name)
+        if not m or name not in wr:
+            continue
+        kind = KIND_OF_MODE[m.group(2)]
+        kernels[kind] = {"kernel": name, "fetch_kib_raw": fe[name], "write_kib_raw": wr[name],
+                         "bytes_per_launch": fe[name] * 1024.0 * f_fac + wr[name] * 1024.0 * w_fac}
+    src = os.path.join(ROOT, "paper_1101_3615_amd", "csrc", "wave2d.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    rec = {"workload": workload, "wave2d_sha256": digest, "fetch_scale": f_fac, "write_scale": w_fac,
+           "copy_probe_bytes": copy_bytes, "kernels": kernels}
+    out = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,7 +153,13 @@ def main():
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--cpu-workers", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write profiles/traffic.json from rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
+    if args.ingest_counters:
+        import fixtures as F
+        print(json.dumps(ingest_counters(*args.ingest_counters, 1024, F.c2().name), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (shots would shard "
               "across GPUs with one all-reduce of the image; that path is not built)", file=sys.stderr)

@@ -160,6 +160,20 @@ def c4(nx=256, nz=128, ns=16, seed=10):
         legendre=[(0, 0)], trial_seeds=())
 
 
+def c4_union(nx=256, nz=128, seed=10):
+    """A serving shape with the source sets of every shot count in one acquisition.
+
+    Returns (workload, groups): groups[ns] lists the acquisition indices of the
+    ns sources placed at (s + 1/2) NX / ns.
+    """
+    xs, groups = [], {}
+    for ns in SERVE_SHOTS:
+        groups[ns] = list(range(len(xs), len(xs) + ns))
+        xs += _even_sources(nx, ns)
+    w = c4(nx, nz, SERVE_SHOTS[0], seed).with_(src=_row0(xs, 2), name=f"c4_2d_{nx}x{nz}_union")
+    return w, groups
+
+
 def c5():
     """3D: 256^3 at 12.5 m, 32 sources, 64 x 64 receivers, BF16 ckpt/8."""
     sx, sy = np.meshgrid(16 + 32 * np.arange(8), 32 + 64 * np.arange(4))

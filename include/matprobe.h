@@ -135,9 +135,10 @@ void mp_destroy(mp_ctx* ctx);
  * drops any cached background wavefield.  Synchronises the stream. */
 int mp_set_background(mp_ctx* ctx, const void* c_dev, void* stream);
 
-/* Device bytes an operator needs with the current settings (MP_OP_*),
- * counting the context's resident state; used for admission control. */
-int mp_footprint(const mp_ctx* ctx, int op, size_t* bytes);
+/* Device bytes an operator needs with the current settings (MP_OP_*) for a
+ * job of nshots shots (nshots <= 0: every acquisition shot), counting the
+ * context's resident state; used for admission control. */
+int mp_footprint(const mp_ctx* ctx, int op, int nshots, size_t* bytes);
 
 /* F: model perturbation dm_dev -> data d_dev (overwritten), Sec. 1.1 / Sec. 2. */
 int mp_apply_F(mp_ctx* ctx, const void* dm_dev, void* d_dev, void* stream);
@@ -148,6 +149,17 @@ int mp_apply_Fadj(mp_ctx* ctx, const void* d_dev, void* img_dev, void* stream);
 /* H = F*F: out_dev = F*(F dm_dev), fused (the data stay internal).  The
  * image is accumulated in FP64 and rounded once to the field precision. */
 int mp_apply_H(mp_ctx* ctx, const void* dm_dev, void* out_dev, void* stream);
+
+/* Batched normal operator for serving: request r applies
+ * sum over s in its shot list of F_s* F_s to dm_dev[r] and writes out_dev[r].
+ * counts: host int32 [nreq] shots per request; shots: host int32, the shot
+ * lists of all requests concatenated (indices into the acquisition, repeats
+ * allowed).  All shots of all requests are propagated together, one kernel
+ * launch per time step; each result is bit-identical to the same request
+ * submitted alone (per-shot work is independent and images are stacked per
+ * request in the order given).  Overwrites the resident background store. */
+int mp_apply_H_batch(mp_ctx* ctx, int nreq, const int* counts, const int* shots, const void* const* dm_dev,
+                     void* const* out_dev, void* stream);
 
 /* Drop the cached background wavefield and free the memory it holds. */
 int mp_release_cache(mp_ctx* ctx);

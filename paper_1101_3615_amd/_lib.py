@@ -30,7 +30,7 @@ SWEEP_KINDS = ("fused", "born", "background", "adjoint")
 
 EXPORTS = [
     "mp_create", "mp_destroy", "mp_set_background", "mp_footprint", "mp_apply_F",
-    "mp_apply_Fadj", "mp_apply_H", "mp_release_cache", "mp_basis_create",
+    "mp_apply_Fadj", "mp_apply_H", "mp_apply_H_batch", "mp_release_cache", "mp_basis_create",
     "mp_basis_destroy", "mp_probe_fit", "mp_apply_Hinv", "mp_last_stats", "mp_strerror",
     "mp_last_error",
 ]
@@ -99,7 +99,9 @@ def lib():
     L.mp_destroy.argtypes = [vp]
     L.mp_destroy.restype = None
     L.mp_set_background.argtypes = [vp, vp, vp]
-    L.mp_footprint.argtypes = [vp, i, ctypes.POINTER(ctypes.c_size_t)]
+    L.mp_footprint.argtypes = [vp, i, i, ctypes.POINTER(ctypes.c_size_t)]
+    L.mp_apply_H_batch.argtypes = [vp, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     for name in ("mp_apply_F", "mp_apply_Fadj", "mp_apply_H"):
         getattr(L, name).argtypes = [vp, vp, vp, vp]
     L.mp_release_cache.argtypes = [vp]

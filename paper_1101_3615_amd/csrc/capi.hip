@@ -181,10 +181,26 @@ int mp_set_background(mp_ctx* ctx, const void* c_dev, void* stream) {
   return finish(ctx, rc);
 }
 
-int mp_footprint(const mp_ctx* ctx, int op, size_t* bytes) {
+int mp_footprint(const mp_ctx* ctx, int op, int nshots, size_t* bytes) {
   if (!ctx || !bytes) return fail(MP_EINVAL, "null argument");
   if (op < MP_OP_F || op > MP_OP_HINV) return fail(MP_EINVAL, "unknown op");
-  return ctx->eng->footprint(op, bytes);
+  return ctx->eng->footprint(op, nshots, bytes);
+}
+
+int mp_apply_H_batch(mp_ctx* ctx, int nreq, const int* counts, const int* shots, const void* const* dm,
+                     void* const* out, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (nreq < 1 || !counts || !shots || !dm || !out) return fail(MP_EINVAL, "bad batch arguments");
+  if (!ctx->has_bg) return fail(MP_ESTATE, "no background set");
+  long long k = 0;
+  for (int r = 0; r < nreq; ++r) {
+    if (counts[r] < 1) return fail(MP_EINVAL, "every request needs at least one shot");
+    if (!dm[r] || !out[r]) return fail(MP_EINVAL, "null request buffer");
+    for (int i = 0; i < counts[r]; ++i, ++k)
+      if (shots[k] < 0 || shots[k] >= ctx->cfg.ns) return fail(MP_EINVAL, "shot index out of range");
+  }
+  return finish(ctx, ctx->eng->apply_H_batch(nreq, counts, shots, dm, out, (hipStream_t)stream));
 }
 
 int mp_apply_F(mp_ctx* ctx, const void* dm, void* d, void* stream) {

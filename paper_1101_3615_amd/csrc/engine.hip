@@ -105,27 +105,22 @@ class EngineT final : public Engine {
       const int z = c.rec[(size_t)nd * r + nd - 1] + c.nb;
       recmap[(size_t)recplane[z] * msz + (size_t)y * cpitch_ + x] = r;
     }
+    hsx_ = sx;
+    hsy_ = sy;
+    hsz_ = sz;
     int rc;
     if ((rc = wav_.ensure(sizeof(T) * c.nt, budget_, "wavelet"))) return rc;
-    if ((rc = srcx_.ensure(sizeof(int) * c.ns, budget_, "sources"))) return rc;
-    if ((rc = srcy_.ensure(sizeof(int) * c.ns, budget_, "sources"))) return rc;
-    if ((rc = srcz_.ensure(sizeof(int) * c.ns, budget_, "sources"))) return rc;
     if ((rc = recplane_.ensure(sizeof(int) * L_.nzp, budget_, "receivers"))) return rc;
     if ((rc = recmap_.ensure(sizeof(int) * recmap.size(), budget_, "receivers"))) return rc;
     if ((rc = kappa_.ensure(sizeof(T) * L_.fstride, budget_, "kappa"))) return rc;
-    if ((rc = dmbar_.ensure(sizeof(T) * L_.fstride, budget_, "dm"))) return rc;
     if ((rc = etax_.ensure(sizeof(T) * L_.nxp, budget_, "sponge"))) return rc;
     if ((rc = etay_.ensure(sizeof(T) * L_.nyp, budget_, "sponge"))) return rc;
     if ((rc = etaz_.ensure(sizeof(T) * L_.nzp, budget_, "sponge"))) return rc;
     if ((rc = small_.ensure(64, budget_, "scratch"))) return rc;
     MP_HIP(hipMemcpy(wav_.get(), wt.data(), sizeof(T) * c.nt, hipMemcpyHostToDevice));
-    MP_HIP(hipMemcpy(srcx_.get(), sx.data(), sizeof(int) * c.ns, hipMemcpyHostToDevice));
-    MP_HIP(hipMemcpy(srcy_.get(), sy.data(), sizeof(int) * c.ns, hipMemcpyHostToDevice));
-    MP_HIP(hipMemcpy(srcz_.get(), sz.data(), sizeof(int) * c.ns, hipMemcpyHostToDevice));
     MP_HIP(hipMemcpy(recplane_.get(), recplane.data(), sizeof(int) * L_.nzp, hipMemcpyHostToDevice));
     MP_HIP(hipMemcpy(recmap_.get(), recmap.data(), sizeof(int) * recmap.size(), hipMemcpyHostToDevice));
     MP_HIP(hipMemset(kappa_.get(), 0, sizeof(T) * L_.fstride));
-    MP_HIP(hipMemset(dmbar_.get(), 0, sizeof(T) * L_.fstride));
     MP_HIP(hipMemset(etay_.get(), 0, sizeof(T) * L_.nyp));
     MP_HIP(hipDeviceSynchronize());
     return MP_OK;
@@ -141,52 +136,83 @@ class EngineT final : public Engine {
   // g slots per shot: every step (full history) or one checkpoint segment
   long long g_slots() const { return ckpt_mode() ? std::min(cfg_.ckpt_every, cfg_.nt) : cfg_.nt; }
   size_t per_shot_bytes() const {
-    size_t b = sizeof(T) * (size_t)(4 * L_.fstride + g_slots() * L_.mstride);
+    size_t b = sizeof(T) * (size_t)(5 * L_.fstride + g_slots() * L_.mstride);
     if (ckpt_mode()) b += (size_t)nck() * 2 * (ck_elem() * (size_t)cstride_ + sizeof(float));
     return b;
   }
-  size_t fixed_bytes() const {
-    return sizeof(T) * (size_t)cfg_.ns * cfg_.nt * cfg_.nr      // data (apply_H)
-           + sizeof(double) * (size_t)cfg_.ns * L_.mstride;    // per-shot images
+  // bytes that scale with the job (data, per-shot images, perturbation slots)
+  size_t job_bytes(int nb, int nslots) const {
+    return sizeof(T) * (size_t)nb * cfg_.nt * cfg_.nr + sizeof(double) * (size_t)nb * L_.mstride +
+           sizeof(T) * (size_t)nslots * L_.fstride + 4 * sizeof(int) * (size_t)nb;
   }
-  int footprint(int op, size_t* bytes) const override {
+  int footprint(int op, int nshots, size_t* bytes) const override {
     (void)op;
-    const int w = std::max(1, std::min(cfg_.ns, max_wave(SIZE_MAX)));
-    *bytes = budget_->used - reserved_sweep() + fixed_bytes() + per_shot_bytes() * (size_t)w;
+    const int nb = nshots > 0 ? nshots : cfg_.ns;
+    const int w = std::max(1, std::min(nb, max_wave(SIZE_MAX, nb, 1)));
+    *bytes = budget_->used - reserved_sweep() + job_bytes(nb, 1) + per_shot_bytes() * (size_t)w;
     return MP_OK;
   }
   size_t reserved_sweep() const {
-    return fields_.bytes() + hist_.bytes() + data_.bytes() + img_.bytes() + ck_.bytes() + cks_.bytes();
+    return fields_.bytes() + hist_.bytes() + data_.bytes() + img_.bytes() + ck_.bytes() + cks_.bytes() +
+           dmbar_.bytes() + jtab_.bytes();
   }
   size_t reserved() const override { return budget_->used; }
 
-  int max_wave(size_t limit) const {
-    const size_t base = budget_->used - reserved_sweep() + fixed_bytes();
+  int max_wave(size_t limit, int nb, int nslots) const {
+    const size_t base = budget_->used - reserved_sweep() + job_bytes(nb, nslots);
     if (limit <= base) return 0;
     const size_t w = (limit - base) / per_shot_bytes();
-    return (int)std::min<size_t>(w, (size_t)cfg_.ns);
+    return (int)std::min<size_t>(w, (size_t)nb);
   }
 
-  // Wave size: the fewest waves that fit, shots split evenly between them.
-  int plan(int* W) {
-    const int wmax = max_wave(budget_->limit);
+  // Buffers for a job of nb shots and nslots perturbations.  Wave size: the
+  // fewest waves that fit, shots split evenly between them.
+  int plan(int nb, int nslots, int* W) {
+    const int wmax = max_wave(budget_->limit, nb, nslots);
     if (wmax < 1) {
       set_error("budget too small for one shot of the sweep");
       return MP_ENOMEM;
     }
-    const int nw = (cfg_.ns + wmax - 1) / wmax;
-    const int w = (cfg_.ns + nw - 1) / nw;
+    const int nw = (nb + wmax - 1) / wmax;
+    const int w = (nb + nw - 1) / nw;
     int rc;
-    if ((rc = data_.ensure(sizeof(T) * (size_t)cfg_.ns * cfg_.nt * cfg_.nr, budget_, "data"))) return rc;
-    if ((rc = img_.ensure(sizeof(double) * (size_t)cfg_.ns * L_.mstride, budget_, "images"))) return rc;
-    if ((rc = fields_.ensure(sizeof(T) * 4 * (size_t)w * L_.fstride, budget_, "fields"))) return rc;
+    if ((rc = data_.ensure(sizeof(T) * (size_t)nb * cfg_.nt * cfg_.nr, budget_, "data"))) return rc;
+    if ((rc = img_.ensure(sizeof(double) * (size_t)nb * L_.mstride, budget_, "images"))) return rc;
+    if ((rc = dmbar_.ensure(sizeof(T) * (size_t)nslots * L_.fstride, budget_, "dm"))) return rc;
+    if ((rc = jtab_.ensure(4 * sizeof(int) * (size_t)nb, budget_, "job tables"))) return rc;
+    if ((rc = fields_.ensure(sizeof(T) * 5 * (size_t)w * L_.fstride, budget_, "fields"))) return rc;
     if ((rc = hist_.ensure(sizeof(T) * (size_t)w * g_slots() * L_.mstride, budget_, "g store"))) return rc;
     if (ckpt_mode()) {
       if ((rc = ck_.ensure(ck_elem() * (size_t)w * nck() * 2 * cstride_, budget_, "checkpoints"))) return rc;
       if ((rc = cks_.ensure(sizeof(float) * (size_t)w * nck() * 2, budget_, "checkpoint scales"))) return rc;
     }
     *W = w;
-    whole_ = (w >= cfg_.ns);
+    whole_ = (w >= nb);
+    return MP_OK;
+  }
+
+  // Job tables: per job shot, the source cell (x, y, z) and the perturbation slot.
+  // Staged through pinned host memory; the previous upload must have landed
+  // before the staging buffer is rewritten.
+  int upload_job(const std::vector<int>& shots, const std::vector<int>& slots) {
+    const size_t nb = shots.size();
+    if (jev_) MP_HIP(hipEventSynchronize(jev_));
+    else MP_HIP(hipEventCreateWithFlags(&jev_, hipEventDisableTiming));
+    if (jcap_ < 4 * nb) {
+      if (jhost_) MP_HIP(hipHostFree(jhost_));
+      jhost_ = nullptr;
+      MP_HIP(hipHostMalloc((void**)&jhost_, sizeof(int) * 4 * nb, hipHostMallocDefault));
+      jcap_ = 4 * nb;
+    }
+    for (size_t b = 0; b < nb; ++b) {
+      jhost_[b] = hsx_[shots[b]];
+      jhost_[nb + b] = hsy_[shots[b]];
+      jhost_[2 * nb + b] = hsz_[shots[b]];
+      jhost_[3 * nb + b] = slots[b];
+    }
+    MP_HIP(hipMemcpyAsync(jtab_.get(), jhost_, sizeof(int) * 4 * nb, hipMemcpyHostToDevice, stream_));
+    MP_HIP(hipEventRecord(jev_, stream_));
+    jn_ = (int)nb;
     return MP_OK;
   }
 
@@ -206,9 +232,11 @@ class EngineT final : public Engine {
     p.etay = etay_.as<T>();
     p.etaz = etaz_.as<T>();
     p.dmbar = dmbar_.as<T>();
-    p.srcx = srcx_.as<int>();
-    p.srcy = srcy_.as<int>();
-    p.srcz = srcz_.as<int>();
+    const int* jt = jtab_.as<int>();
+    p.srcx = jt;
+    p.srcy = jt + jn_;
+    p.srcz = jt + 2 * jn_;
+    p.dm_slot = jt + 3 * jn_;
     p.wav = wav_.as<T>();
     p.recplane = recplane_.as<int>();
     p.recmap = recmap_.as<int>();
@@ -239,9 +267,10 @@ class EngineT final : public Engine {
     T* f = fields_.as<T>();
     const long long fs = (long long)W * L_.fstride;
     p.u_cur = f;
-    p.u_prev = f + fs;
-    p.du_cur = f + 2 * fs;
-    p.du_prev = f + 3 * fs;
+    p.u_next = f + fs;
+    p.u_inc = f + 2 * fs;
+    p.du_cur = f + 3 * fs;
+    p.du_prev = f + 4 * fs;
     p.hist = hist_.as<T>();
     p.data = data_.as<T>();
     p.img = img_.as<double>();
@@ -316,7 +345,7 @@ class EngineT final : public Engine {
   // ---- sweeps ----
   int zero_fields(int W, bool both) {
     (void)both;
-    fill(fields_.as<T>(), 4LL * W * L_.fstride, T(0), stream_);
+    fill(fields_.as<T>(), 5LL * W * L_.fstride, T(0), stream_);
     MP_CHECK_LAUNCH();
     return MP_OK;
   }
@@ -372,6 +401,11 @@ class EngineT final : public Engine {
       (void)hipEventDestroy(sp.a);
       (void)hipEventDestroy(sp.b);
     }
+    if (jev_) {
+      (void)hipEventSynchronize(jev_);
+      (void)hipEventDestroy(jev_);
+    }
+    if (jhost_) (void)hipHostFree(jhost_);
   }
 
   // forward sweep of shots [s0, s0+nsh): mode 0 fused, 1 Born from stored g, 2 background only.
@@ -399,7 +433,7 @@ class EngineT final : public Engine {
       if (mode == 0) step(M_FUSED, p, n, hs, ck, cs, cm);
       else if (mode == 1) step(M_BORN, p, n, n, CK_NONE, -1, -1);
       else step(M_BG, p, n, hs, ck, cs, cm);
-      std::swap(p.u_cur, p.u_prev);
+      std::swap(p.u_cur, p.u_next);
       std::swap(p.du_cur, p.du_prev);
     }
     MP_CHECK_LAUNCH();
@@ -431,14 +465,10 @@ class EngineT final : public Engine {
       const int len = std::min(kk, cfg_.nt - n0);
       if ((rc = span_begin(MP_SWEEP_BACKGROUND, len, &sp))) return rc;
       expand(p, nsh, ck, j, stream_);
-      T* uc = p.u_cur;
-      T* up = p.u_prev;
       for (int n = n0; n < n0 + len; ++n) {
         step(M_BG, p, n, n - n0, CK_NONE, -1, -1);
-        std::swap(p.u_cur, p.u_prev);
+        std::swap(p.u_cur, p.u_next);
       }
-      p.u_cur = uc;
-      p.u_prev = up;
       if ((rc = span_end(sp))) return rc;
       if ((rc = span_begin(MP_SWEEP_ADJOINT, len, &sp))) return rc;
       for (int k = n0 + len; k >= n0 + 1; --k) {
@@ -451,17 +481,26 @@ class EngineT final : public Engine {
     return MP_OK;
   }
 
-  void finish_stats(int waves, bool used_cache) {
-    stats.cell_steps = (double)cfg_.prop_cells() * cfg_.nt * cfg_.ns;
+  void finish_stats(int waves, bool used_cache, long long shots) {
+    stats.cell_steps = (double)cfg_.prop_cells() * cfg_.nt * (double)shots;
     stats.waves = waves;
     stats.background_cached = used_cache ? 1 : 0;
     stats.bytes_reserved = budget_->used;
   }
 
+  // the job of a plain call: every acquisition shot once, perturbation slot 0
+  int plain_job(int* W) {
+    int rc;
+    if ((rc = plan(cfg_.ns, 1, W))) return rc;
+    std::vector<int> shots(cfg_.ns), slots(cfg_.ns, 0);
+    for (int i = 0; i < cfg_.ns; ++i) shots[i] = i;
+    return upload_job(shots, slots);
+  }
+
   int apply_F(const void* dm, void* d, hipStream_t s) override {
     stream_ = s;
     int W, rc;
-    if ((rc = plan(&W))) return rc;
+    if ((rc = plain_job(&W))) return rc;
     extend(dmbar_.as<T>(), static_cast<const T*>(dm), pad(), s);
     MP_CHECK_LAUNCH();
     // with checkpoints the Born field still needs g at every step: always fused
@@ -472,14 +511,14 @@ class EngineT final : public Engine {
       if ((rc = forward(use_cache ? 1 : 0, s0, nsh, W, static_cast<T*>(d)))) return rc;
     }
     cached_ = whole_;
-    finish_stats(waves, use_cache);
+    finish_stats(waves, use_cache, cfg_.ns);
     return MP_OK;
   }
 
   int apply_Fadj(const void* d, void* img, hipStream_t s) override {
     stream_ = s;
     int W, rc;
-    if ((rc = plan(&W))) return rc;
+    if ((rc = plain_job(&W))) return rc;
     const bool use_cache = cached_ && whole_;
     int waves = 0;
     for (int s0 = 0; s0 < cfg_.ns; s0 += W, ++waves) {
@@ -491,14 +530,14 @@ class EngineT final : public Engine {
     cached_ = whole_;
     stack(static_cast<T*>(img), img_.as<double>(), cfg_.ns, L_.mstride, cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
     MP_CHECK_LAUNCH();
-    finish_stats(waves, use_cache);
+    finish_stats(waves, use_cache, cfg_.ns);
     return MP_OK;
   }
 
   int apply_H(const void* dm, void* out, hipStream_t s) override {
     stream_ = s;
     int W, rc;
-    if ((rc = plan(&W))) return rc;
+    if ((rc = plain_job(&W))) return rc;
     extend(dmbar_.as<T>(), static_cast<const T*>(dm), pad(), s);
     MP_CHECK_LAUNCH();
     const bool use_cache = cached_ && whole_ && !ckpt_mode();
@@ -512,7 +551,45 @@ class EngineT final : public Engine {
     cached_ = whole_;
     stack(static_cast<T*>(out), img_.as<double>(), cfg_.ns, L_.mstride, cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
     MP_CHECK_LAUNCH();
-    finish_stats(waves, use_cache);
+    finish_stats(waves, use_cache, cfg_.ns);
+    return MP_OK;
+  }
+
+  // Several normal-operator applications in one sweep: request r applies
+  // sum over its shots of F_s* F_s to dm[r].  The shots of all requests are
+  // propagated together (one launch per time step); each request's image is
+  // stacked from its own shots in the order given.
+  int apply_H_batch(int nreq, const int* counts, const int* shots, const void* const* dm, void* const* out,
+                    hipStream_t s) override {
+    stream_ = s;
+    std::vector<int> js, jslot;
+    for (int r = 0, k = 0; r < nreq; ++r)
+      for (int i = 0; i < counts[r]; ++i, ++k) {
+        js.push_back(shots[k]);
+        jslot.push_back(r);
+      }
+    const int nb = (int)js.size();
+    int W, rc;
+    if ((rc = plan(nb, nreq, &W))) return rc;
+    if ((rc = upload_job(js, jslot))) return rc;
+    for (int r = 0; r < nreq; ++r) {
+      extend(dmbar_.as<T>() + (long long)r * L_.fstride, static_cast<const T*>(dm[r]), pad(), s);
+      MP_CHECK_LAUNCH();
+    }
+    cached_ = false;     // the stores now hold this job's shots
+    int waves = 0;
+    T* data = data_.as<T>();
+    for (int s0 = 0; s0 < nb; s0 += W, ++waves) {
+      const int nsh = std::min(W, nb - s0);
+      if ((rc = forward(0, s0, nsh, W, data))) return rc;
+      if ((rc = adjoint(s0, nsh, W, data))) return rc;
+    }
+    for (int r = 0, b0 = 0; r < nreq; b0 += counts[r], ++r) {
+      stack(static_cast<T*>(out[r]), img_.as<double>() + (long long)b0 * L_.mstride, counts[r], L_.mstride,
+            cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
+      MP_CHECK_LAUNCH();
+    }
+    finish_stats(waves, false, nb);
     return MP_OK;
   }
 
@@ -522,6 +599,10 @@ class EngineT final : public Engine {
     fields_.release();
     data_.release();
     img_.release();
+    ck_.release();
+    cks_.release();
+    dmbar_.release();
+    jtab_.release();
     return MP_OK;
   }
 
@@ -535,7 +616,12 @@ class EngineT final : public Engine {
   bool cached_ = false;
   bool whole_ = false;
   hipStream_t stream_ = nullptr;
-  DevBuf wav_, srcx_, srcy_, srcz_, recplane_, recmap_, kappa_, dmbar_, etax_, etay_, etaz_, small_;
+  DevBuf wav_, recplane_, recmap_, kappa_, dmbar_, jtab_, etax_, etay_, etaz_, small_;
+  std::vector<int> hsx_, hsy_, hsz_;
+  int* jhost_ = nullptr;
+  size_t jcap_ = 0;
+  hipEvent_t jev_ = nullptr;
+  int jn_ = 0;
   DevBuf fields_, hist_, data_, img_, ck_, cks_;
 };
 

@@ -32,27 +32,29 @@ struct Step {
   const T* etax;             // [nxp]
   const T* etay;             // [nyp]
   const T* etaz;             // [nzp]
-  const T* dmbar;            // field layout: zero-extended model perturbation
-  const int* srcx;           // [ns] propagation-grid source cell
+  const T* dmbar;            // [slot][field layout]: zero-extended model perturbations
+  const int* dm_slot;        // [shots of the job] perturbation slot of each shot
+  const int* srcx;           // [shots of the job] propagation-grid source cell
   const int* srcy;
   const int* srcz;
   const T* wav;              // [nt] wavelet / h^ndim
   const int* recplane;       // [nzp] receiver map of the plane, or -1
   const int* recmap;         // [maps][nyp][cpitch]: receiver index or -1
   int nr, nt;
-  int shot0;                 // global index of local shot 0 of this wave
+  int shot0;                 // job index of local shot 0 of this wave
   int zc, nchunks, ngroups, nwg;
-  T* u_cur;                  // background levels n and n-1 (n-1 overwritten by n+1)
-  T* u_prev;
+  T* u_cur;                  // background level n (read)
+  T* u_next;                 // background level n+1 (written)
+  T* u_inc;                  // background increment u^n - u^{n-1}, updated in place
   T* du_cur;                 // Born / adjoint levels
   T* du_prev;
   T* hist;                   // g store: [local shot][slot][model]
   long long hstride;         // elements per local shot in hist
-  T* data;                   // [ns][nt][nr] (global shot index)
-  double* img;               // [ns][model] FP64 per-shot images
+  T* data;                   // [shots of the job][nt][nr]
+  double* img;               // [shots of the job][model] FP64 per-shot images
   // background checkpoints (checkpoint snapshot modes); compact layout
   // [z][y][cpitch] per level
-  void* ck;                  // [local shot][nck][2][cstride]: FP32 (u^n, u^{n-1}) or BF16 (u^n, u^n - u^{n-1})
+  void* ck;                  // [local shot][nck][2][cstride]: (u^n, u^n - u^{n-1}) in FP32 or BF16
   float* ck_scale;           // [local shot][nck][2] max-abs scale of each BF16 level
   long long cstride;         // elements per checkpoint level (nzp * nyp * cpitch)
   int cpitch;                // compact row pitch (multiple of 4)
@@ -73,7 +75,7 @@ void step2d(int mode, const Step<float>& p, int n, int hslot, int ck, int ck_sto
 void step2d(int mode, const Step<double>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
 void step3d(int mode, const Step<float>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
 void step3d(int mode, const Step<double>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
-// u_cur <- u^{jk}, u_prev <- u^{jk-1} from checkpoint j for the wave's shots
+// u_cur <- u^{jk}, u_inc <- u^{jk} - u^{jk-1} from checkpoint j for the wave's shots
 void expand(const Step<float>& p, int nshots, int ck, int j, hipStream_t s);
 void expand(const Step<double>& p, int nshots, int ck, int j, hipStream_t s);
 

@@ -17,6 +17,24 @@
 
 namespace mp {
 
+// 8th-order Laplacian of the 4 cells of a lane in difference form:
+// sum_j c_j [(u_{x-j} - u) + (u_{x+j} - u) + (u_{z-j} - u) + (u_{z+j} - u)], the
+// smallest weights first.  Algebraically equal to c0 u + sum_j c_j (pairs);
+// in FP32 it rounds relative to the differences instead of to u, which keeps
+// smooth, well-resolved fields accurate over thousands of steps.
+template <typename T>
+__device__ __forceinline__ void lap_diff(const T (&w)[12], const V4<T>* q, int r, const Step<T>& p, T out[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const T c = w[4 + i];
+    T s = p.c4 * (((w[0 + i] - c) + (w[8 + i] - c)) + ((q[(r + 0) % 9].v[i] - c) + (q[(r + 8) % 9].v[i] - c)));
+    s += p.c3 * (((w[1 + i] - c) + (w[7 + i] - c)) + ((q[(r + 1) % 9].v[i] - c) + (q[(r + 7) % 9].v[i] - c)));
+    s += p.c2 * (((w[2 + i] - c) + (w[6 + i] - c)) + ((q[(r + 2) % 9].v[i] - c) + (q[(r + 6) % 9].v[i] - c)));
+    s += p.c1 * (((w[3 + i] - c) + (w[5 + i] - c)) + ((q[(r + 3) % 9].v[i] - c) + (q[(r + 5) % 9].v[i] - c)));
+    out[i] = s;
+  }
+}
+
 template <typename T, int MODE, int CK>
 __global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int ck_store, int ck_max) {
   const int lane = threadIdx.x & 63;
@@ -72,18 +90,24 @@ __global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int
   const T wsrc = (MODE == M_FUSED || MODE == M_BG) ? p.wav[n] : T(0);
 
   // field pointers: queue field A (u0 / du / nu), optional B (du in fused mode)
+  // A: the queued field (background u in FUSED/BG, Born or adjoint field otherwise).
+  // The background is stepped in increment form: Ainc holds u^n - u^{n-1} (updated
+  // in place), u^{n+1} goes to Anext; the other fields keep two levels (Anext
+  // holds level n-1 and receives level n+1).
+  constexpr bool BGM = (MODE == M_FUSED || MODE == M_BG);
   const T* Acur;
   T* Anext;
+  T* Ainc = nullptr;
   const T* Bcur = nullptr;
   T* Bnext = nullptr;
-  if (MODE == M_FUSED) {
+  if (BGM) {
     Acur = p.u_cur + fo;
-    Anext = p.u_prev + fo;
-    Bcur = p.du_cur + fo;
-    Bnext = p.du_prev + fo;
-  } else if (MODE == M_BG) {
-    Acur = p.u_cur + fo;
-    Anext = p.u_prev + fo;
+    Anext = p.u_next + fo;
+    Ainc = p.u_inc + fo;
+    if (MODE == M_FUSED) {
+      Bcur = p.du_cur + fo;
+      Bnext = p.du_prev + fo;
+    }
   } else {
     Acur = p.du_cur + fo;
     Anext = p.du_prev + fo;
@@ -100,7 +124,7 @@ __global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int
 
   const long long kofs = (long long)SLACK + (long long)GZ * pitch + XL;
   const T* kap = p.kappa + kofs;
-  const T* dmb = p.dmbar + kofs;
+  const T* dmb = p.dmbar + (long long)p.dm_slot[shot] * p.L.fstride + kofs;
   const T* hist_n = p.hist + (long long)ls * p.hstride + (long long)hslot * p.L.mstride;
   double* img = (MODE == M_ADJ) ? p.img + (long long)shot * p.L.mstride : nullptr;
   T* hist_w = (MODE == M_FUSED || MODE == M_BG) ? const_cast<T*>(hist_n) : nullptr;
@@ -140,15 +164,7 @@ __global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int
           w[4 + i] = C.v[i];
           w[8 + i] = shl1(C.v[i], ahr.v[i]);
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          T s = p.c0x * w[4 + i];
-          s += p.c1 * ((w[3 + i] + w[5 + i]) + (qa[(r + 3) % 9].v[i] + qa[(r + 5) % 9].v[i]));
-          s += p.c2 * ((w[2 + i] + w[6 + i]) + (qa[(r + 2) % 9].v[i] + qa[(r + 6) % 9].v[i]));
-          s += p.c3 * ((w[1 + i] + w[7 + i]) + (qa[(r + 1) % 9].v[i] + qa[(r + 7) % 9].v[i]));
-          s += p.c4 * ((w[0 + i] + w[8 + i]) + (qa[(r + 0) % 9].v[i] + qa[(r + 8) % 9].v[i]));
-          lapA[i] = s;
-        }
+        lap_diff(w, qa, r, p, lapA);
       }
       if (TWO) {
         const V4<T>& C = qb[(r + 4) % 9];
@@ -159,15 +175,7 @@ __global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int
           w[4 + i] = C.v[i];
           w[8 + i] = shl1(C.v[i], bhr.v[i]);
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          T s = p.c0x * w[4 + i];
-          s += p.c1 * ((w[3 + i] + w[5 + i]) + (qb[(r + 3) % 9].v[i] + qb[(r + 5) % 9].v[i]));
-          s += p.c2 * ((w[2 + i] + w[6 + i]) + (qb[(r + 2) % 9].v[i] + qb[(r + 6) % 9].v[i]));
-          s += p.c3 * ((w[1 + i] + w[7 + i]) + (qb[(r + 1) % 9].v[i] + qb[(r + 7) % 9].v[i]));
-          s += p.c4 * ((w[0 + i] + w[8 + i]) + (qb[(r + 0) % 9].v[i] + qb[(r + 8) % 9].v[i]));
-          lapB[i] = s;
-        }
+        lap_diff(w, qb, r, p, lapB);
       }
       if (!xin) continue;   // nothing to write for padding lanes (after all DPP use)
 
@@ -229,23 +237,33 @@ __global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int
         }
       }
 
-      const V4<T> aprev = ld4(Anext + orow);
+      // aprev: level n-1 (two-level fields) or the increment u^n - u^{n-1} (background)
+      const V4<T> aprev = ld4((BGM ? Ainc : Anext) + orow);
       V4<T> adm = zero4<T>();
       if (MODE == M_BORN) adm = ld4(dmb + orow);
-      V4<T> anew;
+      V4<T> anew, ainc;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const T c = qa[(r + 4) % 9].v[i];
-        const T src = (MODE == M_BORN) ? kap4.v[i] * (lapA[i] - adm.v[i] * g[i])
-                                       : kap4.v[i] * lapA[i];
-        anew.v[i] = a[i] * (T(2) * c + src) - b[i] * aprev.v[i];
+        if (BGM) {
+          // u+ = a (2u + kappa Lam) - b u-  written as  d+ = b d + a kappa Lam,  u+ = u + d+
+          ainc.v[i] = b[i] * aprev.v[i] + a[i] * (kap4.v[i] * lapA[i]);
+          anew.v[i] = c + ainc.v[i];
+        } else {
+          const T src = (MODE == M_BORN) ? kap4.v[i] * (lapA[i] - adm.v[i] * g[i]) : kap4.v[i] * lapA[i];
+          anew.v[i] = a[i] * (T(2) * c + src) - b[i] * aprev.v[i];
+        }
       }
       if (xvalall) {
         st4(Anext + orow, anew);
+        if (BGM) st4(Ainc + orow, ainc);
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (xvalid[i]) Anext[orow + i] = anew.v[i];
+          if (xvalid[i]) {
+            Anext[orow + i] = anew.v[i];
+            if (BGM) Ainc[orow + i] = ainc.v[i];
+          }
       }
 
       V4<T> bnew;
@@ -266,7 +284,7 @@ __global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int
         }
       }
 
-      // background checkpoint from (u^n, u^{n-1}) and running maxima for the next one
+      // background checkpoint (u^n, u^n - u^{n-1}) and running maxima for the next one
       if (CK != CK_NONE && (MODE == M_FUSED || MODE == M_BG)) {
         if (ck_store >= 0) {
           const long long co = (long long)z * p.cpitch + x;
@@ -291,7 +309,7 @@ __global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int
             for (int i = 0; i < 4; ++i) {
               const float uc = (float)qa[(r + 4) % 9].v[i];
               h0[i] = bf16_rne(uc * i0);
-              h1[i] = bf16_rne((uc - (float)aprev.v[i]) * i1);
+              h1[i] = bf16_rne((float)aprev.v[i] * i1);
             }
             if (xvalall) {
               *reinterpret_cast<uint2*>(c0) = make_uint2(h0[0] | ((unsigned)h0[1] << 16), h0[2] | ((unsigned)h0[3] << 16));
@@ -311,7 +329,7 @@ __global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int
           for (int i = 0; i < 4; ++i)
             if (xvalid[i]) {
               mx0 = fmaxf(mx0, fabsf((float)anew.v[i]));
-              mx1 = fmaxf(mx1, fabsf((float)(anew.v[i] - qa[(r + 4) % 9].v[i])));
+              mx1 = fmaxf(mx1, fabsf((float)ainc.v[i]));
             }
         }
       }
@@ -367,8 +385,8 @@ __global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int
   }
 }
 
-// u_cur <- u^{jk}, u_prev <- u^{jk-1} on the propagation cells of every local shot
-// (2D and 3D layouts).
+// u_cur <- u^{jk}, u_inc <- u^{jk} - u^{jk-1} on the propagation cells of every
+// local shot (2D and 3D layouts).
 template <typename T, int CK>
 __global__ void k_expand(Step<T> p, int nshots, int j) {
   const long long cells = (long long)p.L.nzp * p.L.nyp * p.L.nxp;
@@ -385,20 +403,19 @@ __global__ void k_expand(Step<T> p, int nshots, int j) {
                          (long long)(y + gy) * p.L.pitch + XL + x;
     const long long lv = ((long long)ls * p.nck + j) * 2;
     const long long co = ((long long)z * p.L.nyp + y) * p.cpitch + x;
-    T un, up;
+    T un, ui;
     if (CK == CK_F32) {
       const T* c0 = static_cast<const T*>(p.ck) + lv * p.cstride + co;
       un = c0[0];
-      up = c0[p.cstride];
+      ui = c0[p.cstride];
     } else {
       const unsigned short* c0 = static_cast<const unsigned short*>(p.ck) + lv * p.cstride + co;
       const float s0 = p.ck_scale[lv], s1 = p.ck_scale[lv + 1];
-      const float a = bf16_to_f(c0[0]) * s0;
-      un = (T)a;
-      up = (T)(a - bf16_to_f(c0[p.cstride]) * s1);
+      un = (T)(bf16_to_f(c0[0]) * s0);
+      ui = (T)(bf16_to_f(c0[p.cstride]) * s1);
     }
     p.u_cur[fo] = un;
-    p.u_prev[fo] = up;
+    p.u_inc[fo] = ui;
   }
 }
 

@@ -36,13 +36,18 @@ __device__ __forceinline__ void lap_row(const V4<T>* qa, int r, const V4<T>& hl,
     ym[j] = *reinterpret_cast<const V4<T>*>(&P[yl + 4 - (j + 1)][c4]);
     yp[j] = *reinterpret_cast<const V4<T>*>(&P[yl + 4 + (j + 1)][c4]);
   }
+  // difference form, smallest weights first (see the 2D kernel)
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    T s = p.c0x * w[4 + i];
-    s += p.c1 * ((w[3 + i] + w[5 + i]) + (ym[0].v[i] + yp[0].v[i]) + (qa[(r + 3) % 9].v[i] + qa[(r + 5) % 9].v[i]));
-    s += p.c2 * ((w[2 + i] + w[6 + i]) + (ym[1].v[i] + yp[1].v[i]) + (qa[(r + 2) % 9].v[i] + qa[(r + 6) % 9].v[i]));
-    s += p.c3 * ((w[1 + i] + w[7 + i]) + (ym[2].v[i] + yp[2].v[i]) + (qa[(r + 1) % 9].v[i] + qa[(r + 7) % 9].v[i]));
-    s += p.c4 * ((w[0 + i] + w[8 + i]) + (ym[3].v[i] + yp[3].v[i]) + (qa[(r + 0) % 9].v[i] + qa[(r + 8) % 9].v[i]));
+    const T c = w[4 + i];
+    T s = p.c4 * (((w[0 + i] - c) + (w[8 + i] - c)) + ((ym[3].v[i] - c) + (yp[3].v[i] - c)) +
+                  ((qa[(r + 0) % 9].v[i] - c) + (qa[(r + 8) % 9].v[i] - c)));
+    s += p.c3 * (((w[1 + i] - c) + (w[7 + i] - c)) + ((ym[2].v[i] - c) + (yp[2].v[i] - c)) +
+                 ((qa[(r + 1) % 9].v[i] - c) + (qa[(r + 7) % 9].v[i] - c)));
+    s += p.c2 * (((w[2 + i] - c) + (w[6 + i] - c)) + ((ym[1].v[i] - c) + (yp[1].v[i] - c)) +
+                 ((qa[(r + 2) % 9].v[i] - c) + (qa[(r + 6) % 9].v[i] - c)));
+    s += p.c1 * (((w[3 + i] - c) + (w[5 + i] - c)) + ((ym[0].v[i] - c) + (yp[0].v[i] - c)) +
+                 ((qa[(r + 3) % 9].v[i] - c) + (qa[(r + 5) % 9].v[i] - c)));
     out[i] = s;
   }
 }
@@ -112,18 +117,21 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
   }
   const T wsrc = (MODE == M_FUSED || MODE == M_BG) ? p.wav[n] : T(0);
 
+  // background in increment form (see the 2D kernel)
+  constexpr bool BGM = (MODE == M_FUSED || MODE == M_BG);
   const T* Acur;
   T* Anext;
+  T* Ainc = nullptr;
   const T* Bcur = nullptr;
   T* Bnext = nullptr;
-  if (MODE == M_FUSED) {
+  if (BGM) {
     Acur = p.u_cur + fo;
-    Anext = p.u_prev + fo;
-    Bcur = p.du_cur + fo;
-    Bnext = p.du_prev + fo;
-  } else if (MODE == M_BG) {
-    Acur = p.u_cur + fo;
-    Anext = p.u_prev + fo;
+    Anext = p.u_next + fo;
+    Ainc = p.u_inc + fo;
+    if (MODE == M_FUSED) {
+      Bcur = p.du_cur + fo;
+      Bnext = p.du_prev + fo;
+    }
   } else {
     Acur = p.du_cur + fo;
     Anext = p.du_prev + fo;
@@ -149,7 +157,7 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
 
   const long long kofs = (long long)SLACK + (long long)GZ * plane + (long long)GY * pitch + XL;
   const T* kap = p.kappa + kofs;
-  const T* dmb = p.dmbar + kofs;
+  const T* dmb = p.dmbar + (long long)p.dm_slot[shot] * p.L.fstride + kofs;
   const T* hist_n = p.hist + (long long)ls * p.hstride + (long long)hslot * p.L.mstride;
   double* img = (MODE == M_ADJ) ? p.img + (long long)shot * p.L.mstride : nullptr;
   T* hist_w = (MODE == M_FUSED || MODE == M_BG) ? const_cast<T*>(hist_n) : nullptr;
@@ -251,22 +259,31 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
         }
       }
 
-      const V4<T> aprev = ld4(Anext + orow);
+      const V4<T> aprev = ld4((BGM ? Ainc : Anext) + orow);
       V4<T> adm = zero4<T>();
       if (MODE == M_BORN) adm = ld4(dmb + orow);
-      V4<T> anew;
+      V4<T> anew, ainc;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const T cc = qa[(r + 4) % 9].v[i];
-        const T src = (MODE == M_BORN) ? kap4.v[i] * (lapA[i] - adm.v[i] * g[i]) : kap4.v[i] * lapA[i];
-        anew.v[i] = a[i] * (T(2) * cc + src) - b[i] * aprev.v[i];
+        if (BGM) {
+          ainc.v[i] = b[i] * aprev.v[i] + a[i] * (kap4.v[i] * lapA[i]);
+          anew.v[i] = cc + ainc.v[i];
+        } else {
+          const T src = (MODE == M_BORN) ? kap4.v[i] * (lapA[i] - adm.v[i] * g[i]) : kap4.v[i] * lapA[i];
+          anew.v[i] = a[i] * (T(2) * cc + src) - b[i] * aprev.v[i];
+        }
       }
       if (xvalall) {
         st4(Anext + orow, anew);
+        if (BGM) st4(Ainc + orow, ainc);
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (xvalid[i]) Anext[orow + i] = anew.v[i];
+          if (xvalid[i]) {
+            Anext[orow + i] = anew.v[i];
+            if (BGM) Ainc[orow + i] = ainc.v[i];
+          }
       }
 
       V4<T> bnew;
@@ -311,7 +328,7 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
             for (int i = 0; i < 4; ++i) {
               const float uc = (float)qa[(r + 4) % 9].v[i];
               h0[i] = bf16_rne(uc * i0);
-              h1[i] = bf16_rne((uc - (float)aprev.v[i]) * i1);
+              h1[i] = bf16_rne((float)aprev.v[i] * i1);
             }
             if (xvalall) {
               *reinterpret_cast<uint2*>(c0) = make_uint2(h0[0] | ((unsigned)h0[1] << 16), h0[2] | ((unsigned)h0[3] << 16));
@@ -331,7 +348,7 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
           for (int i = 0; i < 4; ++i)
             if (xvalid[i]) {
               mx0 = fmaxf(mx0, fabsf((float)anew.v[i]));
-              mx1 = fmaxf(mx1, fabsf((float)(anew.v[i] - qa[(r + 4) % 9].v[i])));
+              mx1 = fmaxf(mx1, fabsf((float)ainc.v[i]));
             }
         }
       }

@@ -119,12 +119,29 @@ class Problem:
         L.check(self._lib.mp_apply_H(self._ctx, _ptr(dm), _ptr(o), _stream(stream)))
         return o
 
-    def footprint(self, op="H"):
+    def footprint(self, op="H", nshots=0):
+        """Device bytes the operator needs for nshots shots (0: all acquisition shots)."""
         code = {"F": L.MP_OP_F, "Fadj": L.MP_OP_FADJ, "H": L.MP_OP_H, "fit": L.MP_OP_FIT,
                 "Hinv": L.MP_OP_HINV}[op]
         b = ctypes.c_size_t()
-        L.check(self._lib.mp_footprint(self._ctx, code, ctypes.byref(b)))
+        L.check(self._lib.mp_footprint(self._ctx, code, int(nshots), ctypes.byref(b)))
         return b.value
+
+    def apply_H_batch(self, dms, shot_lists, outs=None, stream=None):
+        """out[r] = sum over shot_lists[r] of F_s* F_s dms[r], all requests in one sweep."""
+        dms = [self._model(d, "dm") for d in dms]
+        if outs is None:
+            outs = [torch.empty(self.model_shape, dtype=self.torch_dtype, device=self.device) for _ in dms]
+        n = len(dms)
+        counts = np.ascontiguousarray([len(s) for s in shot_lists], dtype=np.int32)
+        shots = np.ascontiguousarray(np.concatenate([np.asarray(s, dtype=np.int32) for s in shot_lists]))
+        dp = (ctypes.c_void_p * n)(*[d.data_ptr() for d in dms])
+        op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        L.check(self._lib.mp_apply_H_batch(self._ctx, n, counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                           shots.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), dp, op,
+                                           _stream(stream)))
+        self._keep = dms                     # inputs must outlive the enqueued work
+        return outs
 
     def release_cache(self):
         L.check(self._lib.mp_release_cache(self._ctx))
