@@ -99,6 +99,62 @@ def traffic_for(kind, w):
 KIND_OF_MODE = {"0": "fused", "1": "born", "2": "background", "3": "adjoint"}
 
 
+def serve_leg(seconds, rate=20.0, seed=13):
+    """Serving workload: seeded Poisson arrivals (rate req/s) of apply_H requests
+    on the grids {256x128, 512x256, 1024x512} (steps 48/96/192) with 16/32/64
+    shots, FP32 fields and BF16 checkpoints every 4 steps.  Reports latency
+    percentiles under the offered load, and the throughput of the same requests
+    submitted at once through the continuous-batching server ("served") versus
+    one request at a time on one stream ("plain")."""
+    import torch
+
+    import fixtures as F
+    from paper_1101_3615_amd.serve import GpuExecutor, Server, poisson_requests, summarize
+
+    shapes, groups = {}, {}
+    for (nx, nz), sd in zip(F.SERVE_SHAPES, (10, 11, 12)):
+        w, g = F.c4_union(nx, nz, sd)
+        shapes[(nx, nz)] = (w, F.medium(w))
+        groups[(nx, nz)] = g
+    ex = GpuExecutor(shapes, lanes_per_shape=2)
+
+    def make_dm(r):
+        w, c = shapes[r.shape]
+        return torch.from_numpy(F.wavepackets(w, c, 1000 + r.rid, max(1, w.model_cells // 4096))).cuda()
+
+    reqs = poisson_requests(rate, seconds, groups, F.SERVE_SHOTS, seed=seed, make_dm=make_dm)
+    # warm every lane once (allocations, code objects) with a one-shot request
+    for lane in ex.lane_keys():
+        w, c = shapes[lane[0]]
+        dm = torch.from_numpy(F.wavepackets(w, c, 999, 1)).cuda()
+        ex.lanes[lane]["problem"].apply_H_batch([dm], [[0]])
+    torch.cuda.synchronize()
+    srv = Server(ex, max_batch_shots=512)
+    done = srv.run(reqs)
+    torch.cuda.synchronize()
+    load = summarize(done, warmup=min(1.0, 0.1 * seconds))
+    # capacity: all requests at t = 0, batched, versus one at a time
+    for r in reqs:
+        r.arrival, r.finished = 0.0, None
+    srv2 = Server(ex, max_batch_shots=512)
+    t0 = time.perf_counter()
+    srv2.run(reqs)
+    torch.cuda.synchronize()
+    t_served = time.perf_counter() - t0
+    cs = sum(r.cell_steps for r in reqs)
+    t0 = time.perf_counter()
+    for r in reqs:
+        ex.lanes[(r.shape, 0)]["problem"].apply_H_batch([r.dm], [r.shots])
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    return {"requests": len(reqs), "rate_per_s": rate, "seconds": seconds, "batches": srv.nbatches,
+            "p50_ms": round(1e3 * load["p50_s"], 3), "p99_ms": round(1e3 * load["p99_s"], 3),
+            "offered_gcell_steps_per_s": round(load["gcell_steps_per_s"], 3),
+            "served_capacity_gcell_steps_per_s": round(cs / t_served / 1e9, 3),
+            "plain_capacity_gcell_steps_per_s": round(cs / t_plain / 1e9, 3),
+            "served_vs_plain": round(t_plain / t_served, 3)}
+
+
 def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, workload):
     """profiles/traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
     this benchmark and of the copy probe: per sweep kernel, HBM bytes per launch =
@@ -153,6 +209,8 @@ def main():
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--cpu-workers", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the Poisson serving run (0: skip the serving leg)")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/traffic.json from rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
@@ -220,6 +278,8 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = P.stats()
+    P.release_cache()
+    serving = serve_leg(args.serve_seconds) if (args.serve_seconds > 0 and not args.profile_steps) else None
     ms_per_step = 1e3 * wall / args.steps
     cell_steps = len(ys) * w.cell_steps
     value = cell_steps / (wall / args.steps) / 1e9
@@ -257,6 +317,7 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": kind,
                      "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 3)},
         "cpu_baseline": cpu,
+        "serving": serving,
         "sweeps": sweeps,
         "profile_run": bool(args.profile_steps),
         "fit_relres": relres,

@@ -173,7 +173,11 @@ class EngineT final : public Engine {
       set_error("budget too small for one shot of the sweep");
       return MP_ENOMEM;
     }
-    const int nw = (nb + wmax - 1) / wmax;
+    // MP_MAX_WAVE caps the shots per wave (tuning: a smaller wave keeps the
+    // per-step working set inside the on-die Infinity Cache)
+    int cap = wmax;
+    if (const char* mw = getenv("MP_MAX_WAVE")) cap = std::max(1, std::min(cap, atoi(mw)));
+    const int nw = (nb + cap - 1) / cap;
     const int w = (nb + nw - 1) / nw;
     int rc;
     if ((rc = data_.ensure(sizeof(T) * (size_t)nb * cfg_.nt * cfg_.nr, budget_, "data"))) return rc;

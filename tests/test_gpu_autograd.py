@@ -33,12 +33,13 @@ def _c3_slice(snap, nshots=8):
     return w.with_(src=w.src[sel], snap=snap)
 
 
-@pytest.mark.parametrize("snap,tol", [("ckpt_f32", 1e-3), ("ckpt_bf16", 2e-2)])
+@pytest.mark.parametrize("snap,tol", [("ckpt_f32", 1e-3), ("ckpt_bf16", 1e-2)])
 def test_c3_slice_dot_product_and_finite_differences(snap, tol):
     """1024 x 512, 4000 steps, snapshots every 4 steps (8 of the 128 shots):
     dot-product test and central differences of L = 1/2 ||F dm - d_obs||^2 along
-    32 seeded directions (L is quadratic, so the central difference is exact up to
-    rounding); tolerance FP32 checkpoints 1e-3, BF16 checkpoints 2e-2."""
+    32 seeded wavepacket directions (L is quadratic, so the central difference is
+    exact up to rounding); tolerance FP32 checkpoints 1e-3, BF16 checkpoints 1e-2
+    (median over directions)."""
     M, born = _gpu()
     w = _c3_slice(snap)
     c = F.medium(w)
@@ -54,9 +55,11 @@ def test_c3_slice_dot_product_and_finite_differences(snap, tol):
     loss.backward()
     grad = x.grad.double()
 
-    # dot-product test <F m, d> = <m, F* d>
-    m = torch.from_numpy(F.normal_field(w.model_shape, 8)).cuda()
-    dd = torch.from_numpy(F.normal_field((w.ns, w.nt, w.nr), 9)).cuda()
+    # dot-product test <F m, d> = <m, F* d> with band-limited vectors: m a wavepacket
+    # sum, d the Born data of another one (with BF16 checkpoints F* is approximate,
+    # and white-noise vectors would weigh the grid-scale part the rounding perturbs)
+    m = torch.from_numpy(F.wavepackets(w, c, 8, 64)).cuda()
+    dd = P.apply_F(torch.from_numpy(F.wavepackets(w, c, 9, 64)).cuda()).clone()
     lhs = float((P.apply_F(m).double() * dd.double()).sum())
     rhs = float((m.double() * P.apply_Fadj(dd).double()).sum())
     dot_err = abs(lhs - rhs) / abs(lhs)
@@ -68,7 +71,7 @@ def test_c3_slice_dot_product_and_finite_differences(snap, tol):
 
     errs = []
     for i in range(32):
-        v = torch.from_numpy(F.normal_field(w.model_shape, 100 + i)).cuda() * float(refl.abs().max())
+        v = torch.from_numpy(F.wavepackets(w, c, 100 + i, 64)).cuda() * float(refl.abs().max())
         eps = 1.0
         fd = (L(dm0 + eps * v) - L(dm0 - eps * v)) / (2 * eps)
         an = float((grad * v.double()).sum())
