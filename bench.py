@@ -59,24 +59,28 @@ def cpu_baseline(nsteps, workers):
                       f"FP64 numpy, one process per shot, slowest worker {wall:.1f} s"}
 
 
-def kernel_bytes(kind, w):
-    """Algorithmic HBM bytes of one launch (one time step over all shots) of a sweep kernel.
+def kernel_bytes(kind, w, s=2):
+    """Algorithmic HBM bytes of one launch of a 2D sweep kernel that takes s time
+    steps (1 or 2) for every shot of the workload (FP32 fields, FP64 image).
 
-    Streaming model per propagation cell-step and shot (FP32): fused forward
-    reads u, u-, du, du-, kappa, dm and writes u+, du+ (32 B) and writes g on
-    the model cells (4 B); the Born-only forward reads du, du-, kappa, dm and
-    writes du+ (20 B) and reads g (4 B per model cell); the background-only
-    sweep moves 16 B plus the g write; the adjoint reads nu, nu-, kappa and
-    writes nu+ (16 B) and, per model cell, reads g (4 B) and updates the FP64
-    image (16 B).
+    Per shot, a launch reads its two input levels and writes its outputs once on
+    the propagation grid, and touches the g store and image on the model grid:
+      background: reads u, D and writes u, D (16 B per cell); writes g of each
+                  step (4 B per model cell and step);
+      Born:       reads du^n, du^{n-1} (8 B per cell), writes s levels (4 B
+                  each); reads g of each step (4 B per model cell and step);
+      adjoint:    as Born for the field and g, plus one read-modify-write of the
+                  FP64 image (16 B per model cell).
+    Shared by all shots and counted once per launch: kappa (4 B per cell) and,
+    for the Born kernel, the extended perturbation (4 B per cell).
     """
-    s = 4
+    e = 4
     prop, model, ns = w.prop_cells, w.model_cells, w.ns
-    per = {"fused": 8 * s * prop + s * model,
-           "born": 5 * s * prop + s * model,
-           "background": 4 * s * prop + s * model,
-           "adjoint": 4 * s * prop + (s + 16) * model}[kind]
-    return per * ns
+    per = {"background": 4 * e * prop + s * e * model,
+           "born": 2 * e * prop + s * e * prop + s * e * model,
+           "adjoint": 2 * e * prop + s * e * prop + s * e * model + 16 * model}[kind]
+    shared = e * prop * (2 if kind == "born" else 1)
+    return per * ns + shared
 
 
 def traffic_for(kind, w):
@@ -179,10 +183,10 @@ def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_m
     fe, wr = means(fetch_dir), means(write_dir)
     kernels = {}
     for name in fe:
-        m = re.search(r"k_step(\d)d<float, (\d), (\d)>", name)
-        if not m or name not in wr:
+        m = re.search(r"k_sweep2d<float, (\d), (\d), (\d)>", name)
+        if not m or name not in wr or m.group(2) != "2":
             continue
-        kind = KIND_OF_MODE[m.group(2)]
+        kind = KIND_OF_MODE[m.group(1)]
         kernels[kind] = {"kernel": name, "fetch_kib_raw": fe[name], "write_kib_raw": wr[name],
                          "bytes_per_launch": fe[name] * 1024.0 * f_fac + wr[name] * 1024.0 * w_fac}
     src = os.path.join(ROOT, "paper_1101_3615_amd", "csrc", "wave2d.hip")
@@ -285,17 +289,23 @@ def main():
     value = cell_steps / (wall / args.steps) / 1e9
 
     # dominant kernel: the sweep kind with the most device time in the timed region
+    def per_launch(k):
+        n = st["launches_sweep"][k]
+        return (st["ms_sweep"][k] / 1e3 / n, st["steps_sweep"][k] / n) if n else (None, None)
+
     kind = max(st["ms_sweep"], key=lambda k: st["ms_sweep"][k])
-    launches = st["launches_sweep"][kind]
-    avg_s = st["ms_sweep"][kind] / 1e3 / max(launches, 1)
-    alg = kernel_bytes(kind, w)
+    avg_s, spl = per_launch(kind)
+    alg = kernel_bytes(kind, w, round(spl))
     achieved = alg / avg_s / 1e9
     traffic = traffic_for(kind, w)
-    sweeps = {k: {"ms": round(st["ms_sweep"][k], 3), "launches": st["launches_sweep"][k],
-                  "us_per_launch": round(1e3 * st["ms_sweep"][k] / max(st["launches_sweep"][k], 1), 3),
-                  "alg_GBs": round(kernel_bytes(k, w) / (st["ms_sweep"][k] / 1e3 / max(st["launches_sweep"][k], 1)) / 1e9, 1)
-                  if st["launches_sweep"][k] else None}
-              for k in st["ms_sweep"]}
+    sweeps = {}
+    for k in st["ms_sweep"]:
+        t, sl = per_launch(k)
+        if t is None:
+            continue
+        sweeps[k] = {"ms": round(st["ms_sweep"][k], 3), "launches": st["launches_sweep"][k],
+                     "steps_per_launch": round(sl, 3), "us_per_launch": round(1e6 * t, 3),
+                     "alg_GBs": round(kernel_bytes(k, w, round(sl)) / t / 1e9, 1)}
     line = {
         "metric": "Gcell-steps/s for H=F*F (fraction of HBM roofline); served p50/p99 latency",
         "value": round(value, 3),
@@ -315,7 +325,8 @@ def main():
                    "apply_H_cell_steps_per_step": cell_steps},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": kind,
-                     "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 3)},
+                     "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 3),
+                     "steps_per_launch": round(spl, 3)},
         "cpu_baseline": cpu,
         "serving": serving,
         "sweeps": sweeps,

@@ -107,7 +107,7 @@ typedef struct mp_opts {
   int timing;          /* 1: record HIP events around every sweep (read by mp_last_stats) */
 } mp_opts;
 
-#define MP_SWEEP_FUSED 0       /* forward: background and Born fields together */
+#define MP_SWEEP_FUSED 0       /* forward: background and Born fields together (3D) */
 #define MP_SWEEP_BORN 1        /* forward: Born field from the resident background */
 #define MP_SWEEP_BACKGROUND 2  /* forward: background field only (store or recompute) */
 #define MP_SWEEP_ADJOINT 3     /* reverse: adjoint field and imaging */
@@ -119,9 +119,11 @@ typedef struct mp_stats {
   size_t bytes_reserved;  /* device memory the context holds */
   /* with mp_opts.timing: device time of the sweeps enqueued since the previous
    * mp_last_stats call, per sweep kind MP_SWEEP_*, from HIP events recorded on
-   * the calls' streams around each sweep (one kernel launch per time step) */
+   * the calls' streams around each sweep; kernel launches and time steps they
+   * covered (2D sweeps take two steps per launch, 3D sweeps one) */
   double ms_sweep[4];
   long long launches_sweep[4];
+  long long steps_sweep[4];
 } mp_stats;
 
 /* Create a context for one grid and acquisition.  Validates every index and

@@ -56,7 +56,8 @@ class Opts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("cell_steps", ctypes.c_double), ("waves", ctypes.c_int),
                 ("background_cached", ctypes.c_int), ("bytes_reserved", ctypes.c_size_t),
-                ("ms_sweep", ctypes.c_double * 4), ("launches_sweep", ctypes.c_longlong * 4)]
+                ("ms_sweep", ctypes.c_double * 4), ("launches_sweep", ctypes.c_longlong * 4),
+                ("steps_sweep", ctypes.c_longlong * 4)]
 
 
 class BasisDesc(ctypes.Structure):

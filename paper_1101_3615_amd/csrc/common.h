@@ -10,17 +10,17 @@ namespace mp {
 // Field layout on the propagation grid (2D slice per shot, 3D volume per shot):
 //   element (x, z) of a 2D field lives at  base + SLACK + (z + GZ) * pitch + (x + XL)
 // The GZ ghost rows above and below, the XL left columns and the columns past
-// nxp are never written and stay zero, so the 8th-order stencil can read a
-// radius of 4 cells around every propagation cell without bounds checks; the
-// SLACK elements in front of and behind every slice cover the 4-column halo
-// read of the first and last ghost rows.
+// nxp are never written and stay zero, so a stencil may read a radius of 4
+// cells around every propagation cell; the SLACK elements in front of and
+// behind every slice cover the 4-column halo read of the first and last ghost
+// rows.  (The 3D sweeps rely on this; the 2D sweeps skip reads outside the grid.)
 constexpr int XL = 4;
 constexpr int GZ = 4;
 constexpr int GY = 4;            // ghost rows in y (3D)
 constexpr int SLACK = 64;
 constexpr int LANES = 64;        // wavefront size on gfx950
-constexpr int CPL = 4;           // cells per lane along x
-constexpr int STRIP = LANES * CPL;
+constexpr int HL2 = 4;           // 2D sweeps: halo lanes at each end of a strip
+constexpr int SW2 = 2 * (LANES - 2 * HL2);   // 2D sweeps: output cells per strip (2 per lane)
 
 template <typename T>
 struct alignas(4 * sizeof(T)) V4 {

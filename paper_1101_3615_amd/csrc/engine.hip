@@ -1,8 +1,9 @@
 // Operator engine (2D and 3D): memory plan, shot waves, forward / reverse sweeps.
 //
-// Per shot the sweeps keep four field slices (background u and Born / adjoint
-// field, two time levels each; the leapfrog writes level n+1 over level n-1),
-// the g = c^2 (L u + f) store on the model grid, and an FP64 image.  Shots that
+// Per shot the sweeps keep the field slices of the background u and of the
+// Born / adjoint field (2D: input and output levels of launches that take two
+// time steps; 3D: two levels stepped in place), the g = c^2 (L u + f) store on
+// the model grid, and an FP64 image.  Shots that
 // do not fit the budget together are processed in waves; images of every shot
 // are kept and stacked in shot order at the end, so the result does not depend
 // on how shots were grouped.  When all shots fit, the g store of the last
@@ -55,8 +56,10 @@ class EngineT final : public Engine {
     L_.nyp = (c.ndim == 3) ? c.ny + 2 * c.nb : 1;
     L_.nzp = c.nz + 2 * c.nb;
     if (c.ndim == 2) {
-      L_.nstrips = (int)((L_.nxp + XL + STRIP - 1) / STRIP);
-      L_.pitch = L_.nstrips * STRIP;
+      // strips of SW2 output cells; the row pitch covers every lane of every
+      // strip (8 halo cells on either side), so the sweeps load rows unmasked
+      L_.nstrips = (L_.nxp + SW2 - 1) / SW2;
+      L_.pitch = (int)round_up(XL + (long long)L_.nstrips * SW2 + 2 * HL2 + 4, 16);
       L_.nytiles = 1;
       L_.ypitch = 1;
     } else {
@@ -108,6 +111,13 @@ class EngineT final : public Engine {
     hsx_ = sx;
     hsy_ = sy;
     hsz_ = sz;
+    rec_lo_ = L_.nzp;
+    rec_hi_ = -1;
+    for (int z = 0; z < L_.nzp; ++z)
+      if (recplane[z] >= 0) {
+        rec_lo_ = std::min(rec_lo_, z);
+        rec_hi_ = std::max(rec_hi_, z);
+      }
     int rc;
     if ((rc = wav_.ensure(sizeof(T) * c.nt, budget_, "wavelet"))) return rc;
     if ((rc = recplane_.ensure(sizeof(int) * L_.nzp, budget_, "receivers"))) return rc;
@@ -116,6 +126,10 @@ class EngineT final : public Engine {
     if ((rc = etax_.ensure(sizeof(T) * L_.nxp, budget_, "sponge"))) return rc;
     if ((rc = etay_.ensure(sizeof(T) * L_.nyp, budget_, "sponge"))) return rc;
     if ((rc = etaz_.ensure(sizeof(T) * L_.nzp, budget_, "sponge"))) return rc;
+    if (c.ndim == 2) {
+      if ((rc = damp_.ensure(sizeof(T) * 2 * L_.fstride, budget_, "sponge"))) return rc;
+      MP_HIP(hipMemset(damp_.get(), 0, sizeof(T) * 2 * L_.fstride));
+    }
     if ((rc = small_.ensure(64, budget_, "scratch"))) return rc;
     MP_HIP(hipMemcpy(wav_.get(), wt.data(), sizeof(T) * c.nt, hipMemcpyHostToDevice));
     MP_HIP(hipMemcpy(recplane_.get(), recplane.data(), sizeof(int) * L_.nzp, hipMemcpyHostToDevice));
@@ -135,8 +149,11 @@ class EngineT final : public Engine {
   size_t ck_elem() const { return cfg_.snap == MP_SNAP_CKPT_BF16 ? 2 : sizeof(T); }
   // g slots per shot: every step (full history) or one checkpoint segment
   long long g_slots() const { return ckpt_mode() ? std::min(cfg_.ckpt_every, cfg_.nt) : cfg_.nt; }
+  // field slices per shot: 2D keeps input and output levels of the background and
+  // of the Born / adjoint field (4 + 4); 3D steps them in place (5)
+  int nslices() const { return cfg_.ndim == 2 ? 8 : 5; }
   size_t per_shot_bytes() const {
-    size_t b = sizeof(T) * (size_t)(5 * L_.fstride + g_slots() * L_.mstride);
+    size_t b = sizeof(T) * (size_t)(nslices() * L_.fstride + g_slots() * L_.mstride);
     if (ckpt_mode()) b += (size_t)nck() * 2 * (ck_elem() * (size_t)cstride_ + sizeof(float));
     return b;
   }
@@ -184,7 +201,7 @@ class EngineT final : public Engine {
     if ((rc = img_.ensure(sizeof(double) * (size_t)nb * L_.mstride, budget_, "images"))) return rc;
     if ((rc = dmbar_.ensure(sizeof(T) * (size_t)nslots * L_.fstride, budget_, "dm"))) return rc;
     if ((rc = jtab_.ensure(4 * sizeof(int) * (size_t)nb, budget_, "job tables"))) return rc;
-    if ((rc = fields_.ensure(sizeof(T) * 5 * (size_t)w * L_.fstride, budget_, "fields"))) return rc;
+    if ((rc = fields_.ensure(sizeof(T) * nslices() * (size_t)w * L_.fstride, budget_, "fields"))) return rc;
     if ((rc = hist_.ensure(sizeof(T) * (size_t)w * g_slots() * L_.mstride, budget_, "g store"))) return rc;
     if (ckpt_mode()) {
       if ((rc = ck_.ensure(ck_elem() * (size_t)w * nck() * 2 * cstride_, budget_, "checkpoints"))) return rc;
@@ -235,6 +252,7 @@ class EngineT final : public Engine {
     p.etax = etax_.as<T>();
     p.etay = etay_.as<T>();
     p.etaz = etaz_.as<T>();
+    p.damp = damp_.as<T>();
     p.dmbar = dmbar_.as<T>();
     const int* jt = jtab_.as<int>();
     p.srcx = jt;
@@ -244,30 +262,21 @@ class EngineT final : public Engine {
     p.wav = wav_.as<T>();
     p.recplane = recplane_.as<int>();
     p.recmap = recmap_.as<int>();
+    p.rec_lo = rec_lo_;
+    p.rec_hi = rec_hi_;
     p.nr = cfg_.nr;
     p.nt = cfg_.nt;
     p.shot0 = s0;
-    int zc = zc_target_;
-    if (cfg_.ndim == 2) {
-      // one wavefront per z chunk of a 256-cell strip, four chunks per workgroup
-      if (zc <= 0) {
-        const long long per_row = (long long)nsh * L_.nstrips;
-        zc = (int)std::max<long long>(8, std::min<long long>(64, (long long)L_.nzp * per_row / 4096));
-      }
-      const int ngroups = std::max(1, (int)((L_.nzp + 4LL * zc - 1) / (4LL * zc)));
-      p.ngroups = ngroups;
-      p.zc = (L_.nzp + 4 * ngroups - 1) / (4 * ngroups);
-      p.nchunks = (L_.nzp + p.zc - 1) / p.zc;
-      p.nwg = nsh * L_.nstrips * ngroups;
-    } else {
+    if (cfg_.ndim == 3) {
       // one workgroup per 64 x 16 tile and z chunk
+      int zc = zc_target_;
       const long long tiles = (long long)nsh * L_.nstrips * L_.nytiles;
       if (zc <= 0) zc = (int)std::max<long long>(8, std::min<long long>(64, (long long)L_.nzp * tiles / 2048));
       p.nchunks = (L_.nzp + zc - 1) / zc;
       p.zc = (L_.nzp + p.nchunks - 1) / p.nchunks;
       p.ngroups = 1;
       p.nwg = (int)(tiles * p.nchunks);
-    }
+    }   // 2D: the launcher picks the z chunking per kernel
     T* f = fields_.as<T>();
     const long long fs = (long long)W * L_.fstride;
     p.u_cur = f;
@@ -275,6 +284,7 @@ class EngineT final : public Engine {
     p.u_inc = f + 2 * fs;
     p.du_cur = f + 3 * fs;
     p.du_prev = f + 4 * fs;
+    p.in0 = p.in1 = p.out0 = p.out1 = nullptr;
     p.hist = hist_.as<T>();
     p.data = data_.as<T>();
     p.img = img_.as<double>();
@@ -288,8 +298,7 @@ class EngineT final : public Engine {
   }
 
   void step(int mode, const Step<T>& p, int n, int hslot, int ck, int cs, int cm) {
-    if (cfg_.ndim == 2) step2d(mode, p, n, hslot, ck, cs, cm, stream_);
-    else step3d(mode, p, n, hslot, ck, cs, cm, stream_);
+    step3d(mode, p, n, hslot, ck, cs, cm, stream_);
   }
 
   // ---- background ----
@@ -328,9 +337,20 @@ class EngineT final : public Engine {
     Pad pd = pad();
     kappa(kappa_.as<T>(), c, pd, cfg_.dt, s);
     MP_CHECK_LAUNCH();
+    if (cfg_.ndim == 2) {
+      damping2d(damp_.as<T>(), etax_.as<T>(), etaz_.as<T>(), pd, cfg_.dt, s);
+      MP_CHECK_LAUNCH();
+    }
     MP_HIP(hipStreamSynchronize(s));   // host tables above must outlive the copies
     cached_ = false;
     return MP_OK;
+  }
+
+  // perturbation slot k <- E dm, ghost cells zero
+  void put_dm(int k, const void* dm, hipStream_t s) {
+    T* dst = dmbar_.as<T>() + (long long)k * L_.fstride;
+    fill(dst, L_.fstride, T(0), s);
+    extend(dst, static_cast<const T*>(dm), pad(), s);
   }
 
   Pad pad() const {
@@ -349,7 +369,7 @@ class EngineT final : public Engine {
   // ---- sweeps ----
   int zero_fields(int W, bool both) {
     (void)both;
-    fill(fields_.as<T>(), 5LL * W * L_.fstride, T(0), stream_);
+    fill(fields_.as<T>(), (long long)nslices() * W * L_.fstride, T(0), stream_);
     MP_CHECK_LAUNCH();
     return MP_OK;
   }
@@ -359,13 +379,14 @@ class EngineT final : public Engine {
     hipEvent_t a = nullptr, b = nullptr;
     int kind = 0;
     long long launches = 0;
+    long long steps = 0;
   };
   std::vector<Span> spans_;
   size_t nspans_ = 0;
 
-  int span_begin(int kind, long long launches, Span** out) {
+  int span_begin(int kind, long long launches, Span** out, long long steps = -1) {
     *out = nullptr;
-    if (!cfg_.timing || nspans_ >= 4096) return MP_OK;   // bounded until the next collection
+    if (!cfg_.timing || nspans_ >= 16384) return MP_OK;   // bounded until the next collection
     if (nspans_ == spans_.size()) {
       Span sp;
       MP_HIP(hipEventCreate(&sp.a));
@@ -375,6 +396,7 @@ class EngineT final : public Engine {
     Span* sp = &spans_[nspans_++];
     sp->kind = kind;
     sp->launches = launches;
+    sp->steps = steps < 0 ? launches : steps;
     MP_HIP(hipEventRecord(sp->a, stream_));
     *out = sp;
     return MP_OK;
@@ -388,6 +410,7 @@ class EngineT final : public Engine {
     for (int k = 0; k < 4; ++k) {
       stats.ms_sweep[k] = 0.0;
       stats.launches_sweep[k] = 0;
+      stats.steps_sweep[k] = 0;
     }
     for (size_t i = 0; i < nspans_; ++i) {
       MP_HIP(hipEventSynchronize(spans_[i].b));
@@ -395,6 +418,7 @@ class EngineT final : public Engine {
       MP_HIP(hipEventElapsedTime(&ms, spans_[i].a, spans_[i].b));
       stats.ms_sweep[spans_[i].kind] += ms;
       stats.launches_sweep[spans_[i].kind] += spans_[i].launches;
+      stats.steps_sweep[spans_[i].kind] += spans_[i].steps;
     }
     nspans_ = 0;
     return MP_OK;
@@ -412,10 +436,148 @@ class EngineT final : public Engine {
     if (jhost_) (void)hipHostFree(jhost_);
   }
 
+  // ---- 2D sweeps: up to two time steps per launch ----
+  // Buffer roles rotate between launches: the background keeps (u, D) in and
+  // out; the Born / adjoint field keeps (level 0, level -1) in and two output
+  // levels.
+  struct Rot2 {
+    T* bg[4];   // u in, D in, u out, D out
+    T* wf[4];   // level 0, level -1, level 1 out, level 2 out
+  };
+  Rot2 rot2(int W) {
+    T* f = fields_.as<T>();
+    const long long fs = (long long)W * L_.fstride;
+    Rot2 r;
+    for (int i = 0; i < 4; ++i) {
+      r.bg[i] = f + i * fs;
+      r.wf[i] = f + (4 + i) * fs;
+    }
+    return r;
+  }
+  void launch_bg(Step<T>& p, Rot2& r, int nsh, int ns, int ck, int n, int hs1, int hs2, int cs, int cm) {
+    p.in0 = r.bg[0];
+    p.in1 = r.bg[1];
+    p.out0 = r.bg[2];
+    p.out1 = r.bg[3];
+    sweep2d(M_BG, ns, ck, p, nsh, n, hs1, hs2, cs, cm, zc_target_, stream_);
+    std::swap(r.bg[0], r.bg[2]);
+    std::swap(r.bg[1], r.bg[3]);
+  }
+  void launch_wf(int mode, Step<T>& p, Rot2& r, int nsh, int ns, int n, int hs1, int hs2) {
+    p.in0 = r.wf[0];
+    p.in1 = r.wf[1];
+    p.out0 = r.wf[2];
+    p.out1 = r.wf[3];
+    sweep2d(mode, ns, CK_NONE, p, nsh, n, hs1, hs2, -1, -1, zc_target_, stream_);
+    T* w[4] = {r.wf[0], r.wf[1], r.wf[2], r.wf[3]};
+    if (ns == 2) {   // next: level 0 <- level 2, level -1 <- level 1
+      r.wf[0] = w[3]; r.wf[1] = w[2]; r.wf[2] = w[0]; r.wf[3] = w[1];
+    } else {         // next: level 0 <- level 1, level -1 <- level 0
+      r.wf[0] = w[2]; r.wf[1] = w[0]; r.wf[2] = w[1]; r.wf[3] = w[3];
+    }
+  }
+
+  // Forward sweep of shots [s0, s0+nsh) in segments (the checkpoint interval, or
+  // all nt steps): the background over the segment (g into the segment's slots,
+  // checkpoint of the segment's first level), then the Born field over it.
+  // mode 0: background + Born, 1: Born from the stored g, 2: background only.
+  int forward2d(int mode, int s0, int nsh, int W, T* data) {
+    int rc;
+    if ((rc = zero_fields(W, true))) return rc;
+    Step<T> p = params(s0, nsh, W);
+    p.data = data;
+    Rot2 r = rot2(W);
+    const int ck = ck_kind();
+    if (ck == CK_BF16 && mode != 1) {
+      fill(cks_.as<float>(), (long long)nsh * nck() * 2, 0.0f, stream_);
+      MP_CHECK_LAUNCH();
+    }
+    const int kk = ckpt_mode() ? cfg_.ckpt_every : cfg_.nt;
+    const bool keep_g = !(mode == 2 && ckpt_mode());   // g is only needed by a Born sweep or the cache
+    for (int n0 = 0; n0 < cfg_.nt; n0 += kk) {
+      const int len = std::min(kk, cfg_.nt - n0);
+      const int j = n0 / kk;
+      const int base = ckpt_mode() ? n0 : 0;   // g slot of step n is n - base
+      Span* sp;
+      if (mode != 1) {
+        if ((rc = span_begin(MP_SWEEP_BACKGROUND, (len + 1) / 2, &sp, len))) return rc;
+        for (int n = n0; n < n0 + len;) {
+          const int ns = std::min(2, n0 + len - n);
+          const int cs = (ck != CK_NONE && n == n0) ? j : -1;
+          const int cm = (ck == CK_BF16 && n + ns == n0 + len && j + 1 < nck()) ? j + 1 : -1;
+          const int hs1 = keep_g ? n - base : -1;
+          const int hs2 = (keep_g && ns == 2) ? n + 1 - base : -1;
+          launch_bg(p, r, nsh, ns, ck, n, hs1, hs2, cs, cm);
+          n += ns;
+        }
+        if ((rc = span_end(sp))) return rc;
+      }
+      if (mode != 2) {
+        if ((rc = span_begin(MP_SWEEP_BORN, (len + 1) / 2, &sp, len))) return rc;
+        for (int n = n0; n < n0 + len;) {
+          const int ns = std::min(2, n0 + len - n);
+          launch_wf(M_BORN, p, r, nsh, ns, n, n - base, ns == 2 ? n + 1 - base : -1);
+          n += ns;
+        }
+        if ((rc = span_end(sp))) return rc;
+      }
+    }
+    MP_CHECK_LAUNCH();
+    return MP_OK;
+  }
+
+  int adjoint2d(int s0, int nsh, int W, const T* data) {
+    int rc;
+    if ((rc = zero_fields(W, false))) return rc;
+    fill(img_.as<double>() + (long long)s0 * L_.mstride, (long long)nsh * L_.mstride, 0.0, stream_);
+    Step<T> p = params(s0, nsh, W);
+    p.data = const_cast<T*>(data);
+    Rot2 r = rot2(W);
+    Span* sp;
+    if (!ckpt_mode()) {
+      if ((rc = span_begin(MP_SWEEP_ADJOINT, (cfg_.nt + 1) / 2, &sp, cfg_.nt))) return rc;
+      for (int k = cfg_.nt; k >= 1;) {
+        const int ns = k >= 2 ? 2 : 1;
+        launch_wf(M_ADJ, p, r, nsh, ns, k, k - 1, ns == 2 ? k - 2 : -1);
+        k -= ns;
+      }
+      MP_CHECK_LAUNCH();
+      return span_end(sp);
+    }
+    // checkpoint modes: per segment (last first) recompute g from the checkpoint,
+    // then run the adjoint down through the segment
+    const int kk = cfg_.ckpt_every;
+    const int ck = ck_kind();
+    for (int j = nck() - 1; j >= 0; --j) {
+      const int n0 = j * kk;
+      const int len = std::min(kk, cfg_.nt - n0);
+      if ((rc = span_begin(MP_SWEEP_BACKGROUND, (len + 1) / 2, &sp, len))) return rc;
+      p.u_cur = r.bg[0];
+      p.u_inc = r.bg[1];
+      expand(p, nsh, ck, j, stream_);
+      for (int n = n0; n < n0 + len;) {
+        const int ns = std::min(2, n0 + len - n);
+        launch_bg(p, r, nsh, ns, CK_NONE, n, n - n0, ns == 2 ? n + 1 - n0 : -1, -1, -1);
+        n += ns;
+      }
+      if ((rc = span_end(sp))) return rc;
+      if ((rc = span_begin(MP_SWEEP_ADJOINT, (len + 1) / 2, &sp, len))) return rc;
+      for (int k = n0 + len; k >= n0 + 1;) {
+        const int ns = (k - n0 >= 2) ? 2 : 1;
+        launch_wf(M_ADJ, p, r, nsh, ns, k, k - 1 - n0, ns == 2 ? k - 2 - n0 : -1);
+        k -= ns;
+      }
+      if ((rc = span_end(sp))) return rc;
+    }
+    MP_CHECK_LAUNCH();
+    return MP_OK;
+  }
+
   // forward sweep of shots [s0, s0+nsh): mode 0 fused, 1 Born from stored g, 2 background only.
   // In the checkpoint modes the background levels are stored every ckpt_every steps
   // instead of g.
   int forward(int mode, int s0, int nsh, int W, T* data) {
+    if (cfg_.ndim == 2) return forward2d(mode, s0, nsh, W, data);
     int rc;
     if ((rc = zero_fields(W, true))) return rc;
     Step<T> p = params(s0, nsh, W);
@@ -445,6 +607,7 @@ class EngineT final : public Engine {
   }
 
   int adjoint(int s0, int nsh, int W, const T* data) {
+    if (cfg_.ndim == 2) return adjoint2d(s0, nsh, W, data);
     int rc;
     if ((rc = zero_fields(W, false))) return rc;
     fill(img_.as<double>() + (long long)s0 * L_.mstride, (long long)nsh * L_.mstride, 0.0, stream_);
@@ -505,7 +668,7 @@ class EngineT final : public Engine {
     stream_ = s;
     int W, rc;
     if ((rc = plain_job(&W))) return rc;
-    extend(dmbar_.as<T>(), static_cast<const T*>(dm), pad(), s);
+    put_dm(0, dm, s);
     MP_CHECK_LAUNCH();
     // with checkpoints the Born field still needs g at every step: always fused
     const bool use_cache = cached_ && whole_ && !ckpt_mode();
@@ -542,7 +705,7 @@ class EngineT final : public Engine {
     stream_ = s;
     int W, rc;
     if ((rc = plain_job(&W))) return rc;
-    extend(dmbar_.as<T>(), static_cast<const T*>(dm), pad(), s);
+    put_dm(0, dm, s);
     MP_CHECK_LAUNCH();
     const bool use_cache = cached_ && whole_ && !ckpt_mode();
     int waves = 0;
@@ -577,7 +740,7 @@ class EngineT final : public Engine {
     if ((rc = plan(nb, nreq, &W))) return rc;
     if ((rc = upload_job(js, jslot))) return rc;
     for (int r = 0; r < nreq; ++r) {
-      extend(dmbar_.as<T>() + (long long)r * L_.fstride, static_cast<const T*>(dm[r]), pad(), s);
+      put_dm(r, dm[r], s);
       MP_CHECK_LAUNCH();
     }
     cached_ = false;     // the stores now hold this job's shots
@@ -620,8 +783,9 @@ class EngineT final : public Engine {
   bool cached_ = false;
   bool whole_ = false;
   hipStream_t stream_ = nullptr;
-  DevBuf wav_, recplane_, recmap_, kappa_, dmbar_, jtab_, etax_, etay_, etaz_, small_;
+  DevBuf wav_, recplane_, recmap_, kappa_, dmbar_, jtab_, etax_, etay_, etaz_, damp_, small_;
   std::vector<int> hsx_, hsy_, hsz_;
+  int rec_lo_ = 0, rec_hi_ = -1;
   int* jhost_ = nullptr;
   size_t jcap_ = 0;
   hipEvent_t jev_ = nullptr;

@@ -18,7 +18,7 @@ struct Layout {
   int mpitch;          // model-grid x pitch (multiple of 4)
   long long mplane;    // model elements per z plane (mpitch * ny)
   long long mstride;   // model elements per slice (mplane * nz)
-  int nstrips;         // 2D: 256-cell strips per row; 3D: 64-cell x tiles
+  int nstrips;         // 2D: 120-cell output strips per row; 3D: 64-cell x tiles
   int nytiles;         // 3D: 16-row y tiles (1 in 2D)
 };
 
@@ -32,6 +32,7 @@ struct Step {
   const T* etax;             // [nxp]
   const T* etay;             // [nyp]
   const T* etaz;             // [nzp]
+  const T* damp;             // 2D: (a, b) per cell, field layout with 2 values per element
   const T* dmbar;            // [slot][field layout]: zero-extended model perturbations
   const int* dm_slot;        // [shots of the job] perturbation slot of each shot
   const int* srcx;           // [shots of the job] propagation-grid source cell
@@ -40,9 +41,16 @@ struct Step {
   const T* wav;              // [nt] wavelet / h^ndim
   const int* recplane;       // [nzp] receiver map of the plane, or -1
   const int* recmap;         // [maps][nyp][cpitch]: receiver index or -1
+  int rec_lo, rec_hi;        // first and last z plane holding receivers (rec_lo > rec_hi: none)
   int nr, nt;
   int shot0;                 // job index of local shot 0 of this wave
   int zc, nchunks, ngroups, nwg;
+  // 2D sweeps (one or two steps per launch): inputs and outputs of the launch
+  T* in0;                    // background u^n / field level 0
+  T* in1;                    // background increment D^n / field level -1
+  T* out0;                   // background u^{n+NS} / field level 1
+  T* out1;                   // background D^{n+NS} / field level 2
+  // 3D sweeps (one step per launch) and checkpoint expansion
   T* u_cur;                  // background level n (read)
   T* u_next;                 // background level n+1 (written)
   T* u_inc;                  // background increment u^n - u^{n-1}, updated in place
@@ -66,13 +74,22 @@ enum { CK_NONE = 0, CK_F32 = 1, CK_BF16 = 2 };
 // Sweep kernels.
 enum { M_FUSED = 0, M_BORN = 1, M_BG = 2, M_ADJ = 3 };
 
-// One time step of every shot of a wave.  mode: M_*; n: step (adjoint: k);
+// 2D: nsteps (1 or 2) time steps of every shot of a wave in one launch.
+// mode: M_BG, M_BORN or M_ADJ; n: first step (adjoint: k, the first level
+// computed is nu^k); hs1, hs2: g slots of the two steps (written by M_BG, -1 for
+// none; read by M_BORN and M_ADJ); ck: CK_* encoding of M_BG; ck_store:
+// checkpoint written from the launch's input level (u^n, D^n) or -1; ck_max:
+// checkpoint whose BF16 scales take the maxima of the launch's last level or -1;
+// zc > 0 forces the z-chunk height.  nsh: shots in the wave.
+void sweep2d(int mode, int nsteps, int ck, const Step<float>& p, int nsh, int n, int hs1, int hs2, int ck_store,
+             int ck_max, int zc, hipStream_t s);
+void sweep2d(int mode, int nsteps, int ck, const Step<double>& p, int nsh, int n, int hs1, int hs2, int ck_store,
+             int ck_max, int zc, hipStream_t s);
+// 3D: one time step of every shot of a wave.  mode: M_*; n: step (adjoint: k);
 // hslot: g slot written (background modes) or read (Born, adjoint);
 // ck: CK_* encoding; ck_store: checkpoint written from (u^n, u^{n-1}) at this
 // step or -1; ck_max: checkpoint whose BF16 scales accumulate max |u^{n+1}| and
 // max |u^{n+1} - u^n| at this step or -1.
-void step2d(int mode, const Step<float>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
-void step2d(int mode, const Step<double>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
 void step3d(int mode, const Step<float>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
 void step3d(int mode, const Step<double>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
 // u_cur <- u^{jk}, u_inc <- u^{jk} - u^{jk-1} from checkpoint j for the wave's shots

@@ -1,44 +1,245 @@
-// 2D time-step kernels of the Born / reverse-time sweeps (gfx950).
+// 2D sweep kernels of the Born / reverse-time sweeps (gfx950): one or two time
+// steps per launch.
 //
-// One wavefront owns a strip of 256 cells along x (4 per lane, 16-byte loads)
-// and marches down a chunk of rows in z.  The 9 rows of the z-stencil sit in a
-// register queue, the x-neighbours come from the adjacent lanes through DPP
-// wavefront shifts, and the two lanes at the strip ends load the 4-cell halo.
-// No LDS and no barriers: the four waves of a workgroup are independent and
-// take consecutive z-chunks of the same strip, so their halo rows hit in L1/L2.
+// Decomposition.  A wavefront owns an x strip of 64 lanes x 2 cells and a chunk
+// of rows [z0, z1) in z.  Lanes 4..59 (SW2 = 112 cells) are the strip's output;
+// lanes 0-3 and 60-63 are an 8-cell x halo, enough for two steps of the
+// radius-4 stencil without loading any halo separately.  With two steps per
+// launch the wave computes the intermediate level on its chunk widened by 4 rows
+// above and below (from level-0 rows [z0-8, z1+8)), and level 2 on [z0, z1), so
+// it needs nothing that another wave computes; neighbouring chunks march in
+// opposite directions so that they read their shared rows at the same time.  Recomputed halo values come from
+// the same inputs through the same operations as in the wave that owns the cell
+// (the undamped interior form where that wave uses it too), and outputs go to
+// other buffers than the inputs, which neighbouring waves are still reading.
+//
+// Rows march in z through 9-row register queues (level 0 and level 1); x
+// neighbours come from adjacent lanes through DPP wavefront shifts.  No LDS and
+// no barriers: the four waves of a workgroup take consecutive chunks of one
+// strip, so their overlapping rows hit in L1/L2.  Row indices are uniform across
+// the wavefront.  Rows outside [0, nzp) are zero and never read; cells outside
+// [0, nxp) read as zero from the ghost columns and are never written.
 //
 // Scheme (damped leapfrog, 8th-order Laplacian, fields zero outside the grid):
-//   background  Lam = L u + f,  g = c^2 Lam,  u+ = a (2u + kappa Lam) - b u-
-//   Born        du+ = a (2 du + kappa (L du - dm g)) - b du-        (Sec. 2)
-//   adjoint     nu  = a (2 nu' + kappa (L nu' + R^T d)) - b nu''    (exact transpose)
-//   imaging     I  -= g^{k-1} nu^k                                   (FP64)
+//   background  Lam = L u + f,  g = c^2 Lam,  D+ = b D + a kappa Lam,  u+ = u + D+
+//               (u+ = a (2u + kappa Lam) - b u- written with the increment D = u - u-)
+//   Born        du+ = a (2 du + kappa (L du - dm g)) - b du-          (Sec. 2)
+//   adjoint     nu  = a (2 nu' + kappa (L nu' + R^T d)) - b nu''      (exact transpose)
+//   imaging     I  -= g^{k-1} nu^k                                    (FP64)
+#include <algorithm>
+
 #include "common.h"
 #include "wave.h"
 
 namespace mp {
 
-// 8th-order Laplacian of the 4 cells of a lane in difference form:
-// sum_j c_j [(u_{x-j} - u) + (u_{x+j} - u) + (u_{z-j} - u) + (u_{z+j} - u)], the
-// smallest weights first.  Algebraically equal to c0 u + sum_j c_j (pairs);
-// in FP32 it rounds relative to the differences instead of to u, which keeps
-// smooth, well-resolved fields accurate over thousands of steps.
 template <typename T>
-__device__ __forceinline__ void lap_diff(const T (&w)[12], const V4<T>* q, int r, const Step<T>& p, T out[4]) {
+struct alignas(2 * sizeof(T)) V2 {
+  T v[2];
+};
+template <typename T>
+__device__ __forceinline__ V2<T> ld2(const T* p) {
+  return *reinterpret_cast<const V2<T>*>(p);
+}
+template <typename T>
+__device__ __forceinline__ void st2(T* p, const V2<T>& v) {
+  *reinterpret_cast<V2<T>*>(p) = v;
+}
+template <typename T>
+__device__ __forceinline__ V2<T> zero2() {
+  V2<T> r;
+  r.v[0] = T(0);
+  r.v[1] = T(0);
+  return r;
+}
+
+// Buffer-resource access (raw buffers: byte offsets, a per-lane offset plus a
+// wave-uniform one, hardware range check against the resource's size; reads
+// past it return zero, writes past it are dropped).  Word 3 of the resource is
+// the gfx9-family raw-buffer configuration (32-bit data format).
+using Rsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ Rsrc rsrc(const void* base, long long bytes) {
+  const int n = bytes >= 0xffffffffLL ? -1 : (int)(unsigned)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
+}
+__device__ __forceinline__ V2<float> bld2(Rsrc r, unsigned vo, unsigned so, float) {
+  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+  V2<float> o;
+  o.v[0] = __uint_as_float(v.x);
+  o.v[1] = __uint_as_float(v.y);
+  return o;
+}
+__device__ __forceinline__ V2<double> bld2(Rsrc r, unsigned vo, unsigned so, double) {
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+  V2<double> o;
+  o.v[0] = __longlong_as_double(((long long)v.y << 32) | v.x);
+  o.v[1] = __longlong_as_double(((long long)v.w << 32) | v.z);
+  return o;
+}
+__device__ __forceinline__ void bst2(const V2<float>& a, Rsrc r, unsigned vo, unsigned so) {
+  u32x2 v;
+  v.x = __float_as_uint(a.v[0]);
+  v.y = __float_as_uint(a.v[1]);
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, 0);
+}
+__device__ __forceinline__ void bst2(const V2<double>& a, Rsrc r, unsigned vo, unsigned so) {
+  const long long b0 = __double_as_longlong(a.v[0]), b1 = __double_as_longlong(a.v[1]);
+  u32x4 v;
+  v.x = (unsigned)b0;
+  v.y = (unsigned)(b0 >> 32);
+  v.z = (unsigned)b1;
+  v.w = (unsigned)(b1 >> 32);
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, 0);
+}
+// (a, b) of the lane's two cells from the interleaved damping table
+__device__ __forceinline__ void bld_ab(Rsrc r, unsigned vo, unsigned so, float a[2], float b[2]) {
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+  a[0] = __uint_as_float(v.x);
+  b[0] = __uint_as_float(v.y);
+  a[1] = __uint_as_float(v.z);
+  b[1] = __uint_as_float(v.w);
+}
+__device__ __forceinline__ void bld_ab(Rsrc r, unsigned vo, unsigned so, double a[2], double b[2]) {
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+  const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, vo + 16, so, 0);
+  a[0] = __longlong_as_double(((long long)v.y << 32) | v.x);
+  b[0] = __longlong_as_double(((long long)v.w << 32) | v.z);
+  a[1] = __longlong_as_double(((long long)w.y << 32) | w.x);
+  b[1] = __longlong_as_double(((long long)w.w << 32) | w.z);
+}
+
+// Cells x-4 .. x+5 around the lane's pair (x, x+1): the pairs of lanes l-2, l-1,
+// l, l+1, l+2 (lanes past either end of the wavefront read zero; their results
+// are not used).
+template <typename T>
+__device__ __forceinline__ T mov_shr1(T v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+template <typename T>
+__device__ __forceinline__ T mov_shl1(T v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+template <>
+__device__ __forceinline__ double mov_shr1<double>(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <>
+__device__ __forceinline__ double mov_shl1<double>(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ void xnb(const V2<T>& C, T w[10]) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 2; ++i) {
+    const T l1 = mov_shr1(C.v[i]);
+    const T r1 = mov_shl1(C.v[i]);
+    w[i] = mov_shr1(l1);
+    w[2 + i] = l1;
+    w[4 + i] = C.v[i];
+    w[6 + i] = r1;
+    w[8 + i] = mov_shl1(r1);
+  }
+}
+
+// 8th-order Laplacian of the lane's two cells in difference form:
+// sum_j c_j [(u_{x-j} - u) + (u_{x+j} - u) + (u_{z-j} - u) + (u_{z+j} - u)], the
+// smallest weights first.  Algebraically c0 u + sum_j c_j (pairs); in FP32 it
+// rounds relative to the differences instead of to u, which keeps smooth,
+// well-resolved fields accurate over thousands of steps.  q[(rb + j) % 9] holds
+// row (centre - 4 + j).
+template <typename T>
+__device__ __forceinline__ void lap2(const T (&w)[10], const V2<T>* q, int rb, const Step<T>& p, T out[2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
     const T c = w[4 + i];
-    T s = p.c4 * (((w[0 + i] - c) + (w[8 + i] - c)) + ((q[(r + 0) % 9].v[i] - c) + (q[(r + 8) % 9].v[i] - c)));
-    s += p.c3 * (((w[1 + i] - c) + (w[7 + i] - c)) + ((q[(r + 1) % 9].v[i] - c) + (q[(r + 7) % 9].v[i] - c)));
-    s += p.c2 * (((w[2 + i] - c) + (w[6 + i] - c)) + ((q[(r + 2) % 9].v[i] - c) + (q[(r + 6) % 9].v[i] - c)));
-    s += p.c1 * (((w[3 + i] - c) + (w[5 + i] - c)) + ((q[(r + 3) % 9].v[i] - c) + (q[(r + 5) % 9].v[i] - c)));
+    T s = p.c4 * (((w[0 + i] - c) + (w[8 + i] - c)) + ((q[(rb + 0) % 9].v[i] - c) + (q[(rb + 8) % 9].v[i] - c)));
+    s += p.c3 * (((w[1 + i] - c) + (w[7 + i] - c)) + ((q[(rb + 1) % 9].v[i] - c) + (q[(rb + 7) % 9].v[i] - c)));
+    s += p.c2 * (((w[2 + i] - c) + (w[6 + i] - c)) + ((q[(rb + 2) % 9].v[i] - c) + (q[(rb + 6) % 9].v[i] - c)));
+    s += p.c1 * (((w[3 + i] - c) + (w[5 + i] - c)) + ((q[(rb + 3) % 9].v[i] - c) + (q[(rb + 5) % 9].v[i] - c)));
     out[i] = s;
   }
 }
 
-template <typename T, int MODE, int CK>
-__global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int ck_store, int ck_max) {
+// Products and fused multiply-adds with the rounding spelled out, so that the
+// damped and undamped forms of the update below give the same bits where a = b = 1.
+__device__ __forceinline__ float rmul(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double rmul(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ float rfma(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+__device__ __forceinline__ double rfma(double a, double b, double c) { return __fma_rn(a, b, c); }
+
+// Leapfrog update of one pair with damping (a, b).
+//   background: t = kappa Lam, nd = b D + a t, nv = u + nd
+//   Born:       nv = a (2c + kappa (L - dm g)) - b prev
+//   adjoint:    nv = a (2c + kappa L) - b prev
+// Outside the layer (a = b = 1) the multiplications by one are dropped; every
+// other operation is rounded as in the damped form.
+template <typename T, int MODE, bool DAMP>
+__device__ __forceinline__ void update(const T lap[2], const V2<T>& c, const V2<T>& prev, const V2<T>& kap,
+                                       const T* a, const T* b, const T g[2], const V2<T>& dm, V2<T>& nv,
+                                       V2<T>& nd) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (MODE == M_BG) {
+      const T t = rmul(kap.v[i], lap[i]);
+      nd.v[i] = DAMP ? rfma(b[i], prev.v[i], rmul(a[i], t)) : prev.v[i] + t;
+      nv.v[i] = c.v[i] + nd.v[i];
+    } else {
+      const T src = (MODE == M_BORN) ? rmul(kap.v[i], rfma(-dm.v[i], g[i], lap[i])) : rmul(kap.v[i], lap[i]);
+      const T X = rfma(T(2), c.v[i], src);
+      nv.v[i] = DAMP ? rfma(a[i], X, -rmul(b[i], prev.v[i])) : X - prev.v[i];
+    }
+  }
+}
+
+// Inputs of one loop iteration (level 1 on row z, level 2 on row z - 4d for the
+// march direction d = +-1), loaded one iteration ahead so that their latency
+// overlaps the previous row's work.
+// Every load is unconditional: rows outside the grid and lanes outside the
+// model fall outside their buffer resource and read zero.
+template <typename T>
+struct RowIn {
+  V2<T> q;          // level-0 row z + 4d (enters the queue)
+  V2<T> pv;         // row z: level -1 (Born, adjoint) or background increment D^n
+  V2<T> k1, k2;     // kappa on rows z and z - 4d
+  V2<T> m1, m2;     // Born: extended perturbation on rows z and z - 4d
+  V2<T> g1, g2;     // Born: g^n (row z), g^{n+1} (row z - 4d); adjoint: g^{k-1}, g^{k-2} (imaging row)
+  V2<double> im;    // adjoint: image pair on the imaging row
+  T a1[2], b1[2];   // damping on row z (strips that reach into the layer along x)
+  T a2[2], b2[2];   // damping on row z - 4d
+};
+
+// Per-lane byte offset that every buffer access of an inactive lane uses: past
+// the end of any resource, so reads return zero and writes are dropped.
+constexpr unsigned OFF_NONE = 0x80000000u;
+
+// One launch of NS (1 or 2) time steps of every shot of a wave.
+//   M_BG:   in0 = u^n, in1 = D^n            -> out0 = u^{n+NS}, out1 = D^{n+NS};
+//           g^n -> slot hs1, g^{n+1} -> slot hs2 (a negative slot is not written);
+//           checkpoint ck_store <- (u^n, D^n); BF16 maxima of the last level -> ck_max.
+//   M_BORN: in0 = du^n, in1 = du^{n-1}      -> out0 = du^{n+1}, out1 = du^{n+2};
+//           reads g^n (hs1), g^{n+1} (hs2); records d[n], d[n+1].
+//   M_ADJ:  in0 = nu^{k+1}, in1 = nu^{k+2}  -> out0 = nu^k, out1 = nu^{k-1}  (n = k);
+//           injects d[k-1], d[k-2]; images with g^{k-1} (hs1), g^{k-2} (hs2).
+//
+// Lane l holds cells x = strip * SW2 - 2 HL2 + 2 l and x + 1.  Field rows are
+// read through buffer resources that cover exactly rows [0, nzp) of the strip:
+// the row pitch covers every lane of every strip and cells outside the grid are
+// zero ghost cells, rows outside the grid fall outside the resource.  Every
+// value computed for a cell outside the grid is replaced by zero.  Row indices
+// are wave-uniform.
+template <typename T, int MODE, int NS, int CK>
+__global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int hs2, int ck_store, int ck_max) {
+  constexpr bool BG = (MODE == M_BG);
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = xcd_item(p.nwg);
   if (item >= p.nwg) return;
   const int group = item % p.ngroups;
@@ -47,332 +248,311 @@ __global__ __launch_bounds__(256) void k_step2d(Step<T> p, int n, int hslot, int
   const int ls = rest / p.L.nstrips;
   const int chunk = group * 4 + wv;
   if (chunk >= p.nchunks) return;
-  const int z0 = chunk * p.zc;
-  const int z1 = min(z0 + p.zc, p.L.nzp);
-
-  const int pitch = p.L.pitch;
+  const int nzp = p.L.nzp;
   const int nxp = p.L.nxp;
-  const int x = strip * STRIP + lane * CPL - XL;   // prop x of this lane's first cell
-  const bool xin = (x >= 0) && (x < nxp);          // lane holds propagation cells
-  const bool hl_in = (lane == 0) && (x - 4 >= 0) && (x - 4 < nxp);
-  const bool hr_in = (lane == 63) && (x + 4 < nxp);
-  const long long fo = (long long)ls * p.L.fstride + SLACK + (long long)GZ * pitch + XL;
-  const long long col = x;
+  const int nb = p.L.nb;
+  const int nz = p.L.nz;
+  const int z0 = chunk * p.zc;
+  const int z1 = min(z0 + p.zc, nzp);
+  const long long pitch = p.L.pitch;
   const int shot = p.shot0 + ls;
 
-  // model-grid column of this lane
-  const int xm = x - p.L.nb;
-  bool xmod[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) xmod[i] = (xm + i >= 0) && (xm + i < p.L.nx);
-  const bool xmodall = xmod[0] && xmod[1] && xmod[2] && xmod[3];
-  const bool xmodany = xmod[0] || xmod[1] || xmod[2] || xmod[3];
-
-  T ex[4];
-  bool xsponge = false;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int xi = x + i;
-    ex[i] = (xi >= 0 && xi < nxp) ? p.etax[xi] : T(0);
-    xsponge = xsponge || (ex[i] != T(0));
-  }
-  bool xvalid[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) xvalid[i] = (x + i >= 0) && (x + i < nxp);
-  const bool xvalall = xvalid[0] && xvalid[1] && xvalid[2] && xvalid[3];
-
-  // source cell of this shot (background modes)
+  const int sx0 = strip * SW2 - 2 * HL2;                 // first cell of lane 0 (uniform)
+  const int x = sx0 + 2 * lane;                          // first cell of the lane's pair
+  const bool xin = (x >= 0) && (x < nxp);
+  const bool outl = xin && (lane >= HL2) && (lane < LANES - HL2);
+  const bool xv1 = x + 1 < nxp;
+  const bool all_in = (sx0 >= 0) && (sx0 + 2 * LANES <= nxp);               // every cell of the strip is in the grid
+  const bool x_free = (sx0 >= nb) && (sx0 + 2 * LANES <= nxp - nb);          // no damping along x in the strip
+  const int xm = x - nb;                                                     // model column of the pair
+  const bool xmod = (xm >= 0) && (xm < p.L.nx);
+  const bool xmod1 = xm + 1 < p.L.nx;
   int sx = -1, sz = -1;
-  if (MODE == M_FUSED || MODE == M_BG) {
+  if (BG) {
     sx = p.srcx[shot];
     sz = p.srcz[shot];
   }
-  const T wsrc = (MODE == M_FUSED || MODE == M_BG) ? p.wav[n] : T(0);
 
-  // field pointers: queue field A (u0 / du / nu), optional B (du in fused mode)
-  // A: the queued field (background u in FUSED/BG, Born or adjoint field otherwise).
-  // The background is stepped in increment form: Ainc holds u^n - u^{n-1} (updated
-  // in place), u^{n+1} goes to Anext; the other fields keep two levels (Anext
-  // holds level n-1 and receives level n+1).
-  constexpr bool BGM = (MODE == M_FUSED || MODE == M_BG);
-  const T* Acur;
-  T* Anext;
-  T* Ainc = nullptr;
-  const T* Bcur = nullptr;
-  T* Bnext = nullptr;
-  if (BGM) {
-    Acur = p.u_cur + fo;
-    Anext = p.u_next + fo;
-    Ainc = p.u_inc + fo;
-    if (MODE == M_FUSED) {
-      Bcur = p.du_cur + fo;
-      Bnext = p.du_prev + fo;
+  // field resources based at the strip's cell (sx0, 0), nzp rows long
+  const long long kofs = (long long)SLACK + (long long)GZ * pitch + XL + sx0;
+  const long long fo = (long long)ls * p.L.fstride + kofs;
+  const unsigned rowb = (unsigned)(pitch * (long long)sizeof(T));
+  const long long fbytes = (long long)nzp * rowb;
+  const Rsrc rI0 = rsrc(p.in0 + fo, fbytes);
+  const Rsrc rI1 = rsrc(p.in1 + fo, fbytes);
+  const Rsrc rO0 = rsrc(p.out0 + fo, fbytes);
+  const Rsrc rO1 = rsrc(p.out1 + fo, fbytes);
+  const Rsrc rK = rsrc(p.kappa + kofs, fbytes);
+  const Rsrc rD = rsrc(p.damp + 2 * kofs, 2 * fbytes);
+  const Rsrc rM = rsrc(p.dmbar + (long long)p.dm_slot[shot] * p.L.fstride + kofs, fbytes);
+  const unsigned vo = (unsigned)(2 * lane) * (unsigned)sizeof(T);          // lane offset in a field row
+  const unsigned vs = outl ? vo : OFF_NONE;                                  // ... for stores
+  // model resources (g slots, image): nz rows of mpitch
+  const long long hbase = (long long)ls * p.hstride;
+  const long long mbytes = (long long)nz * p.L.mpitch * (long long)sizeof(T);
+  const Rsrc rH1 = rsrc(hs1 >= 0 ? p.hist + hbase + (long long)hs1 * p.L.mstride : p.hist, hs1 >= 0 ? mbytes : 0);
+  const Rsrc rH2 = rsrc(hs2 >= 0 ? p.hist + hbase + (long long)hs2 * p.L.mstride : p.hist, hs2 >= 0 ? mbytes : 0);
+  const Rsrc rIm = rsrc(MODE == M_ADJ ? p.img + (long long)shot * p.L.mstride : p.img,
+                        MODE == M_ADJ ? (long long)nz * p.L.mpitch * 8 : 0);
+  const unsigned mrowb = (unsigned)p.L.mpitch * (unsigned)sizeof(T);
+  const unsigned gvo = xmod ? (unsigned)xm * (unsigned)sizeof(T) : OFF_NONE;             // g loads
+  const unsigned gvs = (xmod && outl) ? (unsigned)xm * (unsigned)sizeof(T) : OFF_NONE;   // g stores
+  const unsigned ivo = (xmod && outl) ? (unsigned)xm * 8u : OFF_NONE;                   // image
+  const unsigned irowb = (unsigned)p.L.mpitch * 8u;
+  float mx0 = 0.0f, mx1 = 0.0f;   // BF16 checkpoints: running max |u|, |D| of the last level
+
+  // row offsets wrap to past the end of the resource for rows above the grid
+  auto frow = [&](int z) -> unsigned { return vo + (unsigned)z * rowb; };
+  // g rows: a pair that ends past nx stores zero into the model row's pad column,
+  // so loads of such a pair need no mask
+  auto gld = [&](const Rsrc& r, int zm) -> V2<T> { return bld2(r, gvo + (unsigned)zm * mrowb, 0u, T(0)); };
+  auto gst = [&](const Rsrc& r, int zm, const T g[2]) {
+    V2<T> gg;
+    gg.v[0] = g[0];
+    gg.v[1] = xmod1 ? g[1] : T(0);
+    bst2(gg, r, gvs + (unsigned)zm * mrowb, 0u);
+  };
+  // receiver indices of the pair on row z (-1: none); false if the row has none
+  auto recs = [&](int z, int rm[2]) -> bool {
+    rm[0] = rm[1] = -1;
+    if (z < p.rec_lo || z > p.rec_hi) return false;   // no lookup outside the receiver rows
+    const int rp = p.recplane[z];
+    if (rp < 0) return false;
+    if (xin) {
+      const int2 m2 = *reinterpret_cast<const int2*>(p.recmap + (long long)rp * p.cpitch + x);
+      rm[0] = m2.x;
+      rm[1] = xv1 ? m2.y : -1;
     }
-  } else {
-    Acur = p.du_cur + fo;
-    Anext = p.du_prev + fo;
+    return true;
+  };
+  // FP32 / BF16 checkpoint of (u^n, D^n) on an output row (the pad column of the
+  // compact rows absorbs a zero past nxp)
+  const long long lv = ((long long)ls * p.nck + max(ck_store, 0)) * 2;   // checkpoint level pair
+  float i0 = 1.0f, i1 = 1.0f;   // BF16: reciprocal scales of the stored levels
+  if (CK == CK_BF16 && ck_store >= 0) {
+    const float s0 = p.ck_scale[lv], s1 = p.ck_scale[lv + 1];
+    if (s0 > 0.0f) i0 = 1.0f / s0;
+    if (s1 > 0.0f) i1 = 1.0f / s1;
   }
-  constexpr bool TWO = (MODE == M_FUSED);
+  auto ckstore = [&](int z, const V2<T>& u, const V2<T>& d) {
+    if (!outl) return;
+    const long long co = (long long)z * p.cpitch + x;
+    if (CK == CK_F32) {
+      T* c0 = static_cast<T*>(p.ck) + lv * p.cstride + co;
+      st2(c0, u);
+      st2(c0 + p.cstride, d);
+    } else if (CK == CK_BF16) {
+      unsigned short* c0 = static_cast<unsigned short*>(p.ck) + lv * p.cstride + co;
+      const unsigned short a0 = bf16_rne((float)u.v[0] * i0), a1 = bf16_rne((float)u.v[1] * i0);
+      const unsigned short b0 = bf16_rne((float)d.v[0] * i1), b1 = bf16_rne((float)d.v[1] * i1);
+      *reinterpret_cast<unsigned int*>(c0) = a0 | ((unsigned)a1 << 16);
+      *reinterpret_cast<unsigned int*>(c0 + p.cstride) = b0 | ((unsigned)b1 << 16);
+    }
+  };
+  auto track = [&](const V2<T>& u, const V2<T>& d) {
+    if (outl) {
+      mx0 = fmaxf(mx0, fmaxf(fabsf((float)u.v[0]), fabsf((float)u.v[1])));
+      mx1 = fmaxf(mx1, fmaxf(fabsf((float)d.v[0]), fabsf((float)d.v[1])));
+    }
+  };
+  // one level on row z from the centre pair c, its Laplacian, kappa, dm and the
+  // previous level; (ap, bp): the prefetched damping of strips that reach the layer
+  auto level = [&](int z, const V2<T>& c, T lap[2], const V2<T>& kp, const V2<T>& dm, const V2<T>& pv,
+                   const T g[2], const T* ap, const T* bp, V2<T>& nv, V2<T>& nd) {
+    if (!x_free) {
+      update<T, MODE, true>(lap, c, pv, kp, ap, bp, g, dm, nv, nd);
+    } else if (z >= nb && z < nzp - nb) {
+      update<T, MODE, false>(lap, c, pv, kp, nullptr, nullptr, g, dm, nv, nd);
+    } else {
+      T a[2], b[2];
+      bld_ab(rD, 2 * frow(z), 0u, a, b);
+      update<T, MODE, true>(lap, c, pv, kp, a, b, g, dm, nv, nd);
+    }
+    if (!all_in) {
+      if (!xin) {
+        nv = zero2<T>();
+        nd = zero2<T>();
+      } else if (!xv1) {
+        nv.v[1] = T(0);
+        nd.v[1] = T(0);
+      }
+    }
+  };
+  // March direction: even chunks go down (z increasing), odd chunks up, so that
+  // two neighbouring chunks reach the rows around their shared boundary at the
+  // same time and the second reads of those rows hit in L2.  The queue holds rows
+  // in march order; the Laplacian sums each symmetric pair commutatively, so the
+  // direction does not change any result bit.
+  const int d = (chunk & 1) ? -1 : 1;
+  const int nit = (z1 - z0) + ((NS == 2) ? 8 : 0);          // level-1 rows of the march
+  const int zs = (d > 0) ? ((NS == 2) ? z0 - 4 : z0) : ((NS == 2) ? z1 + 3 : z1 - 1);
+  auto fetch = [&](int z, RowIn<T>& f) {
+    f.q = bld2(rI0, frow(z + 4 * d), 0u, T(0));
+    f.pv = bld2(rI1, frow(z), 0u, T(0));
+    f.k1 = bld2(rK, frow(z), 0u, T(0));
+    if (!x_free) {
+      bld_ab(rD, 2 * frow(z), 0u, f.a1, f.b1);
+      if (NS == 2) bld_ab(rD, 2 * frow(z - 4 * d), 0u, f.a2, f.b2);
+    }
+    if (MODE == M_BORN) {
+      f.m1 = bld2(rM, frow(z), 0u, T(0));
+      f.g1 = gld(rH1, z - nb);
+    }
+    if (NS == 2) {
+      f.k2 = bld2(rK, frow(z - 4 * d), 0u, T(0));
+      if (MODE == M_BORN) {
+        f.m2 = bld2(rM, frow(z - 4 * d), 0u, T(0));
+        f.g2 = gld(rH2, z - 4 * d - nb);
+      }
+    }
+    if (MODE == M_ADJ) {
+      const int zm = (NS == 2 ? z - 4 * d : z) - nb;   // imaging row
+      f.g1 = gld(rH1, zm);
+      if (NS == 2) f.g2 = gld(rH2, zm);
+      f.im = bld2(rIm, ivo + (unsigned)zm * irowb, 0u, 0.0);
+    }
+  };
 
-  V4<T> qa[9], qb[9];
+  V2<T> q0[9], q1[9], dq[9];   // level-0 rows, level-1 rows, background increment at level 1
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const long long o = (long long)(z0 - 4 + s) * pitch + col;
-    qa[s] = xin ? ld4(Acur + o) : zero4<T>();
-    if (TWO) qb[s] = xin ? ld4(Bcur + o) : zero4<T>();
-  }
+  for (int s = 0; s < 8; ++s) q0[s] = bld2(rI0, frow(zs + (s - 4) * d), 0u, T(0));
+  RowIn<T> cur, nxt;
+  fetch(zs, cur);
 
-  const long long kofs = (long long)SLACK + (long long)GZ * pitch + XL;
-  const T* kap = p.kappa + kofs;
-  const T* dmb = p.dmbar + (long long)p.dm_slot[shot] * p.L.fstride + kofs;
-  const T* hist_n = p.hist + (long long)ls * p.hstride + (long long)hslot * p.L.mstride;
-  double* img = (MODE == M_ADJ) ? p.img + (long long)shot * p.L.mstride : nullptr;
-  T* hist_w = (MODE == M_FUSED || MODE == M_BG) ? const_cast<T*>(hist_n) : nullptr;
-  const T* dat = p.data;
-  float mx0 = 0.0f, mx1 = 0.0f;   // running max |u^{n+1}|, |u^{n+1} - u^n| (BF16 checkpoints)
-
-  for (int zb = z0; zb < z1; zb += 9) {
+  for (int tb = 0; tb < nit; tb += 9) {
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
-      const int z = zb + r;
-      if (z >= z1) break;
-      // bring in row z+4
-      {
-        const long long o = (long long)(z + 4) * pitch + col;
-        qa[(r + 8) % 9] = xin ? ld4(Acur + o) : zero4<T>();
-        if (TWO) qb[(r + 8) % 9] = xin ? ld4(Bcur + o) : zero4<T>();
-      }
-      const long long orow = (long long)z * pitch + col;
-      // x halo of the centre row
-      V4<T> ahl = zero4<T>(), ahr = zero4<T>(), bhl = zero4<T>(), bhr = zero4<T>();
-      if (hl_in) {
-        ahl = ld4(Acur + orow - 4);
-        if (TWO) bhl = ld4(Bcur + orow - 4);
-      }
-      if (hr_in) {
-        ahr = ld4(Acur + orow + 4);
-        if (TWO) bhr = ld4(Bcur + orow + 4);
-      }
-      // Laplacian of A (and B)
-      T lapA[4], lapB[4];
-      {
-        const V4<T>& C = qa[(r + 4) % 9];
-        T w[12];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          w[i] = shr1(C.v[i], ahl.v[i]);
-          w[4 + i] = C.v[i];
-          w[8 + i] = shl1(C.v[i], ahr.v[i]);
-        }
-        lap_diff(w, qa, r, p, lapA);
-      }
-      if (TWO) {
-        const V4<T>& C = qb[(r + 4) % 9];
-        T w[12];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          w[i] = shr1(C.v[i], bhl.v[i]);
-          w[4 + i] = C.v[i];
-          w[8 + i] = shl1(C.v[i], bhr.v[i]);
-        }
-        lap_diff(w, qb, r, p, lapB);
-      }
-      if (!xin) continue;   // nothing to write for padding lanes (after all DPP use)
+      const int t = tb + r;   // iteration: level 1 on row z, level 2 on row z - 4d
+      if (t >= nit) break;
+      const int z = zs + t * d;
+      fetch(z + d, nxt);
+      q0[(r + 8) % 9] = cur.q;
+      const bool out_row = (z >= z0) && (z < z1);
 
-      // point source (background) / receiver injection (adjoint)
-      if ((MODE == M_FUSED || MODE == M_BG) && z == sz) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (x + i == sx) lapA[i] += wsrc;
-      }
-      const int rp = p.recplane[z];
-      const bool recrow = rp >= 0;
-      int rm[4] = {-1, -1, -1, -1};
-      if (recrow) {
-        const int4 m4 = *reinterpret_cast<const int4*>(p.recmap + (long long)rp * p.cpitch + x);
-        rm[0] = m4.x;
-        rm[1] = m4.y;
-        rm[2] = m4.z;
-        rm[3] = m4.w;
-        if (MODE == M_ADJ) {
-          const T* drow = dat + ((long long)shot * p.nt + (n - 1)) * p.nr;
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (rm[i] >= 0) lapA[i] += drow[rm[i]];
+      // ---- level 1 on row z ----
+      if (z >= 0 && z < nzp) {
+        const unsigned so = (unsigned)z * rowb;
+        const V2<T>& c0 = q0[(r + 4) % 9];
+        T w[10];
+        xnb(c0, w);
+        T lap[2];
+        lap2(w, q0, r, p, lap);
+        if (BG && z == sz) {
+          const T ws = p.wav[n];
+          if (x == sx) lap[0] += ws;
+          if (x + 1 == sx) lap[1] += ws;
         }
-      }
-
-      const V4<T> kap4 = ld4(kap + orow);
-      const T ez = p.etaz[z];
-      T a[4], b[4];
-      if (ez == T(0) && !xsponge) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          a[i] = T(1);
-          b[i] = T(1);
+        int rm[2];
+        const bool recrow = recs(z, rm);
+        if (MODE == M_ADJ && recrow) {
+          const T* drow = p.data + ((long long)shot * p.nt + (n - 1)) * p.nr;
+          if (rm[0] >= 0) lap[0] += drow[rm[0]];
+          if (rm[1] >= 0) lap[1] += drow[rm[1]];
         }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) damping(ex[i] + ez, p.hdt, a[i], b[i]);
-      }
-
-      const int zm = z - p.L.nb;
-      const bool zmod = (zm >= 0) && (zm < p.L.nz);
-      const long long mo = (long long)zm * p.L.mpitch + xm;
-
-      // g on this row: computed (background modes) or read (Born, adjoint)
-      T g[4] = {T(0), T(0), T(0), T(0)};
-      if (MODE == M_FUSED || MODE == M_BG) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) g[i] = kap4.v[i] * lapA[i] * p.inv_dt2;
-      } else if (zmod && xmodany) {
-        if (xmodall) {
-          const V4<T> gg = ld4(hist_n + mo);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) g[i] = gg.v[i];
+        T g[2];
+        if (BG) {
+          g[0] = rmul(rmul(cur.k1.v[0], lap[0]), p.inv_dt2);
+          g[1] = rmul(rmul(cur.k1.v[1], lap[1]), p.inv_dt2);
         } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (xmod[i]) g[i] = hist_n[mo + i];
+          g[0] = cur.g1.v[0];   // Born: g^n (unused by the adjoint update)
+          g[1] = cur.g1.v[1];
         }
-      }
-
-      // aprev: level n-1 (two-level fields) or the increment u^n - u^{n-1} (background)
-      const V4<T> aprev = ld4((BGM ? Ainc : Anext) + orow);
-      V4<T> adm = zero4<T>();
-      if (MODE == M_BORN) adm = ld4(dmb + orow);
-      V4<T> anew, ainc;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const T c = qa[(r + 4) % 9].v[i];
-        if (BGM) {
-          // u+ = a (2u + kappa Lam) - b u-  written as  d+ = b d + a kappa Lam,  u+ = u + d+
-          ainc.v[i] = b[i] * aprev.v[i] + a[i] * (kap4.v[i] * lapA[i]);
-          anew.v[i] = c + ainc.v[i];
-        } else {
-          const T src = (MODE == M_BORN) ? kap4.v[i] * (lapA[i] - adm.v[i] * g[i]) : kap4.v[i] * lapA[i];
-          anew.v[i] = a[i] * (T(2) * c + src) - b[i] * aprev.v[i];
+        V2<T> nv, nd;
+        level(z, c0, lap, cur.k1, cur.m1, cur.pv, g, cur.a1, cur.b1, nv, nd);
+        if (NS == 2) {
+          q1[r] = nv;
+          if (BG) dq[r] = nd;
         }
-      }
-      if (xvalall) {
-        st4(Anext + orow, anew);
-        if (BGM) st4(Ainc + orow, ainc);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (xvalid[i]) {
-            Anext[orow + i] = anew.v[i];
-            if (BGM) Ainc[orow + i] = ainc.v[i];
-          }
-      }
-
-      V4<T> bnew;
-      if (TWO) {
-        const V4<T> bprev = ld4(Bnext + orow);
-        const V4<T> dm4 = ld4(dmb + orow);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const T c = qb[(r + 4) % 9].v[i];
-          bnew.v[i] = a[i] * (T(2) * c + kap4.v[i] * (lapB[i] - dm4.v[i] * g[i])) - b[i] * bprev.v[i];
-        }
-        if (xvalall) {
-          st4(Bnext + orow, bnew);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (xvalid[i]) Bnext[orow + i] = bnew.v[i];
-        }
-      }
-
-      // background checkpoint (u^n, u^n - u^{n-1}) and running maxima for the next one
-      if (CK != CK_NONE && (MODE == M_FUSED || MODE == M_BG)) {
-        if (ck_store >= 0) {
-          const long long co = (long long)z * p.cpitch + x;
-          const long long lv = ((long long)ls * p.nck + ck_store) * 2;
-          if (CK == CK_F32) {
-            T* c0 = static_cast<T*>(p.ck) + lv * p.cstride + co;
-            T* c1 = c0 + p.cstride;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if (xvalid[i]) {
-                c0[i] = qa[(r + 4) % 9].v[i];
-                c1[i] = aprev.v[i];
-              }
+        if (out_row) {
+          if (BG) {
+            if (CK != CK_NONE && ck_store >= 0) ckstore(z, c0, cur.pv);
+            gst(rH1, z - nb, g);
+            if (NS == 1) {
+              bst2(nv, rO0, vs + so, 0u);
+              bst2(nd, rO1, vs + so, 0u);
+              if (CK == CK_BF16 && ck_max >= 0) track(nv, nd);
+            }
           } else {
-            const float* sc = p.ck_scale + lv;
-            const float s0 = sc[0], s1 = sc[1];
-            const float i0 = s0 > 0.0f ? 1.0f / s0 : 1.0f, i1 = s1 > 0.0f ? 1.0f / s1 : 1.0f;
-            unsigned short* c0 = static_cast<unsigned short*>(p.ck) + lv * p.cstride + co;
-            unsigned short* c1 = c0 + p.cstride;
-            unsigned short h0[4], h1[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const float uc = (float)qa[(r + 4) % 9].v[i];
-              h0[i] = bf16_rne(uc * i0);
-              h1[i] = bf16_rne((float)aprev.v[i] * i1);
+            bst2(nv, rO0, vs + so, 0u);
+            if (MODE == M_BORN && recrow && outl) {
+              T* drow = p.data + ((long long)shot * p.nt + n) * p.nr;
+              if (rm[0] >= 0) drow[rm[0]] = nv.v[0];
+              if (rm[1] >= 0) drow[rm[1]] = nv.v[1];
             }
-            if (xvalall) {
-              *reinterpret_cast<uint2*>(c0) = make_uint2(h0[0] | ((unsigned)h0[1] << 16), h0[2] | ((unsigned)h0[3] << 16));
-              *reinterpret_cast<uint2*>(c1) = make_uint2(h1[0] | ((unsigned)h1[1] << 16), h1[2] | ((unsigned)h1[3] << 16));
-            } else {
-#pragma unroll
-              for (int i = 0; i < 4; ++i)
-                if (xvalid[i]) {
-                  c0[i] = h0[i];
-                  c1[i] = h1[i];
-                }
+            if (MODE == M_ADJ && NS == 1) {
+              const int zm = z - nb;
+              V2<double> acc = cur.im;
+              acc.v[0] -= (double)cur.g1.v[0] * (double)nv.v[0];
+              acc.v[1] -= (double)cur.g1.v[1] * (double)nv.v[1];
+              bst2(acc, rIm, ivo + (unsigned)zm * irowb, 0u);
             }
           }
         }
-        if (CK == CK_BF16 && ck_max >= 0) {
+      } else if (NS == 2) {
+        q1[r] = zero2<T>();
+        if (BG) dq[r] = zero2<T>();
+      }
+
+      // ---- level 2 on row z - 4d ----
+      if (NS == 2 && t >= 8) {
+        const int y = z - 4 * d;
+        const unsigned so = (unsigned)y * rowb;
+        const V2<T>& c1 = q1[(r + 5) % 9];
+        T w[10];
+        xnb(c1, w);
+        T lap[2];
+        lap2(w, q1, r + 1, p, lap);
+        if (BG && y == sz) {
+          const T ws = p.wav[n + 1];
+          if (x == sx) lap[0] += ws;
+          if (x + 1 == sx) lap[1] += ws;
+        }
+        int rm[2];
+        const bool recrow = recs(y, rm);
+        if (MODE == M_ADJ && recrow) {
+          const T* drow = p.data + ((long long)shot * p.nt + (n - 2)) * p.nr;
+          if (rm[0] >= 0) lap[0] += drow[rm[0]];
+          if (rm[1] >= 0) lap[1] += drow[rm[1]];
+        }
+        const V2<T> pv = BG ? dq[(r + 5) % 9] : q0[r % 9];
+        T g[2];
+        if (BG) {
+          g[0] = rmul(rmul(cur.k2.v[0], lap[0]), p.inv_dt2);
+          g[1] = rmul(rmul(cur.k2.v[1], lap[1]), p.inv_dt2);
+        } else {
+          g[0] = cur.g2.v[0];
+          g[1] = cur.g2.v[1];
+        }
+        V2<T> nv, nd;
+        level(y, c1, lap, cur.k2, cur.m2, pv, g, cur.a2, cur.b2, nv, nd);
+        if (BG) {
+          bst2(nv, rO0, vs + so, 0u);
+          bst2(nd, rO1, vs + so, 0u);
+          gst(rH2, y - nb, g);
+          if (CK == CK_BF16 && ck_max >= 0) track(nv, nd);
+        } else {
+          bst2(nv, rO1, vs + so, 0u);
+          if (MODE == M_BORN && recrow && outl) {
+            T* drow = p.data + ((long long)shot * p.nt + n + 1) * p.nr;
+            if (rm[0] >= 0) drow[rm[0]] = nv.v[0];
+            if (rm[1] >= 0) drow[rm[1]] = nv.v[1];
+          }
+          if (MODE == M_ADJ) {
+            const int zm = y - nb;
+            V2<double> acc = cur.im;
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (xvalid[i]) {
-              mx0 = fmaxf(mx0, fabsf((float)anew.v[i]));
-              mx1 = fmaxf(mx1, fabsf((float)ainc.v[i]));
+            for (int i = 0; i < 2; ++i) {
+              acc.v[i] -= (double)cur.g1.v[i] * (double)c1.v[i];
+              acc.v[i] -= (double)cur.g2.v[i] * (double)nv.v[i];
             }
+            bst2(acc, rIm, ivo + (unsigned)zm * irowb, 0u);
+          }
         }
       }
-
-      // history of g (background modes)
-      if (CK == CK_NONE && (MODE == M_FUSED || MODE == M_BG) && zmod && xmodany) {
-        V4<T> gg;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) gg.v[i] = g[i];
-        if (xmodall) {
-          st4(hist_w + mo, gg);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (xmod[i]) hist_w[mo + i] = g[i];
-        }
-      }
-
-      // receiver gather of du^{n+1} (Born modes)
-      if ((MODE == M_FUSED || MODE == M_BORN) && recrow) {
-        T* drow = p.data + ((long long)shot * p.nt + n) * p.nr;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (rm[i] >= 0) drow[rm[i]] = TWO ? bnew.v[i] : anew.v[i];
-      }
-
-      // zero-lag imaging I -= g^{k-1} nu^k in FP64 (adjoint)
-      if (MODE == M_ADJ && zmod && xmodany) {
-        if (xmodall) {
-          V4<double> acc = *reinterpret_cast<V4<double>*>(img + mo);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) acc.v[i] -= (double)g[i] * (double)anew.v[i];
-          *reinterpret_cast<V4<double>*>(img + mo) = acc;
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (xmod[i]) img[mo + i] -= (double)g[i] * (double)anew.v[i];
-        }
-      }
+      cur = nxt;
     }
-    // rotate nothing: the queue is addressed modulo 9 and zb advances by 9
   }
-  if (CK == CK_BF16 && (MODE == M_FUSED || MODE == M_BG) && ck_max >= 0) {
+  if (CK == CK_BF16 && BG && ck_max >= 0) {
     for (int o = 32; o > 0; o >>= 1) {
       mx0 = fmaxf(mx0, __shfl_xor(mx0, o));
       mx1 = fmaxf(mx1, __shfl_xor(mx1, o));
@@ -419,26 +599,83 @@ __global__ void k_expand(Step<T> p, int nshots, int j) {
   }
 }
 
-template <typename T, int MODE, int CK>
-static void go(const Step<T>& p, int n, int hslot, int cs, int cm, hipStream_t st) {
-  hipLaunchKernelGGL((k_step2d<T, MODE, CK>), dim3(xcd_grid(p.nwg)), dim3(256), 0, st, p, n, hslot, cs, cm);
+// ---- host side ----
+
+static int device_cus() {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      ncu = v;
+    else
+      ncu = 256;
+  }
+  return ncu;
+}
+
+// z chunking: one wave per (shot, strip, chunk), four chunks per workgroup.
+// Picks the chunk height that minimises (resident rounds) x (rows a wave
+// marches), so that a launch fills the resident wave slots without a long
+// tail.  zc_fixed > 0 forces the chunk height.
+template <typename T>
+static void chunking(Step<T>& p, int nsh, int nsteps, int wg_per_cu, int zc_fixed) {
+  const int nzp = p.L.nzp;
+  const long long cap = (long long)device_cus() * std::max(1, wg_per_cu);
+  const long long cols = (long long)nsh * p.L.nstrips;
+  int best_zc = nzp;
+  double best = 1e300;
+  for (int nch = 1; nch <= nzp; ++nch) {
+    const int zc = (nzp + nch - 1) / nch;
+    if ((nzp + zc - 1) / zc != nch) continue;
+    const long long wgs = cols * ((nch + 3) / 4);
+    const long long rounds = (wgs + cap - 1) / cap;
+    const double rows = (nsteps == 2) ? 2.0 * zc + 16.0 : zc + 8.0;
+    const double cost = (double)rounds * rows;
+    if (cost < best) {
+      best = cost;
+      best_zc = zc;
+    }
+  }
+  if (zc_fixed > 0) best_zc = std::min(zc_fixed, nzp);
+  p.zc = best_zc;
+  p.nchunks = (nzp + best_zc - 1) / best_zc;
+  p.ngroups = (p.nchunks + 3) / 4;
+  p.nwg = (int)(cols * p.ngroups);
+}
+
+template <typename T, int MODE, int NS, int CK>
+static void go(Step<T> p, int nsh, int n, int hs1, int hs2, int cs, int cm, int zc_fixed, hipStream_t st) {
+  static int occ = 0;   // resident workgroups per CU for this kernel
+  if (occ == 0) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_sweep2d<T, MODE, NS, CK>, 256, 0) != hipSuccess || b < 1)
+      b = 1;
+    occ = b;
+  }
+  chunking(p, nsh, NS, occ, zc_fixed);
+  hipLaunchKernelGGL((k_sweep2d<T, MODE, NS, CK>), dim3(xcd_grid(p.nwg)), dim3(256), 0, st, p, n, hs1, hs2, cs, cm);
+}
+
+template <typename T, int MODE, int NS>
+static void go_ck(int ck, const Step<T>& p, int nsh, int n, int hs1, int hs2, int cs, int cm, int zc, hipStream_t st) {
+  if (MODE == M_BG && ck == CK_F32) go<T, MODE, NS, CK_F32>(p, nsh, n, hs1, hs2, cs, cm, zc, st);
+  else if (MODE == M_BG && ck == CK_BF16) go<T, MODE, NS, CK_BF16>(p, nsh, n, hs1, hs2, cs, cm, zc, st);
+  else go<T, MODE, NS, CK_NONE>(p, nsh, n, hs1, hs2, -1, -1, zc, st);
 }
 
 template <typename T>
-static void launch(int mode, const Step<T>& p, int n, int hs, int ck, int cs, int cm, hipStream_t st) {
-  switch (mode) {
-    case M_FUSED:
-      if (ck == CK_F32) go<T, M_FUSED, CK_F32>(p, n, hs, cs, cm, st);
-      else if (ck == CK_BF16) go<T, M_FUSED, CK_BF16>(p, n, hs, cs, cm, st);
-      else go<T, M_FUSED, CK_NONE>(p, n, hs, -1, -1, st);
-      break;
-    case M_BG:
-      if (ck == CK_F32) go<T, M_BG, CK_F32>(p, n, hs, cs, cm, st);
-      else if (ck == CK_BF16) go<T, M_BG, CK_BF16>(p, n, hs, cs, cm, st);
-      else go<T, M_BG, CK_NONE>(p, n, hs, -1, -1, st);
-      break;
-    case M_BORN: go<T, M_BORN, CK_NONE>(p, n, hs, -1, -1, st); break;
-    default: go<T, M_ADJ, CK_NONE>(p, n, hs, -1, -1, st); break;
+static void sweep_t(int mode, int nsteps, int ck, const Step<T>& p, int nsh, int n, int hs1, int hs2, int cs,
+                    int cm, int zc, hipStream_t st) {
+  if (mode == M_BG) {
+    if (nsteps == 2) go_ck<T, M_BG, 2>(ck, p, nsh, n, hs1, hs2, cs, cm, zc, st);
+    else go_ck<T, M_BG, 1>(ck, p, nsh, n, hs1, hs2, cs, cm, zc, st);
+  } else if (mode == M_BORN) {
+    if (nsteps == 2) go<T, M_BORN, 2, CK_NONE>(p, nsh, n, hs1, hs2, -1, -1, zc, st);
+    else go<T, M_BORN, 1, CK_NONE>(p, nsh, n, hs1, hs2, -1, -1, zc, st);
+  } else {
+    if (nsteps == 2) go<T, M_ADJ, 2, CK_NONE>(p, nsh, n, hs1, hs2, -1, -1, zc, st);
+    else go<T, M_ADJ, 1, CK_NONE>(p, nsh, n, hs1, hs2, -1, -1, zc, st);
   }
 }
 
@@ -451,11 +688,13 @@ static void expand_t(const Step<T>& p, int nshots, int ck, int j, hipStream_t st
   else hipLaunchKernelGGL((k_expand<T, CK_BF16>), dim3((unsigned)b), dim3(256), 0, st, p, nshots, j);
 }
 
-void step2d(int mode, const Step<float>& p, int n, int hs, int ck, int cs, int cm, hipStream_t s) {
-  launch(mode, p, n, hs, ck, cs, cm, s);
+void sweep2d(int mode, int nsteps, int ck, const Step<float>& p, int nsh, int n, int hs1, int hs2, int cs, int cm,
+             int zc, hipStream_t s) {
+  sweep_t(mode, nsteps, ck, p, nsh, n, hs1, hs2, cs, cm, zc, s);
 }
-void step2d(int mode, const Step<double>& p, int n, int hs, int ck, int cs, int cm, hipStream_t s) {
-  launch(mode, p, n, hs, ck, cs, cm, s);
+void sweep2d(int mode, int nsteps, int ck, const Step<double>& p, int nsh, int n, int hs1, int hs2, int cs, int cm,
+             int zc, hipStream_t s) {
+  sweep_t(mode, nsteps, ck, p, nsh, n, hs1, hs2, cs, cm, zc, s);
 }
 void expand(const Step<float>& p, int ns, int ck, int j, hipStream_t s) { expand_t(p, ns, ck, j, s); }
 void expand(const Step<double>& p, int ns, int ck, int j, hipStream_t s) { expand_t(p, ns, ck, j, s); }

@@ -152,7 +152,8 @@ class Problem:
         return dict(cell_steps=s.cell_steps, waves=s.waves,
                     background_cached=bool(s.background_cached), bytes_reserved=s.bytes_reserved,
                     ms_sweep={k: s.ms_sweep[i] for i, k in enumerate(L.SWEEP_KINDS)},
-                    launches_sweep={k: s.launches_sweep[i] for i, k in enumerate(L.SWEEP_KINDS)})
+                    launches_sweep={k: s.launches_sweep[i] for i, k in enumerate(L.SWEEP_KINDS)},
+                    steps_sweep={k: s.steps_sweep[i] for i, k in enumerate(L.SWEEP_KINDS)})
 
 
 class Basis:
