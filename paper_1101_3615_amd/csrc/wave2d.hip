@@ -8,10 +8,10 @@
 // launch the wave computes the intermediate level on its chunk widened by 4 rows
 // above and below (from level-0 rows [z0-8, z1+8)), and level 2 on [z0, z1), so
 // it needs nothing that another wave computes; neighbouring chunks march in
-// opposite directions so that they read their shared rows at the same time.  Recomputed halo values come from
-// the same inputs through the same operations as in the wave that owns the cell
-// (the undamped interior form where that wave uses it too), and outputs go to
-// other buffers than the inputs, which neighbouring waves are still reading.
+// opposite directions so that they read their shared rows at the same time.
+// Recomputed halo values come from the same inputs through the same roundings as
+// in the wave that owns the cell, and outputs go to other buffers than the
+// inputs, which neighbouring waves are still reading.
 //
 // Rows march in z through 9-row register queues (level 0 and level 1); x
 // neighbours come from adjacent lanes through DPP wavefront shifts.  No LDS and
