@@ -14,7 +14,7 @@ namespace mp {
 // cells around every propagation cell; the SLACK elements in front of and
 // behind every slice cover the 4-column halo read of the first and last ghost
 // rows.  (The 3D sweeps rely on this; the 2D sweeps skip reads outside the grid.)
-constexpr int XL = 4;
+constexpr int XL = 8;
 constexpr int GZ = 4;
 constexpr int GY = 4;            // ghost rows in y (3D)
 constexpr int SLACK = 64;

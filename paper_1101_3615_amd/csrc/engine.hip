@@ -59,7 +59,7 @@ class EngineT final : public Engine {
       // strips of SW2 output cells; the row pitch covers every lane of every
       // strip (8 halo cells on either side), so the sweeps load rows unmasked
       L_.nstrips = (L_.nxp + SW2 - 1) / SW2;
-      L_.pitch = (int)round_up(XL + (long long)L_.nstrips * SW2 + 2 * HL2 + 4, 16);
+      L_.pitch = (int)round_up(XL + (long long)L_.nstrips * SW2 + 8, 32);
       L_.nytiles = 1;
       L_.ypitch = 1;
     } else {
@@ -70,7 +70,15 @@ class EngineT final : public Engine {
     }
     L_.plane = (long long)L_.ypitch * L_.pitch;
     L_.fstride = round_up(2LL * SLACK + (long long)(L_.nzp + 2 * GZ) * L_.plane, 64);
-    L_.mpitch = (int)round_up(c.nx, 4);
+    if (c.ndim == 2) {
+      // model rows start so that every strip's first lane lands on a 64-byte
+      // boundary (128 bytes for even strips), like the field rows
+      L_.mxl = (XL + c.nb) % 32;
+      L_.mpitch = (int)round_up(L_.mxl + c.nx + 1, 32);
+    } else {
+      L_.mxl = 0;
+      L_.mpitch = (int)round_up(c.nx, 4);
+    }
     L_.mplane = (long long)L_.mpitch * c.ny;
     L_.mstride = L_.mplane * c.nz;
     cpitch_ = (int)round_up(L_.nxp, 4);
@@ -695,7 +703,7 @@ class EngineT final : public Engine {
       if ((rc = adjoint(s0, nsh, W, static_cast<const T*>(d)))) return rc;
     }
     cached_ = whole_;
-    stack(static_cast<T*>(img), img_.as<double>(), cfg_.ns, L_.mstride, cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
+    stack(static_cast<T*>(img), img_.as<double>() + L_.mxl, cfg_.ns, L_.mstride, cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
     MP_CHECK_LAUNCH();
     finish_stats(waves, use_cache, cfg_.ns);
     return MP_OK;
@@ -716,7 +724,7 @@ class EngineT final : public Engine {
       if ((rc = adjoint(s0, nsh, W, data))) return rc;
     }
     cached_ = whole_;
-    stack(static_cast<T*>(out), img_.as<double>(), cfg_.ns, L_.mstride, cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
+    stack(static_cast<T*>(out), img_.as<double>() + L_.mxl, cfg_.ns, L_.mstride, cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
     MP_CHECK_LAUNCH();
     finish_stats(waves, use_cache, cfg_.ns);
     return MP_OK;
@@ -752,7 +760,7 @@ class EngineT final : public Engine {
       if ((rc = adjoint(s0, nsh, W, data))) return rc;
     }
     for (int r = 0, b0 = 0; r < nreq; b0 += counts[r], ++r) {
-      stack(static_cast<T*>(out[r]), img_.as<double>() + (long long)b0 * L_.mstride, counts[r], L_.mstride,
+      stack(static_cast<T*>(out[r]), img_.as<double>() + L_.mxl + (long long)b0 * L_.mstride, counts[r], L_.mstride,
             cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
       MP_CHECK_LAUNCH();
     }

@@ -15,7 +15,8 @@ struct Layout {
   long long plane;     // elements per z plane (ypitch * pitch)
   long long fstride;   // elements per field slice of one shot
   int nx, ny, nz, nb;  // model grid and layer width
-  int mpitch;          // model-grid x pitch (multiple of 4)
+  int mpitch;          // model-grid x pitch (2D: multiple of 32; 3D: of 4)
+  int mxl;             // 2D: lead elements before model column 0 of every model row (row alignment)
   long long mplane;    // model elements per z plane (mpitch * ny)
   long long mstride;   // model elements per slice (mplane * nz)
   int nstrips;         // 2D: 120-cell output strips per row; 3D: 64-cell x tiles
@@ -45,6 +46,7 @@ struct Step {
   int nr, nt;
   int shot0;                 // job index of local shot 0 of this wave
   int zc, nchunks, ngroups, nwg;
+  int nsh;                   // 2D: shots of the launch
   // 2D sweeps (one or two steps per launch): inputs and outputs of the launch
   T* in0;                    // background u^n / field level 0
   T* in1;                    // background increment D^n / field level -1

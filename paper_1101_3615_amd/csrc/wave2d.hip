@@ -15,8 +15,8 @@
 //
 // Rows march in z through 9-row register queues (level 0 and level 1); x
 // neighbours come from adjacent lanes through DPP wavefront shifts.  No LDS and
-// no barriers: the four waves of a workgroup take consecutive chunks of one
-// strip, so their overlapping rows hit in L1/L2.  Row indices are uniform across
+// no barriers: the four waves of a workgroup take four shots on one strip and
+// chunk, so the rows of the arrays all shots share hit in L1/L2.  Row indices are uniform across
 // the wavefront.  Rows outside [0, nzp) are zero and never read; cells outside
 // [0, nxp) read as zero from the ghost columns and are never written.
 //
@@ -242,12 +242,13 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = xcd_item(p.nwg);
   if (item >= p.nwg) return;
-  const int group = item % p.ngroups;
-  const int rest = item / p.ngroups;
+  // workgroup = four shots on one (strip, chunk): the rows of the arrays they
+  // share (kappa, damping, perturbation) are read by the four waves together
+  const int chunk = item % p.nchunks;
+  const int rest = item / p.nchunks;
   const int strip = rest % p.L.nstrips;
-  const int ls = rest / p.L.nstrips;
-  const int chunk = group * 4 + wv;
-  if (chunk >= p.nchunks) return;
+  const int ls = (rest / p.L.nstrips) * 4 + wv;
+  if (ls >= p.nsh) return;
   const int nzp = p.L.nzp;
   const int nxp = p.L.nxp;
   const int nb = p.L.nb;
@@ -287,12 +288,13 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
   const Rsrc rM = rsrc(p.dmbar + (long long)p.dm_slot[shot] * p.L.fstride + kofs, fbytes);
   const unsigned vo = (unsigned)(2 * lane) * (unsigned)sizeof(T);          // lane offset in a field row
   const unsigned vs = outl ? vo : OFF_NONE;                                  // ... for stores
-  // model resources (g slots, image): nz rows of mpitch
+  // model resources (g slots, image): nz rows of mpitch from model column 0
   const long long hbase = (long long)ls * p.hstride;
   const long long mbytes = (long long)nz * p.L.mpitch * (long long)sizeof(T);
-  const Rsrc rH1 = rsrc(hs1 >= 0 ? p.hist + hbase + (long long)hs1 * p.L.mstride : p.hist, hs1 >= 0 ? mbytes : 0);
-  const Rsrc rH2 = rsrc(hs2 >= 0 ? p.hist + hbase + (long long)hs2 * p.L.mstride : p.hist, hs2 >= 0 ? mbytes : 0);
-  const Rsrc rIm = rsrc(MODE == M_ADJ ? p.img + (long long)shot * p.L.mstride : p.img,
+  const int mxl = p.L.mxl;
+  const Rsrc rH1 = rsrc(hs1 >= 0 ? p.hist + hbase + (long long)hs1 * p.L.mstride + mxl : p.hist, hs1 >= 0 ? mbytes : 0);
+  const Rsrc rH2 = rsrc(hs2 >= 0 ? p.hist + hbase + (long long)hs2 * p.L.mstride + mxl : p.hist, hs2 >= 0 ? mbytes : 0);
+  const Rsrc rIm = rsrc(MODE == M_ADJ ? p.img + (long long)shot * p.L.mstride + mxl : p.img,
                         MODE == M_ADJ ? (long long)nz * p.L.mpitch * 8 : 0);
   const unsigned mrowb = (unsigned)p.L.mpitch * (unsigned)sizeof(T);
   const unsigned gvo = xmod ? (unsigned)xm * (unsigned)sizeof(T) : OFF_NONE;             // g loads
@@ -614,7 +616,7 @@ static int device_cus() {
   return ncu;
 }
 
-// z chunking: one wave per (shot, strip, chunk), four chunks per workgroup.
+// z chunking: one wave per (shot, strip, chunk), four shots per workgroup.
 // Picks the chunk height that minimises (resident rounds) x (rows a wave
 // marches), so that a launch fills the resident wave slots without a long
 // tail.  zc_fixed > 0 forces the chunk height.
@@ -622,13 +624,13 @@ template <typename T>
 static void chunking(Step<T>& p, int nsh, int nsteps, int wg_per_cu, int zc_fixed) {
   const int nzp = p.L.nzp;
   const long long cap = (long long)device_cus() * std::max(1, wg_per_cu);
-  const long long cols = (long long)nsh * p.L.nstrips;
+  const long long cols = (long long)((nsh + 3) / 4) * p.L.nstrips;
   int best_zc = nzp;
   double best = 1e300;
   for (int nch = 1; nch <= nzp; ++nch) {
     const int zc = (nzp + nch - 1) / nch;
     if ((nzp + zc - 1) / zc != nch) continue;
-    const long long wgs = cols * ((nch + 3) / 4);
+    const long long wgs = cols * nch;
     const long long rounds = (wgs + cap - 1) / cap;
     const double rows = (nsteps == 2) ? 2.0 * zc + 16.0 : zc + 8.0;
     const double cost = (double)rounds * rows;
@@ -640,8 +642,9 @@ static void chunking(Step<T>& p, int nsh, int nsteps, int wg_per_cu, int zc_fixe
   if (zc_fixed > 0) best_zc = std::min(zc_fixed, nzp);
   p.zc = best_zc;
   p.nchunks = (nzp + best_zc - 1) / best_zc;
-  p.ngroups = (p.nchunks + 3) / 4;
-  p.nwg = (int)(cols * p.ngroups);
+  p.ngroups = 1;
+  p.nsh = nsh;
+  p.nwg = (int)(cols * p.nchunks);
 }
 
 template <typename T, int MODE, int NS, int CK>
