@@ -134,10 +134,6 @@ class EngineT final : public Engine {
     if ((rc = etax_.ensure(sizeof(T) * L_.nxp, budget_, "sponge"))) return rc;
     if ((rc = etay_.ensure(sizeof(T) * L_.nyp, budget_, "sponge"))) return rc;
     if ((rc = etaz_.ensure(sizeof(T) * L_.nzp, budget_, "sponge"))) return rc;
-    if (c.ndim == 2) {
-      if ((rc = damp_.ensure(sizeof(T) * 2 * L_.fstride, budget_, "sponge"))) return rc;
-      MP_HIP(hipMemset(damp_.get(), 0, sizeof(T) * 2 * L_.fstride));
-    }
     if ((rc = small_.ensure(64, budget_, "scratch"))) return rc;
     MP_HIP(hipMemcpy(wav_.get(), wt.data(), sizeof(T) * c.nt, hipMemcpyHostToDevice));
     MP_HIP(hipMemcpy(recplane_.get(), recplane.data(), sizeof(int) * L_.nzp, hipMemcpyHostToDevice));
@@ -260,7 +256,7 @@ class EngineT final : public Engine {
     p.etax = etax_.as<T>();
     p.etay = etay_.as<T>();
     p.etaz = etaz_.as<T>();
-    p.damp = damp_.as<T>();
+    p.eta_c = (T)eta_c_;
     p.dmbar = dmbar_.as<T>();
     const int* jt = jtab_.as<int>();
     p.srcx = jt;
@@ -332,6 +328,8 @@ class EngineT final : public Engine {
       return MP_EINVAL;
     }
     std::vector<double> ex = sponge_profile(cfg_.nx, cfg_.nb, cmax, cfg_.h, cfg_.sponge_R);
+    eta_c_ = cfg_.nb > 0 ? sponge_max(cfg_.nb, cmax, cfg_.h, cfg_.sponge_R) * 0.5 * cfg_.dt / ((double)cfg_.nb * cfg_.nb)
+                         : 0.0;
     std::vector<double> ez = sponge_profile(cfg_.nz, cfg_.nb, cmax, cfg_.h, cfg_.sponge_R);
     std::vector<T> ext(ex.begin(), ex.end()), ezt(ez.begin(), ez.end());
     MP_HIP(hipMemcpyAsync(etax_.get(), ext.data(), sizeof(T) * ext.size(), hipMemcpyHostToDevice, s));
@@ -345,10 +343,6 @@ class EngineT final : public Engine {
     Pad pd = pad();
     kappa(kappa_.as<T>(), c, pd, cfg_.dt, s);
     MP_CHECK_LAUNCH();
-    if (cfg_.ndim == 2) {
-      damping2d(damp_.as<T>(), etax_.as<T>(), etaz_.as<T>(), pd, cfg_.dt, s);
-      MP_CHECK_LAUNCH();
-    }
     MP_HIP(hipStreamSynchronize(s));   // host tables above must outlive the copies
     cached_ = false;
     return MP_OK;
@@ -791,7 +785,8 @@ class EngineT final : public Engine {
   bool cached_ = false;
   bool whole_ = false;
   hipStream_t stream_ = nullptr;
-  DevBuf wav_, recplane_, recmap_, kappa_, dmbar_, jtab_, etax_, etay_, etaz_, damp_, small_;
+  DevBuf wav_, recplane_, recmap_, kappa_, dmbar_, jtab_, etax_, etay_, etaz_, small_;
+  double eta_c_ = 0.0;   // 2D damping: eta_max dt / (2 nb^2)
   std::vector<int> hsx_, hsy_, hsz_;
   int rec_lo_ = 0, rec_hi_ = -1;
   int* jhost_ = nullptr;

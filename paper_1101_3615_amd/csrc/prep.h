@@ -23,10 +23,6 @@ void extend(float* dst, const float* model, const Pad& p, hipStream_t s);
 void extend(double* dst, const double* model, const Pad& p, hipStream_t s);
 void kappa(float* dst, const float* c, const Pad& p, double dt, hipStream_t s);
 void kappa(double* dst, const double* c, const Pad& p, double dt, hipStream_t s);
-// (a, b) = (1 / (1 + e), (1 - e) a), e = (eta_x + eta_z) dt / 2, per 2D propagation
-// cell, interleaved, at 2 * (origin + z * plane + x)
-void damping2d(float* dst, const float* etax, const float* etaz, const Pad& p, double dt, hipStream_t s);
-void damping2d(double* dst, const double* etax, const double* etaz, const Pad& p, double dt, hipStream_t s);
 // out[0] = bits of max c (as float), out[1] = count of non-finite / non-positive entries
 void cstats(const float* c, long long n, unsigned int* out, hipStream_t s);
 void cstats(const double* c, long long n, unsigned int* out, hipStream_t s);

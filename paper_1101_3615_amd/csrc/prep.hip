@@ -72,24 +72,6 @@ __global__ void k_kappa(T* dst, const T* c, PadMap m, T dt2) {
   }
 }
 
-// Damping coefficients of the 2D sweeps, one (a, b) pair per propagation cell,
-// by the same operations as the per-cell evaluation of the 3D sweeps.
-template <typename T>
-__global__ void k_damp2d(T* dst, const T* etax, const T* etaz, PadMap m, T hdt) {
-  const long long n = (long long)m.nxp * m.nzp;
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long step = (long long)gridDim.x * blockDim.x;
-  for (; i < n; i += step) {
-    const int x = (int)(i % m.nxp);
-    const int z = (int)(i / m.nxp);
-    T a, b;
-    damping(etax[x] + etaz[z], hdt, a, b);
-    const long long o = 2 * (m.origin + (long long)z * m.plane + x);
-    dst[o] = a;
-    dst[o + 1] = b;
-  }
-}
-
 // max |c| and the count of non-finite or non-positive entries.
 template <typename T>
 __global__ void k_cstats(const T* c, long long n, unsigned int* maxbits, unsigned int* bad) {
@@ -164,19 +146,6 @@ static void kappa_t(T* dst, const T* c, const Pad& p, double dt, hipStream_t s) 
 }
 void kappa(float* d, const float* c, const Pad& p, double dt, hipStream_t s) { kappa_t(d, c, p, dt, s); }
 void kappa(double* d, const double* c, const Pad& p, double dt, hipStream_t s) { kappa_t(d, c, p, dt, s); }
-
-template <typename T>
-static void damping2d_t(T* dst, const T* ex, const T* ez, const Pad& p, double dt, hipStream_t s) {
-  const PadMap m = padmap(p);
-  hipLaunchKernelGGL(k_damp2d<T>, grid_for((long long)m.nxp * m.nzp), dim3(256), 0, s, dst, ex, ez, m,
-                     (T)(0.5 * dt));
-}
-void damping2d(float* d, const float* ex, const float* ez, const Pad& p, double dt, hipStream_t s) {
-  damping2d_t(d, ex, ez, p, dt, s);
-}
-void damping2d(double* d, const double* ex, const double* ez, const Pad& p, double dt, hipStream_t s) {
-  damping2d_t(d, ex, ez, p, dt, s);
-}
 
 template <typename T>
 static void cstats_t(const T* c, long long n, unsigned int* out2, hipStream_t s) {

@@ -29,13 +29,17 @@ inline std::vector<double> ricker(double f, double t0, double dt, int nt) {
   return w;
 }
 
+// Peak damping of the layer: eta_max = 3 c_max ln(1/R) / (2 nb h).
+inline double sponge_max(int nb, double cmax, double h, double R) {
+  return 3.0 * cmax * std::log(1.0 / R) / (2.0 * nb * h);
+}
+
 // Damping eta along one axis of n model cells with nb layer cells each side:
-// eta_max (d / nb)^2, d = distance into the layer in cells,
-// eta_max = 3 c_max ln(1/R) / (2 nb h).
+// eta_max (d / nb)^2, d = distance into the layer in cells.
 inline std::vector<double> sponge_profile(int n, int nb, double cmax, double h, double R) {
   std::vector<double> e(n + 2 * nb, 0.0);
   if (nb <= 0) return e;
-  const double emax = 3.0 * cmax * std::log(1.0 / R) / (2.0 * nb * h);
+  const double emax = sponge_max(nb, cmax, h, R);
   for (int i = 0; i < n + 2 * nb; ++i) {
     int d = nb - i;
     const int d2 = i - (n + nb - 1);

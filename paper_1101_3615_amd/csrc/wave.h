@@ -33,7 +33,7 @@ struct Step {
   const T* etax;             // [nxp]
   const T* etay;             // [nyp]
   const T* etaz;             // [nzp]
-  const T* damp;             // 2D: (a, b) per cell, field layout with 2 values per element
+  T eta_c;                   // 2D: eta_max dt / (2 nb^2): damping e = eta_c (dx^2 + dz^2)
   const T* dmbar;            // [slot][field layout]: zero-extended model perturbations
   const int* dm_slot;        // [shots of the job] perturbation slot of each shot
   const int* srcx;           // [shots of the job] propagation-grid source cell

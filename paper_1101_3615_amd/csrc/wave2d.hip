@@ -93,23 +93,6 @@ __device__ __forceinline__ void bst2(const V2<double>& a, Rsrc r, unsigned vo, u
   v.w = (unsigned)(b1 >> 32);
   __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, 0);
 }
-// (a, b) of the lane's two cells from the interleaved damping table
-__device__ __forceinline__ void bld_ab(Rsrc r, unsigned vo, unsigned so, float a[2], float b[2]) {
-  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
-  a[0] = __uint_as_float(v.x);
-  b[0] = __uint_as_float(v.y);
-  a[1] = __uint_as_float(v.z);
-  b[1] = __uint_as_float(v.w);
-}
-__device__ __forceinline__ void bld_ab(Rsrc r, unsigned vo, unsigned so, double a[2], double b[2]) {
-  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
-  const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, vo + 16, so, 0);
-  a[0] = __longlong_as_double(((long long)v.y << 32) | v.x);
-  b[0] = __longlong_as_double(((long long)v.w << 32) | v.z);
-  a[1] = __longlong_as_double(((long long)w.y << 32) | w.x);
-  b[1] = __longlong_as_double(((long long)w.w << 32) | w.z);
-}
-
 // Cells x-4 .. x+5 around the lane's pair (x, x+1): the pairs of lanes l-2, l-1,
 // l, l+1, l+2 (lanes past either end of the wavefront read zero; their results
 // are not used).
@@ -212,13 +195,26 @@ struct RowIn {
   V2<T> m1, m2;     // Born: extended perturbation on rows z and z - 4d
   V2<T> g1, g2;     // Born: g^n (row z), g^{n+1} (row z - 4d); adjoint: g^{k-1}, g^{k-2} (imaging row)
   V2<double> im;    // adjoint: image pair on the imaging row
-  T a1[2], b1[2];   // damping on row z (strips that reach into the layer along x)
-  T a2[2], b2[2];   // damping on row z - 4d
 };
 
 // Per-lane byte offset that every buffer access of an inactive lane uses: past
 // the end of any resource, so reads return zero and writes are dropped.
 constexpr unsigned OFF_NONE = 0x80000000u;
+
+// Damping of the 2D sweeps: e = (eta_x + eta_z) dt / 2 = ec (dx^2 + dz^2) with dx, dz
+// the cell's distances into the layer and ec = eta_max dt / (2 nb^2); a = 1 / (1 + e),
+// b = (1 - e) a.  a = b = 1 exactly where e = 0.
+__device__ __forceinline__ void damp_ab(float ec, int dd, float& a, float& b) {
+  const float e = ec * (float)dd;
+  a = dd > 0 ? __builtin_amdgcn_rcpf(1.0f + e) : 1.0f;
+  b = (1.0f - e) * a;
+}
+__device__ __forceinline__ void damp_ab(double ec, int dd, double& a, double& b) {
+  const double e = ec * (double)dd;
+  a = dd > 0 ? 1.0 / (1.0 + e) : 1.0;
+  b = (1.0 - e) * a;
+}
+__device__ __forceinline__ int layer_depth(int i, int n, int nb) { return max(max(nb - i, i - (n + nb - 1)), 0); }
 
 // One launch of NS (1 or 2) time steps of every shot of a wave.
 //   M_BG:   in0 = u^n, in1 = D^n            -> out0 = u^{n+NS}, out1 = D^{n+NS};
@@ -265,6 +261,12 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
   const bool xv1 = x + 1 < nxp;
   const bool all_in = (sx0 >= 0) && (sx0 + 2 * LANES <= nxp);               // every cell of the strip is in the grid
   const bool x_free = (sx0 >= nb) && (sx0 + 2 * LANES <= nxp - nb);          // no damping along x in the strip
+  int dx2[2];                                                                // squared layer distance along x
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int dxi = layer_depth(x + i, p.L.nx, nb);
+    dx2[i] = dxi * dxi;
+  }
   const int xm = x - nb;                                                     // model column of the pair
   const bool xmod = (xm >= 0) && (xm < p.L.nx);
   const bool xmod1 = xm + 1 < p.L.nx;
@@ -284,7 +286,6 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
   const Rsrc rO0 = rsrc(p.out0 + fo, fbytes);
   const Rsrc rO1 = rsrc(p.out1 + fo, fbytes);
   const Rsrc rK = rsrc(p.kappa + kofs, fbytes);
-  const Rsrc rD = rsrc(p.damp + 2 * kofs, 2 * fbytes);
   const Rsrc rM = rsrc(p.dmbar + (long long)p.dm_slot[shot] * p.L.fstride + kofs, fbytes);
   const unsigned vo = (unsigned)(2 * lane) * (unsigned)sizeof(T);          // lane offset in a field row
   const unsigned vs = outl ? vo : OFF_NONE;                                  // ... for stores
@@ -357,17 +358,16 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
       mx1 = fmaxf(mx1, fmaxf(fabsf((float)d.v[0]), fabsf((float)d.v[1])));
     }
   };
-  // one level on row z from the centre pair c, its Laplacian, kappa, dm and the
-  // previous level; (ap, bp): the prefetched damping of strips that reach the layer
+  // one level on row z from the centre pair c, its Laplacian, kappa, dm and the previous level
   auto level = [&](int z, const V2<T>& c, T lap[2], const V2<T>& kp, const V2<T>& dm, const V2<T>& pv,
-                   const T g[2], const T* ap, const T* bp, V2<T>& nv, V2<T>& nd) {
-    if (!x_free) {
-      update<T, MODE, true>(lap, c, pv, kp, ap, bp, g, dm, nv, nd);
-    } else if (z >= nb && z < nzp - nb) {
+                   const T g[2], V2<T>& nv, V2<T>& nd) {
+    const int dz = layer_depth(z, nz, nb);
+    if (x_free && dz == 0) {
       update<T, MODE, false>(lap, c, pv, kp, nullptr, nullptr, g, dm, nv, nd);
     } else {
       T a[2], b[2];
-      bld_ab(rD, 2 * frow(z), 0u, a, b);
+      damp_ab(p.eta_c, dx2[0] + dz * dz, a[0], b[0]);
+      damp_ab(p.eta_c, dx2[1] + dz * dz, a[1], b[1]);
       update<T, MODE, true>(lap, c, pv, kp, a, b, g, dm, nv, nd);
     }
     if (!all_in) {
@@ -392,10 +392,6 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
     f.q = bld2(rI0, frow(z + 4 * d), 0u, T(0));
     f.pv = bld2(rI1, frow(z), 0u, T(0));
     f.k1 = bld2(rK, frow(z), 0u, T(0));
-    if (!x_free) {
-      bld_ab(rD, 2 * frow(z), 0u, f.a1, f.b1);
-      if (NS == 2) bld_ab(rD, 2 * frow(z - 4 * d), 0u, f.a2, f.b2);
-    }
     if (MODE == M_BORN) {
       f.m1 = bld2(rM, frow(z), 0u, T(0));
       f.g1 = gld(rH1, z - nb);
@@ -460,7 +456,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
           g[1] = cur.g1.v[1];
         }
         V2<T> nv, nd;
-        level(z, c0, lap, cur.k1, cur.m1, cur.pv, g, cur.a1, cur.b1, nv, nd);
+        level(z, c0, lap, cur.k1, cur.m1, cur.pv, g, nv, nd);
         if (NS == 2) {
           q1[r] = nv;
           if (BG) dq[r] = nd;
@@ -526,7 +522,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
           g[1] = cur.g2.v[1];
         }
         V2<T> nv, nd;
-        level(y, c1, lap, cur.k2, cur.m2, pv, g, cur.a2, cur.b2, nv, nd);
+        level(y, c1, lap, cur.k2, cur.m2, pv, g, nv, nd);
         if (BG) {
           bst2(nv, rO0, vs + so, 0u);
           bst2(nd, rO1, vs + so, 0u);
