@@ -70,7 +70,8 @@ def kernel_bytes(kind, w, s=2):
       Born:       reads du^n, du^{n-1} (8 B per cell), writes s levels (4 B
                   each); reads g of each step (4 B per model cell and step);
       adjoint:    as Born for the field and g, plus one read-modify-write of the
-                  FP64 image (16 B per model cell).
+                  FP64 image per group of four shots (16 B per model cell and
+                  group, 4 B per shot).
     Shared by all shots and counted once per launch: kappa (4 B per cell) and,
     for the Born kernel, the extended perturbation (4 B per cell).
     """
@@ -78,7 +79,7 @@ def kernel_bytes(kind, w, s=2):
     prop, model, ns = w.prop_cells, w.model_cells, w.ns
     per = {"background": 4 * e * prop + s * e * model,
            "born": 2 * e * prop + s * e * prop + s * e * model,
-           "adjoint": 2 * e * prop + s * e * prop + s * e * model + 16 * model}[kind]
+           "adjoint": 2 * e * prop + s * e * prop + s * e * model + 4 * model}[kind]
     shared = e * prop * (2 if kind == "born" else 1)
     return per * ns + shared
 

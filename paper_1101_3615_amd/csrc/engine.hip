@@ -71,9 +71,9 @@ class EngineT final : public Engine {
     L_.plane = (long long)L_.ypitch * L_.pitch;
     L_.fstride = round_up(2LL * SLACK + (long long)(L_.nzp + 2 * GZ) * L_.plane, 64);
     if (c.ndim == 2) {
-      // model rows start so that every strip's first lane lands on a 64-byte
-      // boundary (128 bytes for even strips), like the field rows
-      L_.mxl = (XL + c.nb) % 32;
+      // model rows start so that every strip's first output cell lands on a
+      // 64-byte boundary (128 bytes for even strips)
+      L_.mxl = c.nb % 32;
       L_.mpitch = (int)round_up(L_.mxl + c.nx + 1, 32);
     } else {
       L_.mxl = 0;
@@ -161,14 +161,19 @@ class EngineT final : public Engine {
     if (ckpt_mode()) b += (size_t)nck() * 2 * (ck_elem() * (size_t)cstride_ + sizeof(float));
     return b;
   }
-  // bytes that scale with the job (data, per-shot images, perturbation slots)
+  // Shots per image: the 2D adjoint images the four shots of a workgroup into one
+  // FP64 image, so 2D jobs are laid out in groups of four (each request padded
+  // with null shots); 3D images every shot on its own.
+  int gsz() const { return cfg_.ndim == 2 ? 4 : 1; }
+  int pad_group(int n) const { return (n + gsz() - 1) / gsz() * gsz(); }
+  // bytes that scale with the job (data, images, perturbation slots)
   size_t job_bytes(int nb, int nslots) const {
-    return sizeof(T) * (size_t)nb * cfg_.nt * cfg_.nr + sizeof(double) * (size_t)nb * L_.mstride +
+    return sizeof(T) * (size_t)nb * cfg_.nt * cfg_.nr + sizeof(double) * (size_t)(nb / gsz()) * L_.mstride +
            sizeof(T) * (size_t)nslots * L_.fstride + 4 * sizeof(int) * (size_t)nb;
   }
   int footprint(int op, int nshots, size_t* bytes) const override {
     (void)op;
-    const int nb = nshots > 0 ? nshots : cfg_.ns;
+    const int nb = pad_group(nshots > 0 ? nshots : cfg_.ns);
     const int w = std::max(1, std::min(nb, max_wave(SIZE_MAX, nb, 1)));
     *bytes = budget_->used - reserved_sweep() + job_bytes(nb, 1) + per_shot_bytes() * (size_t)w;
     return MP_OK;
@@ -186,23 +191,25 @@ class EngineT final : public Engine {
     return (int)std::min<size_t>(w, (size_t)nb);
   }
 
-  // Buffers for a job of nb shots and nslots perturbations.  Wave size: the
-  // fewest waves that fit, shots split evenly between them.
+  // Buffers for a job of nb shots (a multiple of the group size) and nslots
+  // perturbations.  Wave size: the fewest waves that fit, shots split evenly
+  // between them in whole groups.
   int plan(int nb, int nslots, int* W) {
-    const int wmax = max_wave(budget_->limit, nb, nslots);
-    if (wmax < 1) {
-      set_error("budget too small for one shot of the sweep");
+    const int g = gsz();
+    const int wmax = max_wave(budget_->limit, nb, nslots) / g * g;
+    if (wmax < g) {
+      set_error("budget too small for one group of shots of the sweep");
       return MP_ENOMEM;
     }
-    // MP_MAX_WAVE caps the shots per wave (tuning: a smaller wave keeps the
-    // per-step working set inside the on-die Infinity Cache)
+    // MP_MAX_WAVE caps the shots per wave (a tuning knob)
     int cap = wmax;
-    if (const char* mw = getenv("MP_MAX_WAVE")) cap = std::max(1, std::min(cap, atoi(mw)));
-    const int nw = (nb + cap - 1) / cap;
-    const int w = (nb + nw - 1) / nw;
+    if (const char* mw = getenv("MP_MAX_WAVE")) cap = std::max(g, std::min(cap, atoi(mw) / g * g));
+    const int ngr = nb / g, cgr = cap / g;
+    const int nw = (ngr + cgr - 1) / cgr;
+    const int w = (ngr + nw - 1) / nw * g;
     int rc;
     if ((rc = data_.ensure(sizeof(T) * (size_t)nb * cfg_.nt * cfg_.nr, budget_, "data"))) return rc;
-    if ((rc = img_.ensure(sizeof(double) * (size_t)nb * L_.mstride, budget_, "images"))) return rc;
+    if ((rc = img_.ensure(sizeof(double) * (size_t)(nb / g) * L_.mstride, budget_, "images"))) return rc;
     if ((rc = dmbar_.ensure(sizeof(T) * (size_t)nslots * L_.fstride, budget_, "dm"))) return rc;
     if ((rc = jtab_.ensure(4 * sizeof(int) * (size_t)nb, budget_, "job tables"))) return rc;
     if ((rc = fields_.ensure(sizeof(T) * nslices() * (size_t)w * L_.fstride, budget_, "fields"))) return rc;
@@ -216,7 +223,8 @@ class EngineT final : public Engine {
     return MP_OK;
   }
 
-  // Job tables: per job shot, the source cell (x, y, z) and the perturbation slot.
+  // Job tables: per job shot, the source cell (x, y, z) and the perturbation slot
+  // (shot -1: a null shot that pads a group).
   // Staged through pinned host memory; the previous upload must have landed
   // before the staging buffer is rewritten.
   int upload_job(const std::vector<int>& shots, const std::vector<int>& slots) {
@@ -230,9 +238,10 @@ class EngineT final : public Engine {
       jcap_ = 4 * nb;
     }
     for (size_t b = 0; b < nb; ++b) {
-      jhost_[b] = hsx_[shots[b]];
-      jhost_[nb + b] = hsy_[shots[b]];
-      jhost_[2 * nb + b] = hsz_[shots[b]];
+      const bool null = shots[b] < 0;   // padding of a group: no source, no data
+      jhost_[b] = null ? -1 : hsx_[shots[b]];
+      jhost_[nb + b] = null ? -1 : hsy_[shots[b]];
+      jhost_[2 * nb + b] = null ? -1 : hsz_[shots[b]];
       jhost_[3 * nb + b] = slots[b];
     }
     MP_HIP(hipMemcpyAsync(jtab_.get(), jhost_, sizeof(int) * 4 * nb, hipMemcpyHostToDevice, stream_));
@@ -485,6 +494,10 @@ class EngineT final : public Engine {
   // mode 0: background + Born, 1: Born from the stored g, 2: background only.
   int forward2d(int mode, int s0, int nsh, int W, T* data) {
     int rc;
+    if (nsh % gsz() || s0 % gsz()) {
+      set_error("internal: a 2D sweep takes whole groups of shots");
+      return MP_EINVAL;
+    }
     if ((rc = zero_fields(W, true))) return rc;
     Step<T> p = params(s0, nsh, W);
     p.data = data;
@@ -530,8 +543,13 @@ class EngineT final : public Engine {
 
   int adjoint2d(int s0, int nsh, int W, const T* data) {
     int rc;
+    if (nsh % gsz() || s0 % gsz()) {
+      set_error("internal: a 2D sweep takes whole groups of shots");
+      return MP_EINVAL;
+    }
     if ((rc = zero_fields(W, false))) return rc;
-    fill(img_.as<double>() + (long long)s0 * L_.mstride, (long long)nsh * L_.mstride, 0.0, stream_);
+    fill(img_.as<double>() + (long long)(s0 / gsz()) * L_.mstride, (long long)(nsh / gsz()) * L_.mstride, 0.0,
+         stream_);
     Step<T> p = params(s0, nsh, W);
     p.data = const_cast<T*>(data);
     Rot2 r = rot2(W);
@@ -660,8 +678,9 @@ class EngineT final : public Engine {
   // the job of a plain call: every acquisition shot once, perturbation slot 0
   int plain_job(int* W) {
     int rc;
-    if ((rc = plan(cfg_.ns, 1, W))) return rc;
-    std::vector<int> shots(cfg_.ns), slots(cfg_.ns, 0);
+    const int nb = pad_group(cfg_.ns);
+    if ((rc = plan(nb, 1, W))) return rc;
+    std::vector<int> shots(nb, -1), slots(nb, 0);
     for (int i = 0; i < cfg_.ns; ++i) shots[i] = i;
     return upload_job(shots, slots);
   }
@@ -672,11 +691,12 @@ class EngineT final : public Engine {
     if ((rc = plain_job(&W))) return rc;
     put_dm(0, dm, s);
     MP_CHECK_LAUNCH();
-    // with checkpoints the Born field still needs g at every step: always fused
+    // with checkpoints the Born field still needs g at every step
     const bool use_cache = cached_ && whole_ && !ckpt_mode();
+    const int nb = pad_group(cfg_.ns);
     int waves = 0;
-    for (int s0 = 0; s0 < cfg_.ns; s0 += W, ++waves) {
-      const int nsh = std::min(W, cfg_.ns - s0);
+    for (int s0 = 0; s0 < nb; s0 += W, ++waves) {
+      const int nsh = std::min(W, nb - s0);
       if ((rc = forward(use_cache ? 1 : 0, s0, nsh, W, static_cast<T*>(d)))) return rc;
     }
     cached_ = whole_;
@@ -689,15 +709,17 @@ class EngineT final : public Engine {
     int W, rc;
     if ((rc = plain_job(&W))) return rc;
     const bool use_cache = cached_ && whole_;
+    const int nb = pad_group(cfg_.ns);
     int waves = 0;
-    for (int s0 = 0; s0 < cfg_.ns; s0 += W, ++waves) {
-      const int nsh = std::min(W, cfg_.ns - s0);
+    for (int s0 = 0; s0 < nb; s0 += W, ++waves) {
+      const int nsh = std::min(W, nb - s0);
       if (!use_cache)
         if ((rc = forward(2, s0, nsh, W, nullptr))) return rc;
       if ((rc = adjoint(s0, nsh, W, static_cast<const T*>(d)))) return rc;
     }
     cached_ = whole_;
-    stack(static_cast<T*>(img), img_.as<double>() + L_.mxl, cfg_.ns, L_.mstride, cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
+    stack(static_cast<T*>(img), img_.as<double>() + L_.mxl, nb / gsz(), L_.mstride, cfg_.nx, cfg_.ny, cfg_.nz,
+          L_.mpitch, cfg_.ny, s);
     MP_CHECK_LAUNCH();
     finish_stats(waves, use_cache, cfg_.ns);
     return MP_OK;
@@ -710,15 +732,17 @@ class EngineT final : public Engine {
     put_dm(0, dm, s);
     MP_CHECK_LAUNCH();
     const bool use_cache = cached_ && whole_ && !ckpt_mode();
+    const int nb = pad_group(cfg_.ns);
     int waves = 0;
     T* data = data_.as<T>();
-    for (int s0 = 0; s0 < cfg_.ns; s0 += W, ++waves) {
-      const int nsh = std::min(W, cfg_.ns - s0);
+    for (int s0 = 0; s0 < nb; s0 += W, ++waves) {
+      const int nsh = std::min(W, nb - s0);
       if ((rc = forward(use_cache ? 1 : 0, s0, nsh, W, data))) return rc;
       if ((rc = adjoint(s0, nsh, W, data))) return rc;
     }
     cached_ = whole_;
-    stack(static_cast<T*>(out), img_.as<double>() + L_.mxl, cfg_.ns, L_.mstride, cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
+    stack(static_cast<T*>(out), img_.as<double>() + L_.mxl, nb / gsz(), L_.mstride, cfg_.nx, cfg_.ny, cfg_.nz,
+          L_.mpitch, cfg_.ny, s);
     MP_CHECK_LAUNCH();
     finish_stats(waves, use_cache, cfg_.ns);
     return MP_OK;
@@ -726,17 +750,26 @@ class EngineT final : public Engine {
 
   // Several normal-operator applications in one sweep: request r applies
   // sum over its shots of F_s* F_s to dm[r].  The shots of all requests are
-  // propagated together (one launch per time step); each request's image is
-  // stacked from its own shots in the order given.
+  // propagated together (one launch per time step); each request occupies
+  // whole image groups (padded with null shots), and its image is stacked from
+  // its own groups in order, so a request gives the same bits alone or in a mix.
   int apply_H_batch(int nreq, const int* counts, const int* shots, const void* const* dm, void* const* out,
                     hipStream_t s) override {
     stream_ = s;
-    std::vector<int> js, jslot;
-    for (int r = 0, k = 0; r < nreq; ++r)
+    std::vector<int> js, jslot, first(nreq);
+    int real = 0;
+    for (int r = 0, k = 0; r < nreq; ++r) {
+      first[r] = (int)js.size();
       for (int i = 0; i < counts[r]; ++i, ++k) {
         js.push_back(shots[k]);
         jslot.push_back(r);
       }
+      while ((int)js.size() % gsz()) {
+        js.push_back(-1);
+        jslot.push_back(r);
+      }
+      real += counts[r];
+    }
     const int nb = (int)js.size();
     int W, rc;
     if ((rc = plan(nb, nreq, &W))) return rc;
@@ -753,12 +786,13 @@ class EngineT final : public Engine {
       if ((rc = forward(0, s0, nsh, W, data))) return rc;
       if ((rc = adjoint(s0, nsh, W, data))) return rc;
     }
-    for (int r = 0, b0 = 0; r < nreq; b0 += counts[r], ++r) {
-      stack(static_cast<T*>(out[r]), img_.as<double>() + L_.mxl + (long long)b0 * L_.mstride, counts[r], L_.mstride,
+    for (int r = 0; r < nreq; ++r) {
+      const int g0 = first[r] / gsz(), ng = pad_group(counts[r]) / gsz();
+      stack(static_cast<T*>(out[r]), img_.as<double>() + L_.mxl + (long long)g0 * L_.mstride, ng, L_.mstride,
             cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
       MP_CHECK_LAUNCH();
     }
-    finish_stats(waves, false, nb);
+    finish_stats(waves, false, real);
     return MP_OK;
   }
 

@@ -25,7 +25,7 @@
 //               (u+ = a (2u + kappa Lam) - b u- written with the increment D = u - u-)
 //   Born        du+ = a (2 du + kappa (L du - dm g)) - b du-          (Sec. 2)
 //   adjoint     nu  = a (2 nu' + kappa (L nu' + R^T d)) - b nu''      (exact transpose)
-//   imaging     I  -= g^{k-1} nu^k                                    (FP64)
+//   imaging     I  -= g^{k-1} nu^k                                    (FP64, per group of 4 shots)
 #include <algorithm>
 
 #include "common.h"
@@ -243,8 +243,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
   const int chunk = item % p.nchunks;
   const int rest = item / p.nchunks;
   const int strip = rest % p.L.nstrips;
-  const int ls = (rest / p.L.nstrips) * 4 + wv;
-  if (ls >= p.nsh) return;
+  const int ls = (rest / p.L.nstrips) * 4 + wv;   // the launch holds whole groups of 4 shots
   const int nzp = p.L.nzp;
   const int nxp = p.L.nxp;
   const int nb = p.L.nb;
@@ -275,6 +274,8 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
     sx = p.srcx[shot];
     sz = p.srcz[shot];
   }
+  // a null shot (no source: padding of a group) records and injects no data
+  const bool live = p.srcx[shot] >= 0;
 
   // field resources based at the strip's cell (sx0, 0), nzp rows long
   const long long kofs = (long long)SLACK + (long long)GZ * pitch + XL + sx0;
@@ -295,20 +296,47 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
   const int mxl = p.L.mxl;
   const Rsrc rH1 = rsrc(hs1 >= 0 ? p.hist + hbase + (long long)hs1 * p.L.mstride + mxl : p.hist, hs1 >= 0 ? mbytes : 0);
   const Rsrc rH2 = rsrc(hs2 >= 0 ? p.hist + hbase + (long long)hs2 * p.L.mstride + mxl : p.hist, hs2 >= 0 ? mbytes : 0);
-  const Rsrc rIm = rsrc(MODE == M_ADJ ? p.img + (long long)shot * p.L.mstride + mxl : p.img,
+  // adjoint: one FP64 image per group of four consecutive shots (the workgroup)
+  const Rsrc rIm = rsrc(MODE == M_ADJ ? p.img + (long long)(shot >> 2) * p.L.mstride + mxl : p.img,
                         MODE == M_ADJ ? (long long)nz * p.L.mpitch * 8 : 0);
   const unsigned mrowb = (unsigned)p.L.mpitch * (unsigned)sizeof(T);
-  const unsigned gvo = xmod ? (unsigned)xm * (unsigned)sizeof(T) : OFF_NONE;             // g loads
-  const unsigned gvs = (xmod && outl) ? (unsigned)xm * (unsigned)sizeof(T) : OFF_NONE;   // g stores
-  const unsigned ivo = (xmod && outl) ? (unsigned)xm * 8u : OFF_NONE;                   // image
+  const unsigned gvo = xmod ? (unsigned)xm * (unsigned)sizeof(T) : OFF_NONE;             // g on every lane
+  const unsigned gvs = (xmod && outl) ? (unsigned)xm * (unsigned)sizeof(T) : OFF_NONE;   // g on output lanes
   const unsigned irowb = (unsigned)p.L.mpitch * 8u;
+  // Imaging of the group: the four waves' contributions to a row are summed in LDS
+  // in shot order, then wave w updates the image of lane pairs 16w .. 16w+15
+  // (lanes 0..15 of the wave).  gj: the pair this lane updates.
+  __shared__ V2<double> red[(MODE == M_ADJ) ? 2 : 1][4][(MODE == M_ADJ) ? LANES : 1];
+  const int gj = (wv << 4) + (lane & 15);
+  const int gx = sx0 + 2 * gj;
+  const bool gout = (lane < 16) && (gj >= HL2) && (gj < LANES - HL2) && (gx < nxp) && (gx - nb >= 0) &&
+                    (gx - nb < p.L.nx);
+  const unsigned ivo = gout ? (unsigned)(gx - nb) * 8u : OFF_NONE;
+  int rbuf = 0;
+  auto image = [&](int zm, const V2<double>& cw, const V2<double>& old) {
+    red[rbuf][wv][lane] = cw;
+    __syncthreads();
+    if (lane < 16) {
+      V2<double> acc = old;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const double sum = ((red[rbuf][0][gj].v[i] + red[rbuf][1][gj].v[i]) + red[rbuf][2][gj].v[i]) +
+                           red[rbuf][3][gj].v[i];
+        acc.v[i] += sum;
+      }
+      bst2(acc, rIm, ivo + (unsigned)zm * irowb, 0u);
+    }
+    rbuf ^= 1;
+  };
   float mx0 = 0.0f, mx1 = 0.0f;   // BF16 checkpoints: running max |u|, |D| of the last level
 
   // row offsets wrap to past the end of the resource for rows above the grid
   auto frow = [&](int z) -> unsigned { return vo + (unsigned)z * rowb; };
   // g rows: a pair that ends past nx stores zero into the model row's pad column,
   // so loads of such a pair need no mask
-  auto gld = [&](const Rsrc& r, int zm) -> V2<T> { return bld2(r, gvo + (unsigned)zm * mrowb, 0u, T(0)); };
+  auto gld = [&](const Rsrc& r, unsigned vo_lane, int zm) -> V2<T> {
+    return bld2(r, vo_lane + (unsigned)zm * mrowb, 0u, T(0));
+  };
   auto gst = [&](const Rsrc& r, int zm, const T g[2]) {
     V2<T> gg;
     gg.v[0] = g[0];
@@ -394,19 +422,19 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
     f.k1 = bld2(rK, frow(z), 0u, T(0));
     if (MODE == M_BORN) {
       f.m1 = bld2(rM, frow(z), 0u, T(0));
-      f.g1 = gld(rH1, z - nb);
+      f.g1 = gld(rH1, gvo, z - nb);   // level 1 runs on the halo lanes too
     }
     if (NS == 2) {
       f.k2 = bld2(rK, frow(z - 4 * d), 0u, T(0));
       if (MODE == M_BORN) {
         f.m2 = bld2(rM, frow(z - 4 * d), 0u, T(0));
-        f.g2 = gld(rH2, z - 4 * d - nb);
+        f.g2 = gld(rH2, gvs, z - 4 * d - nb);
       }
     }
     if (MODE == M_ADJ) {
       const int zm = (NS == 2 ? z - 4 * d : z) - nb;   // imaging row
-      f.g1 = gld(rH1, zm);
-      if (NS == 2) f.g2 = gld(rH2, zm);
+      f.g1 = gld(rH1, gvs, zm);
+      if (NS == 2) f.g2 = gld(rH2, gvs, zm);
       f.im = bld2(rIm, ivo + (unsigned)zm * irowb, 0u, 0.0);
     }
   };
@@ -442,7 +470,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
         }
         int rm[2];
         const bool recrow = recs(z, rm);
-        if (MODE == M_ADJ && recrow) {
+        if (MODE == M_ADJ && recrow && live) {
           const T* drow = p.data + ((long long)shot * p.nt + (n - 1)) * p.nr;
           if (rm[0] >= 0) lap[0] += drow[rm[0]];
           if (rm[1] >= 0) lap[1] += drow[rm[1]];
@@ -472,17 +500,19 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
             }
           } else {
             bst2(nv, rO0, vs + so, 0u);
-            if (MODE == M_BORN && recrow && outl) {
+            if (MODE == M_BORN && recrow && outl && live) {
               T* drow = p.data + ((long long)shot * p.nt + n) * p.nr;
               if (rm[0] >= 0) drow[rm[0]] = nv.v[0];
               if (rm[1] >= 0) drow[rm[1]] = nv.v[1];
             }
             if (MODE == M_ADJ && NS == 1) {
               const int zm = z - nb;
-              V2<double> acc = cur.im;
-              acc.v[0] -= (double)cur.g1.v[0] * (double)nv.v[0];
-              acc.v[1] -= (double)cur.g1.v[1] * (double)nv.v[1];
-              bst2(acc, rIm, ivo + (unsigned)zm * irowb, 0u);
+              if (zm >= 0 && zm < nz) {   // uniform over the workgroup
+                V2<double> cw;
+#pragma unroll
+                for (int i = 0; i < 2; ++i) cw.v[i] = -((double)cur.g1.v[i] * (double)nv.v[i]);
+                image(zm, cw, cur.im);
+              }
             }
           }
         }
@@ -507,7 +537,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
         }
         int rm[2];
         const bool recrow = recs(y, rm);
-        if (MODE == M_ADJ && recrow) {
+        if (MODE == M_ADJ && recrow && live) {
           const T* drow = p.data + ((long long)shot * p.nt + (n - 2)) * p.nr;
           if (rm[0] >= 0) lap[0] += drow[rm[0]];
           if (rm[1] >= 0) lap[1] += drow[rm[1]];
@@ -530,20 +560,22 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
           if (CK == CK_BF16 && ck_max >= 0) track(nv, nd);
         } else {
           bst2(nv, rO1, vs + so, 0u);
-          if (MODE == M_BORN && recrow && outl) {
+          if (MODE == M_BORN && recrow && outl && live) {
             T* drow = p.data + ((long long)shot * p.nt + n + 1) * p.nr;
             if (rm[0] >= 0) drow[rm[0]] = nv.v[0];
             if (rm[1] >= 0) drow[rm[1]] = nv.v[1];
           }
           if (MODE == M_ADJ) {
             const int zm = y - nb;
-            V2<double> acc = cur.im;
+            if (zm >= 0 && zm < nz) {   // uniform over the workgroup
+              V2<double> cw;
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-              acc.v[i] -= (double)cur.g1.v[i] * (double)c1.v[i];
-              acc.v[i] -= (double)cur.g2.v[i] * (double)nv.v[i];
+              for (int i = 0; i < 2; ++i) {
+                cw.v[i] = -((double)cur.g1.v[i] * (double)c1.v[i]);
+                cw.v[i] -= (double)cur.g2.v[i] * (double)nv.v[i];
+              }
+              image(zm, cw, cur.im);
             }
-            bst2(acc, rIm, ivo + (unsigned)zm * irowb, 0u);
           }
         }
       }

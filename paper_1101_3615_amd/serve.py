@@ -121,18 +121,20 @@ class Server:
     def _form_batch(self, lane, now):
         shape = lane[0]
         budget = self.ex.lane_budget(lane)
-        batch, nshots = [], 0
+        batch, nshots, njob = [], 0, 0
         for r in list(self.queue.values()):
             if r.shape != shape:
                 continue
             n = nshots + len(r.shots)
+            # each request occupies whole groups of four job entries on the device
+            nj = njob + -(-len(r.shots) // 4) * 4
             if batch and n > self.max_batch_shots:
                 break
-            if batch and self.ex.footprint(lane, n) > budget:
+            if batch and self.ex.footprint(lane, nj) > budget:
                 self.rejected_waits += 1
                 break
             batch.append(r)
-            nshots = n
+            nshots, njob = n, nj
         for r in batch:
             del self.queue[r.rid]
             r.admitted = now

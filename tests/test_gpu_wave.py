@@ -33,9 +33,13 @@ def rel(a, b):
 
 
 def ragged(dtype="f64", nt=150, nx=300, nz=70, ns=3, nr=50, nb=20, seed=31):
-    """Several 256-cell strips and z-chunks with ragged tails in both axes."""
-    src = np.stack([np.array([min(3, nx - 1), nx // 2, nx - 1]), np.array([0, min(5, nz - 1), 0])],
-                   1).astype(np.int32)[:ns]
+    """Several strips and z-chunks with ragged tails in both axes."""
+    if ns <= 3:
+        src = np.stack([np.array([min(3, nx - 1), nx // 2, nx - 1]), np.array([0, min(5, nz - 1), 0])],
+                       1).astype(np.int32)[:ns]
+    else:
+        sx = np.linspace(0, nx - 1, ns).round().astype(np.int32)
+        src = np.stack([sx, (np.arange(ns) % 3).astype(np.int32)], 1)
     recx = np.linspace(0, nx - 1, nr).round().astype(np.int32)
     rec = np.stack([recx, np.zeros(nr, np.int32)], 1)
     return Workload(name="ragged", ndim=2, nx=nx, nz=nz, h=10.0, nb=nb, dt=1.0e-3, nt=nt,
@@ -83,7 +87,8 @@ def test_gpu_dot_product(dtype):
 
 
 def test_background_cache_and_waves_are_bitwise_neutral():
-    w = ragged("f32", nt=100, ns=3)
+    # 10 shots: three groups of four on the device, the last padded with two null shots
+    w = ragged("f32", nt=100, ns=10)
     M, P, c = _setup(w)
     dm = torch.from_numpy(F.wavepackets(w, c, 91, 5))
     first = P.apply_H(dm).cpu()
@@ -91,7 +96,7 @@ def test_background_cache_and_waves_are_bitwise_neutral():
     second = P.apply_H(dm).cpu()
     assert P.stats()["background_cached"]
     assert torch.equal(first, second)
-    # a budget that fits one shot at a time forces three waves
+    # a budget that fits fewer groups at a time forces several waves
     fp = P.footprint("H")
     Q = M.Problem.from_spec(w, budget_bytes=int(fp * 0.55))
     Q.set_background(torch.from_numpy(c))
@@ -197,10 +202,14 @@ def test_checkpoint_modes(snap, k):
     err = rel(img, O.apply_Fadj(d))
     print(f"{snap} every {k}: apply_Fadj rel L2 vs FP64 oracle = {err:.3e}")
     assert err <= tol
-    # waves give the same bits
-    fp = P.footprint("H")
-    Q = M.Problem.from_spec(w, snap=snap, ckpt_every=k, budget_bytes=int(fp * 0.55))
+    # waves give the same bits (10 shots: three groups of four on the device)
+    w10 = w.with_(src=ragged("f32", ns=10).src)
+    P10 = M.Problem.from_spec(w10, snap=snap, ckpt_every=k)
+    P10.set_background(torch.from_numpy(c))
+    whole = P10.apply_H(torch.from_numpy(dm)).cpu().numpy()
+    fp = P10.footprint("H")
+    Q = M.Problem.from_spec(w10, snap=snap, ckpt_every=k, budget_bytes=int(fp * 0.55))
     Q.set_background(torch.from_numpy(c))
     again = Q.apply_H(torch.from_numpy(dm)).cpu().numpy()
     assert Q.stats()["waves"] > 1
-    assert np.array_equal(again, got)
+    assert np.array_equal(again, whole)
