@@ -27,6 +27,7 @@
 //   adjoint     nu  = a (2 nu' + kappa (L nu' + R^T d)) - b nu''      (exact transpose)
 //   imaging     I  -= g^{k-1} nu^k                                    (FP64, per group of 4 shots)
 #include <algorithm>
+#include <cmath>
 
 #include "common.h"
 #include "wave.h"
@@ -439,7 +440,10 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
     }
   };
 
-  V2<T> q0[9], q1[9], dq[9];   // level-0 rows, level-1 rows, background increment at level 1
+  V2<T> q0[9], q1[9];   // level-0 rows, level-1 rows
+  // background: the increment D^{n+1} of level-1 rows, read back four rows later
+  // at the centre of level 2 (kept in LDS: each wave reads only its own entries)
+  __shared__ V2<T> dq[(BG && NS == 2) ? 4 : 1][9][(BG && NS == 2) ? LANES : 1];
 #pragma unroll
   for (int s = 0; s < 8; ++s) q0[s] = bld2(rI0, frow(zs + (s - 4) * d), 0u, T(0));
   RowIn<T> cur, nxt;
@@ -487,7 +491,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
         level(z, c0, lap, cur.k1, cur.m1, cur.pv, g, nv, nd);
         if (NS == 2) {
           q1[r] = nv;
-          if (BG) dq[r] = nd;
+          if (BG) dq[wv][r][lane] = nd;
         }
         if (out_row) {
           if (BG) {
@@ -518,7 +522,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
         }
       } else if (NS == 2) {
         q1[r] = zero2<T>();
-        if (BG) dq[r] = zero2<T>();
+        if (BG) dq[wv][r][lane] = zero2<T>();
       }
 
       // ---- level 2 on row z - 4d ----
@@ -542,7 +546,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
           if (rm[0] >= 0) lap[0] += drow[rm[0]];
           if (rm[1] >= 0) lap[1] += drow[rm[1]];
         }
-        const V2<T> pv = BG ? dq[(r + 5) % 9] : q0[r % 9];
+        const V2<T> pv = BG ? dq[wv][(r + 5) % 9][lane] : q0[r % 9];
         T g[2];
         if (BG) {
           g[0] = rmul(rmul(cur.k2.v[0], lap[0]), p.inv_dt2);
@@ -645,23 +649,29 @@ static int device_cus() {
 }
 
 // z chunking: one wave per (shot, strip, chunk), four shots per workgroup.
-// Picks the chunk height that minimises (resident rounds) x (rows a wave
-// marches), so that a launch fills the resident wave slots without a long
-// tail.  zc_fixed > 0 forces the chunk height.
+// Cost of a launch with nch chunks (calibrated on MI355X): rounds x m^e x
+// (zc + H), with m the workgroups on the busiest CU in a round, zc the chunk
+// height and H = 30 rows of halo traffic per two-step chunk (12 for one step).
+// e = 0.7 for the Born and adjoint kernels, 0.38 for the background kernel,
+// which gains more from a fuller CU.  One workgroup per CU (four waves) hides too
+// little latency, so m counts as at least 2.  zc_fixed > 0 forces the chunk height.
 template <typename T>
-static void chunking(Step<T>& p, int nsh, int nsteps, int wg_per_cu, int zc_fixed) {
+static void chunking(Step<T>& p, int mode, int nsh, int nsteps, int wg_per_cu, int zc_fixed) {
   const int nzp = p.L.nzp;
-  const long long cap = (long long)device_cus() * std::max(1, wg_per_cu);
+  const long long ncu = device_cus();
+  const long long cap = ncu * std::max(1, wg_per_cu);
   const long long cols = (long long)((nsh + 3) / 4) * p.L.nstrips;
+  const double ex = (mode == M_BG) ? 0.38 : 0.7;
+  const double halo = (nsteps == 2) ? 30.0 : 12.0;
   int best_zc = nzp;
   double best = 1e300;
-  for (int nch = 1; nch <= nzp; ++nch) {
+  for (int nch = 1; nch <= std::max(1, nzp / 4); ++nch) {
     const int zc = (nzp + nch - 1) / nch;
     if ((nzp + zc - 1) / zc != nch) continue;
     const long long wgs = cols * nch;
     const long long rounds = (wgs + cap - 1) / cap;
-    const double rows = (nsteps == 2) ? 2.0 * zc + 16.0 : zc + 8.0;
-    const double cost = (double)rounds * rows;
+    const long long m = (wgs + rounds * ncu - 1) / (rounds * ncu);
+    const double cost = (double)rounds * std::pow((double)std::max<long long>(m, 2), ex) * (zc + halo);
     if (cost < best) {
       best = cost;
       best_zc = zc;
@@ -684,7 +694,7 @@ static void go(Step<T> p, int nsh, int n, int hs1, int hs2, int cs, int cm, int 
       b = 1;
     occ = b;
   }
-  chunking(p, nsh, NS, occ, zc_fixed);
+  chunking(p, MODE, nsh, NS, occ, zc_fixed);
   hipLaunchKernelGGL((k_sweep2d<T, MODE, NS, CK>), dim3(xcd_grid(p.nwg)), dim3(256), 0, st, p, n, hs1, hs2, cs, cm);
 }
 
