@@ -184,8 +184,8 @@ __device__ __forceinline__ void update(const T lap[2], const V2<T>& c, const V2<
 }
 
 // Inputs of one loop iteration (level 1 on row z, level 2 on row z - 4d for the
-// march direction d = +-1), loaded one iteration ahead so that their latency
-// overlaps the previous row's work.
+// march direction d = +-1), loaded one or two iterations ahead so that their
+// latency overlaps the work of the rows before.
 // Every load is unconditional: rows outside the grid and lanes outside the
 // model fall outside their buffer resource and read zero.
 template <typename T>
@@ -446,8 +446,12 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
   __shared__ V2<T> dq[(BG && NS == 2) ? 4 : 1][9][(BG && NS == 2) ? LANES : 1];
 #pragma unroll
   for (int s = 0; s < 8; ++s) q0[s] = bld2(rI0, frow(zs + (s - 4) * d), 0u, T(0));
-  RowIn<T> cur, nxt;
+  // prefetch depth: two rows for the background kernel (fewer loads per row, more
+  // latency to cover), one row for the Born and adjoint kernels
+  constexpr int PF = BG ? 2 : 1;
+  RowIn<T> cur, nx1, nx2;   // inputs of this iteration and of the next PF
   fetch(zs, cur);
+  if (PF == 2) fetch(zs + d, nx1);
 
   for (int tb = 0; tb < nit; tb += 9) {
 #pragma unroll
@@ -455,7 +459,8 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
       const int t = tb + r;   // iteration: level 1 on row z, level 2 on row z - 4d
       if (t >= nit) break;
       const int z = zs + t * d;
-      fetch(z + d, nxt);
+      if (PF == 2) fetch(z + 2 * d, nx2);
+      else fetch(z + d, nx1);
       q0[(r + 8) % 9] = cur.q;
       const bool out_row = (z >= z0) && (z < z1);
 
@@ -583,7 +588,8 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
           }
         }
       }
-      cur = nxt;
+      cur = nx1;
+      if (PF == 2) nx1 = nx2;
     }
   }
   if (CK == CK_BF16 && BG && ck_max >= 0) {
