@@ -100,6 +100,15 @@ __device__ __forceinline__ V4<T> zero4() {
   return r;
 }
 
+// Workgroup barrier for an LDS exchange: orders this wave's LDS accesses around
+// the barrier without waiting for its global memory operations (a full
+// __syncthreads would also drain the loads in flight).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Damping coefficients of the leapfrog at a cell: a = 1/(1 + eta dt/2), b = (1 - eta dt/2) a.
 template <typename T>
 __device__ __forceinline__ void damping(T eta, T hdt, T& a, T& b) {

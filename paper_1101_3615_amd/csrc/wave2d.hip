@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
   int rbuf = 0;
   auto image = [&](int zm, const V2<double>& cw, const V2<double>& old) {
     red[rbuf][wv][lane] = cw;
-    __syncthreads();
+    lds_barrier();
     if (lane < 16) {
       V2<double> acc = old;
 #pragma unroll

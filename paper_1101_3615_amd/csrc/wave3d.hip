@@ -15,6 +15,48 @@
 
 namespace mp {
 
+// Buffer-resource access (raw buffers, hardware range check on the per-lane
+// offset: an inactive lane's offset lies past any resource, so its reads return
+// zero and its writes are dropped).  Word 3: gfx9-family raw-buffer configuration.
+using Rsrc3 = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x4_3 __attribute__((ext_vector_type(4)));
+constexpr unsigned OFF_NONE3 = 0x80000000u;
+__device__ __forceinline__ Rsrc3 rsrc3(const void* base, long long bytes) {
+  const int n = bytes >= 0xffffffffLL ? -1 : (int)(unsigned)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
+}
+__device__ __forceinline__ V4<float> bld4(Rsrc3 r, unsigned vo, unsigned so, float) {
+  const u32x4_3 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+  V4<float> o;
+  o.v[0] = __uint_as_float(v.x);
+  o.v[1] = __uint_as_float(v.y);
+  o.v[2] = __uint_as_float(v.z);
+  o.v[3] = __uint_as_float(v.w);
+  return o;
+}
+__device__ __forceinline__ V4<double> bld4(Rsrc3 r, unsigned vo, unsigned so, double) {
+  const u32x4_3 a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+  const u32x4_3 b = __builtin_amdgcn_raw_buffer_load_b128(r, vo + 16, so, 0);
+  V4<double> o;
+  o.v[0] = __longlong_as_double(((long long)a.y << 32) | a.x);
+  o.v[1] = __longlong_as_double(((long long)a.w << 32) | a.z);
+  o.v[2] = __longlong_as_double(((long long)b.y << 32) | b.x);
+  o.v[3] = __longlong_as_double(((long long)b.w << 32) | b.z);
+  return o;
+}
+__device__ __forceinline__ int depth3(int i, int n, int nb) { return max(max(nb - i, i - (n + nb - 1)), 0); }
+// a = 1 / (1 + e), b = (1 - e) a with e = ec * dd (dd: sum of squared layer depths)
+__device__ __forceinline__ void damp3(float ec, int dd, float& a, float& b) {
+  const float e = ec * (float)dd;
+  a = dd > 0 ? __builtin_amdgcn_rcpf(1.0f + e) : 1.0f;
+  b = (1.0f - e) * a;
+}
+__device__ __forceinline__ void damp3(double ec, int dd, double& a, double& b) {
+  const double e = ec * (double)dd;
+  a = dd > 0 ? 1.0 / (1.0 + e) : 1.0;
+  b = (1.0 - e) * a;
+}
+
 constexpr int TX = 64;   // x cells per tile
 constexpr int TY = 16;   // y rows per tile
 constexpr int PY = TY + 8;
@@ -100,14 +142,18 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
   const bool xmodany = xmod[0] || xmod[1] || xmod[2] || xmod[3];
   const bool ymod = (ym >= 0) && (ym < p.L.ny);
 
-  T exy[4];
-  bool xysponge = false;
-  const T ey = yin ? p.etay[y] : T(0);
+  // squared layer depths along x and y of the lane's cells (damping from the
+  // layer's closed form: e = eta_c (dx^2 + dy^2 + dz^2))
+  int dxy2[4];
+  const int dy = depth3(y, p.L.ny, p.L.nb);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    exy[i] = (xvalid[i] ? p.etax[x + i] : T(0)) + ey;
-    xysponge = xysponge || (exy[i] != T(0));
+    const int dx = depth3(x + i, p.L.nx, p.L.nb);
+    dxy2[i] = dx * dx + dy * dy;
   }
+  // tile interior: every cell of the 64 x 16 tile outside the layer in x and y
+  const int tx0 = tx * TX - XL, ty0 = ty * TY;
+  const bool tile_free = tx0 >= p.L.nb && tx0 + TX <= nxp - p.L.nb && ty0 >= p.L.nb && ty0 + TY <= nyp - p.L.nb;
 
   int sx = -1, sy = -1, sz = -1;
   if (MODE == M_FUSED || MODE == M_BG) {
@@ -137,12 +183,27 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
     Anext = p.du_prev + fo;
   }
 
+  // buffer resources on the shot's field slices: a lane adds its offset within a
+  // z plane (OFF_NONE3 outside the grid), a plane the uniform offset soff(z)
+  const long long sb = (long long)ls * p.L.fstride;
+  const long long fbytes3 = p.L.fstride * (long long)sizeof(T);
+  const Rsrc3 rAc = rsrc3((BGM ? p.u_cur : p.du_cur) + sb, fbytes3);
+  const Rsrc3 rAp = rsrc3((BGM ? p.u_inc : p.du_prev) + sb, fbytes3);   // increment / level n-1
+  const Rsrc3 rBc = rsrc3(p.du_cur + sb, fbytes3);
+  const Rsrc3 rBp = rsrc3(p.du_prev + sb, fbytes3);
+  const Rsrc3 rK = rsrc3(p.kappa, fbytes3);
+  const Rsrc3 rM = rsrc3(p.dmbar + (long long)p.dm_slot[shot] * p.L.fstride, fbytes3);
+  const unsigned esz = (unsigned)sizeof(T);
+  const unsigned lvo = act ? (unsigned)((long long)(y + GY) * pitch + XL + x) * esz : OFF_NONE3;
+  const unsigned hlo = hl_in ? (unsigned)((long long)(y + GY) * pitch + XL + x - 4) * esz : OFF_NONE3;
+  const unsigned hro = hr_in ? (unsigned)((long long)(y + GY) * pitch + XL + x + 4) * esz : OFF_NONE3;
+  auto soff = [&](int zz) -> unsigned { return (unsigned)((long long)SLACK + (long long)(zz + GZ) * plane) * esz; };
+
   V4<T> qa[9], qb[9];
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
-    const long long o = (long long)(z0 - 4 + s) * plane + colrow;
-    qa[s] = act ? ld4(Acur + o) : zero4<T>();
-    if (TWO) qb[s] = act ? ld4(Bcur + o) : zero4<T>();
+    qa[s] = bld4(rAc, lvo, soff(z0 - 4 + s), T(0));
+    if (TWO) qb[s] = bld4(rBc, lvo, soff(z0 - 4 + s), T(0));
   }
 
   // halo rows of the LDS plane: threads 0..127 field A, 128..255 field B
@@ -154,10 +215,11 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
   const int hx = tx * TX + hcol - XL;
   const bool hload = (hx >= 0) && (hx < nxp) && (hy >= 0) && (hy < nyp);
   const bool hfieldB = (tid >= 128);
+  const unsigned hvo = hload ? (unsigned)((long long)(hy + GY) * pitch + XL + hx) * esz : OFF_NONE3;
+  const unsigned hvoA = hfieldB ? OFF_NONE3 : hvo;
+  const unsigned hvoB = hfieldB ? hvo : OFF_NONE3;
 
   const long long kofs = (long long)SLACK + (long long)GZ * plane + (long long)GY * pitch + XL;
-  const T* kap = p.kappa + kofs;
-  const T* dmb = p.dmbar + (long long)p.dm_slot[shot] * p.L.fstride + kofs;
   const T* hist_n = p.hist + (long long)ls * p.hstride + (long long)hslot * p.L.mstride;
   double* img = (MODE == M_ADJ) ? p.img + (long long)shot * p.L.mstride : nullptr;
   T* hist_w = (MODE == M_FUSED || MODE == M_BG) ? const_cast<T*>(hist_n) : nullptr;
@@ -171,31 +233,32 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
       if (z >= z1) break;
       {
         const long long o = (long long)(z + 4) * plane + colrow;
-        qa[(r + 8) % 9] = act ? ld4(Acur + o) : zero4<T>();
-        if (TWO) qb[(r + 8) % 9] = act ? ld4(Bcur + o) : zero4<T>();
+        (void)o;
+        qa[(r + 8) % 9] = bld4(rAc, lvo, soff(z + 4), T(0));
+        if (TWO) qb[(r + 8) % 9] = bld4(rBc, lvo, soff(z + 4), T(0));
       }
       const long long oz = (long long)z * plane;
       // centre rows and y halo into LDS
       *reinterpret_cast<V4<T>*>(&PA[buf][yl + 4][c * 4]) = qa[(r + 4) % 9];
       if (TWO) *reinterpret_cast<V4<T>*>(&PB[buf][yl + 4][c * 4]) = qb[(r + 4) % 9];
+      const unsigned sz_ = soff(z);
       {
-        V4<T> hv = zero4<T>();
-        const T* src = hfieldB ? Bcur : Acur;
-        if ((TWO || !hfieldB) && hload) hv = ld4(src + oz + (long long)hy * pitch + hx);
+        V4<T> hv = bld4(rAc, hvoA, sz_, T(0));
+        if (TWO) {
+          const V4<T> hb = bld4(rBc, hvoB, sz_, T(0));
+          if (hfieldB) hv = hb;
+        }
         if (!hfieldB) *reinterpret_cast<V4<T>*>(&PA[buf][hlds][hcol]) = hv;
         else if (TWO) *reinterpret_cast<V4<T>*>(&PB[buf][hlds][hcol]) = hv;
       }
       // x halo of the lane's row
-      V4<T> ahl = zero4<T>(), ahr = zero4<T>(), bhl = zero4<T>(), bhr = zero4<T>();
-      if (hl_in) {
-        ahl = ld4(Acur + oz + colrow - 4);
-        if (TWO) bhl = ld4(Bcur + oz + colrow - 4);
+      const V4<T> ahl = bld4(rAc, hlo, sz_, T(0)), ahr = bld4(rAc, hro, sz_, T(0));
+      V4<T> bhl = zero4<T>(), bhr = zero4<T>();
+      if (TWO) {
+        bhl = bld4(rBc, hlo, sz_, T(0));
+        bhr = bld4(rBc, hro, sz_, T(0));
       }
-      if (hr_in) {
-        ahr = ld4(Acur + oz + colrow + 4);
-        if (TWO) bhr = ld4(Bcur + oz + colrow + 4);
-      }
-      __syncthreads();
+      lds_barrier();
       T lapA[4], lapB[4];
       lap_row(qa, r, ahl, ahr, PA[buf], yl, c * 4, p, lapA);
       if (TWO) lap_row(qb, r, bhl, bhr, PB[TWO ? buf : 0], yl, c * 4, p, lapB);
@@ -208,7 +271,7 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
         for (int i = 0; i < 4; ++i)
           if (x + i == sx) lapA[i] += wsrc;
       }
-      const int rp = p.recplane[z];
+      const int rp = (z < p.rec_lo || z > p.rec_hi) ? -1 : p.recplane[z];
       const bool recrow = rp >= 0;
       int rm[4] = {-1, -1, -1, -1};
       if (recrow) {
@@ -225,10 +288,10 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
         }
       }
 
-      const V4<T> kap4 = ld4(kap + orow);
-      const T ez = p.etaz[z];
+      const V4<T> kap4 = bld4(rK, lvo, sz_, T(0));
+      const int dz = depth3(z, p.L.nz, p.L.nb);
       T a[4], b[4];
-      if (ez == T(0) && !xysponge) {
+      if (tile_free && dz == 0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           a[i] = T(1);
@@ -236,7 +299,7 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
         }
       } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) damping(exy[i] + ez, p.hdt, a[i], b[i]);
+        for (int i = 0; i < 4; ++i) damp3(p.eta_c, dxy2[i] + dz * dz, a[i], b[i]);
       }
 
       const int zm = z - p.L.nb;
@@ -259,9 +322,9 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
         }
       }
 
-      const V4<T> aprev = ld4((BGM ? Ainc : Anext) + orow);
+      const V4<T> aprev = bld4(rAp, lvo, sz_, T(0));
       V4<T> adm = zero4<T>();
-      if (MODE == M_BORN) adm = ld4(dmb + orow);
+      if (MODE == M_BORN) adm = bld4(rM, lvo, sz_, T(0));
       V4<T> anew, ainc;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -288,8 +351,8 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
 
       V4<T> bnew;
       if (TWO) {
-        const V4<T> bprev = ld4(Bnext + orow);
-        const V4<T> dm4 = ld4(dmb + orow);
+        const V4<T> bprev = bld4(rBp, lvo, sz_, T(0));
+        const V4<T> dm4 = bld4(rM, lvo, sz_, T(0));
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const T cc = qb[(r + 4) % 9].v[i];
