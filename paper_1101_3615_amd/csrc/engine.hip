@@ -259,6 +259,10 @@ class EngineT final : public Engine {
     p.c2 = (T)(FD8[2] * ih2);
     p.c3 = (T)(FD8[3] * ih2);
     p.c4 = (T)(FD8[4] * ih2);
+    p.t3 = (T)(FD8[4] * ih2);
+    p.t2 = (T)((FD8[3] + FD8[4]) * ih2);
+    p.t1 = (T)((FD8[2] + FD8[3] + FD8[4]) * ih2);
+    p.t0 = (T)((FD8[1] + FD8[2] + FD8[3] + FD8[4]) * ih2);
     p.hdt = (T)(0.5 * cfg_.dt);
     p.inv_dt2 = (T)(1.0 / (cfg_.dt * cfg_.dt));
     p.kappa = kappa_.as<T>();

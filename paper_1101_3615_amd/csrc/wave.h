@@ -27,6 +27,7 @@ template <typename T>
 struct Step {
   Layout L;
   T c0x, c1, c2, c3, c4;     // 8th-order weights / h^2; c0x = ndim * w0 / h^2
+  T t0, t1, t2, t3;          // tail sums t_k = (c_{k+1} + ... + c_4) / h^2 (2D first-difference form)
   T hdt;                     // dt / 2
   T inv_dt2;                 // 1 / dt^2
   const T* kappa;            // field layout, shared by all shots

@@ -119,45 +119,51 @@ __device__ __forceinline__ double mov_shl1<double>(double v) {
   const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-template <typename T>
-__device__ __forceinline__ void xnb(const V2<T>& C, T w[10]) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const T l1 = mov_shr1(C.v[i]);
-    const T r1 = mov_shl1(C.v[i]);
-    w[i] = mov_shr1(l1);
-    w[2 + i] = l1;
-    w[4 + i] = C.v[i];
-    w[6 + i] = r1;
-    w[8 + i] = mov_shl1(r1);
-  }
-}
-
-// 8th-order Laplacian of the lane's two cells in difference form:
-// sum_j c_j [(u_{x-j} - u) + (u_{x+j} - u) + (u_{z-j} - u) + (u_{z+j} - u)], the
-// smallest weights first.  Algebraically c0 u + sum_j c_j (pairs); in FP32 it
-// rounds relative to the differences instead of to u, which keeps smooth,
-// well-resolved fields accurate over thousands of steps.  q[(rb + j) % 9] holds
-// row (centre - 4 + j).
-template <typename T>
-__device__ __forceinline__ void lap2(const T (&w)[10], const V2<T>* q, int rb, const Step<T>& p, T out[2]) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const T c = w[4 + i];
-    T s = p.c4 * (((w[0 + i] - c) + (w[8 + i] - c)) + ((q[(rb + 0) % 9].v[i] - c) + (q[(rb + 8) % 9].v[i] - c)));
-    s += p.c3 * (((w[1 + i] - c) + (w[7 + i] - c)) + ((q[(rb + 1) % 9].v[i] - c) + (q[(rb + 7) % 9].v[i] - c)));
-    s += p.c2 * (((w[2 + i] - c) + (w[6 + i] - c)) + ((q[(rb + 2) % 9].v[i] - c) + (q[(rb + 6) % 9].v[i] - c)));
-    s += p.c1 * (((w[3 + i] - c) + (w[5 + i] - c)) + ((q[(rb + 3) % 9].v[i] - c) + (q[(rb + 5) % 9].v[i] - c)));
-    out[i] = s;
-  }
-}
-
 // Products and fused multiply-adds with the rounding spelled out, so that the
 // damped and undamped forms of the update below give the same bits where a = b = 1.
 __device__ __forceinline__ float rmul(float a, float b) { return __fmul_rn(a, b); }
 __device__ __forceinline__ double rmul(double a, double b) { return __dmul_rn(a, b); }
 __device__ __forceinline__ float rfma(float a, float b, float c) { return __fmaf_rn(a, b, c); }
 __device__ __forceinline__ double rfma(double a, double b, double c) { return __fma_rn(a, b, c); }
+
+// First differences along x around the lane's two cells (2L, 2L+1):
+// X[j] = u_{2L-3+j} - u_{2L-4+j}, j = 0..8 (lanes L-2 .. L+2 via DPP shifts).
+template <typename T>
+__device__ __forceinline__ void xdiff(const V2<T>& C, T X[9]) {
+  const T e0 = C.v[1] - C.v[0];
+  const T e1 = mov_shl1(C.v[0]) - C.v[1];
+  X[4] = e0;
+  X[5] = e1;
+  X[2] = mov_shr1(e0);
+  X[3] = mov_shr1(e1);
+  X[0] = mov_shr1(X[2]);
+  X[1] = mov_shr1(X[3]);
+  X[6] = mov_shl1(e0);
+  X[7] = mov_shl1(e1);
+  X[8] = mov_shl1(X[6]);
+}
+
+// 8th-order Laplacian of the lane's two cells from first differences.  With
+// e_m = u_{m+1} - u_m, the pair term (u_{x+j} - u_x) + (u_{x-j} - u_x) equals
+// sum_{k<j} (e_{x+k} - e_{x-1-k}), so
+//   sum_j c_j [pairs along x and z] = sum_k t_k [(e_{x+k} - e_{x-1-k}) + (same along z)]
+// with the tail sums t_k = c_{k+1} + ... + c_4 (the smallest first).  In FP32 it
+// rounds relative to the differences, not to u, which keeps smooth, well-resolved
+// fields accurate over thousands of steps, and each difference is formed once per
+// cell instead of once per weight.  E[(rb + m) % 9] holds row(m + 1) - row(m) of
+// the queue (rows in march order, the centre is row 4); a march in the other
+// direction negates every difference, which leaves each result bit unchanged.
+template <typename T>
+__device__ __forceinline__ void lapE(const T (&X)[9], const V2<T>* E, int rb, const Step<T>& p, T out[2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    T s = p.t3 * ((X[7 + i] - X[0 + i]) + (E[(rb + 7) % 9].v[i] - E[(rb + 0) % 9].v[i]));
+    s = rfma(p.t2, (X[6 + i] - X[1 + i]) + (E[(rb + 6) % 9].v[i] - E[(rb + 1) % 9].v[i]), s);
+    s = rfma(p.t1, (X[5 + i] - X[2 + i]) + (E[(rb + 5) % 9].v[i] - E[(rb + 2) % 9].v[i]), s);
+    s = rfma(p.t0, (X[4 + i] - X[3 + i]) + (E[(rb + 4) % 9].v[i] - E[(rb + 3) % 9].v[i]), s);
+    out[i] = s;
+  }
+}
 
 // Leapfrog update of one pair with damping (a, b).
 //   background: t = kappa Lam, nd = b D + a t, nv = u + nd
@@ -441,11 +447,21 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
   };
 
   V2<T> q0[9], q1[9];   // level-0 rows, level-1 rows
+  V2<T> e0[9], e1[9];   // their first differences along the march
+  auto diff = [](const V2<T>& a, const V2<T>& b) {
+    V2<T> r;
+    r.v[0] = a.v[0] - b.v[0];
+    r.v[1] = a.v[1] - b.v[1];
+    return r;
+  };
   // background: the increment D^{n+1} of level-1 rows, read back four rows later
   // at the centre of level 2 (kept in LDS: each wave reads only its own entries)
   __shared__ V2<T> dq[(BG && NS == 2) ? 4 : 1][9][(BG && NS == 2) ? LANES : 1];
 #pragma unroll
   for (int s = 0; s < 8; ++s) q0[s] = bld2(rI0, frow(zs + (s - 4) * d), 0u, T(0));
+#pragma unroll
+  for (int s = 0; s < 7; ++s) e0[s] = diff(q0[s + 1], q0[s]);
+  if (NS == 2) q1[8] = zero2<T>();
   // prefetch depth: two rows for the background kernel (fewer loads per row, more
   // latency to cover), one row for the Born and adjoint kernels
   constexpr int PF = BG ? 2 : 1;
@@ -462,16 +478,17 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
       if (PF == 2) fetch(z + 2 * d, nx2);
       else fetch(z + d, nx1);
       q0[(r + 8) % 9] = cur.q;
+      e0[(r + 7) % 9] = diff(q0[(r + 8) % 9], q0[(r + 7) % 9]);
       const bool out_row = (z >= z0) && (z < z1);
 
       // ---- level 1 on row z ----
       if (z >= 0 && z < nzp) {
         const unsigned so = (unsigned)z * rowb;
         const V2<T>& c0 = q0[(r + 4) % 9];
-        T w[10];
-        xnb(c0, w);
+        T X[9];
+        xdiff(c0, X);
         T lap[2];
-        lap2(w, q0, r, p, lap);
+        lapE(X, e0, r, p, lap);
         if (BG && z == sz) {
           const T ws = p.wav[n];
           if (x == sx) lap[0] += ws;
@@ -529,16 +546,17 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
         q1[r] = zero2<T>();
         if (BG) dq[wv][r][lane] = zero2<T>();
       }
+      if (NS == 2) e1[(r + 8) % 9] = diff(q1[r], q1[(r + 8) % 9]);
 
       // ---- level 2 on row z - 4d ----
       if (NS == 2 && t >= 8) {
         const int y = z - 4 * d;
         const unsigned so = (unsigned)y * rowb;
         const V2<T>& c1 = q1[(r + 5) % 9];
-        T w[10];
-        xnb(c1, w);
+        T X[9];
+        xdiff(c1, X);
         T lap[2];
-        lap2(w, q1, r + 1, p, lap);
+        lapE(X, e1, r + 1, p, lap);
         if (BG && y == sz) {
           const T ws = p.wav[n + 1];
           if (x == sx) lap[0] += ws;
