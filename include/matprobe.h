@@ -127,7 +127,9 @@ typedef struct mp_stats {
 } mp_stats;
 
 /* Create a context for one grid and acquisition.  Validates every index and
- * option; allocates only small tables.  *out receives the context. */
+ * option; allocates only small tables.  *out receives the context.
+ * MP_EINVAL also for grids whose padded wavefield slice or FP64 model-grid image
+ * reaches 1 GiB (the sweeps address them with 32-bit buffer offsets). */
 int mp_create(const mp_grid* g, const mp_acq* a, const mp_opts* o, mp_ctx** out);
 void mp_destroy(mp_ctx* ctx);
 

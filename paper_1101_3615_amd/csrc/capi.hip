@@ -126,6 +126,19 @@ int mp_create(const mp_grid* g, const mp_acq* a, const mp_opts* o, mp_ctx** out)
   }
   if (o->snap == MP_SNAP_CKPT_BF16 && o->dtype != MP_F32)
     return fail(MP_EUNSUPPORTED, "BF16 checkpoints are built for FP32 fields");
+  {
+    // The sweeps address one field slice and one model-grid image with 32-bit
+    // buffer offsets whose out-of-grid values must stay past the end of the
+    // buffer: both stay below 1 GiB.
+    const long long esz = o->dtype == MP_F32 ? 4 : 8;
+    const long long nxp = nx + 2LL * g->nb, nyp = ny + 2LL * g->nb, nzp = nz + 2LL * g->nb;
+    long long field;
+    if (nd == 2) field = (nxp + 176) * (nzp + 8) + 128;
+    else field = ((nxp + 8 + 63) / 64 * 64) * ((nyp + 15) / 16 * 16 + 8) * (nzp + 8) + 128;
+    const long long image = ((long long)nx + 40) * ny * (nz + (long long)g->nb) * 8;
+    if (field * esz >= (1LL << 30) || image >= (1LL << 30))
+      return fail(MP_EINVAL, "grid too large: one wavefield slice and the FP64 image must each stay below 1 GiB");
+  }
 
   mp_ctx* ctx = new mp_ctx();
   Config& c = ctx->cfg;

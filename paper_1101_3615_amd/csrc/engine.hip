@@ -285,10 +285,14 @@ class EngineT final : public Engine {
     p.nt = cfg_.nt;
     p.shot0 = s0;
     if (cfg_.ndim == 3) {
-      // one workgroup per 64 x 16 tile and z chunk
+      // one workgroup per 64 x 16 tile and z chunk: as few chunks as keep about
+      // 2048 workgroups in the launch (each chunk rereads 8 planes of its field)
       int zc = zc_target_;
       const long long tiles = (long long)nsh * L_.nstrips * L_.nytiles;
-      if (zc <= 0) zc = (int)std::max<long long>(8, std::min<long long>(64, (long long)L_.nzp * tiles / 2048));
+      if (zc <= 0) {
+        const long long want = std::min<long long>((2048 + tiles - 1) / tiles, std::max(1, L_.nzp / 8));
+        zc = (int)((L_.nzp + want - 1) / want);
+      }
       p.nchunks = (L_.nzp + zc - 1) / zc;
       p.zc = (L_.nzp + p.nchunks - 1) / p.nchunks;
       p.ngroups = 1;

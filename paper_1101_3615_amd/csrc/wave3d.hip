@@ -9,7 +9,14 @@
 //                 loaded by the first and last lane of the row;
 //   y-neighbours: the tile's centre plane plus 4 halo rows above and below,
 //                 staged in LDS (double buffered: one barrier per plane).
+// Every input of a plane (queue row, halos, kappa, previous level, g, image) is
+// loaded through buffer resources one plane ahead; lanes and planes outside the
+// grid read zero from the hardware range check instead of branching.  Workgroups
+// are persistent and walk their XCD's tiles x-fastest, so tiles that share halo
+// lines run on one L2 at the same time.
 // The arithmetic per cell is that of the 2D kernel with the y axis added.
+#include <algorithm>
+
 #include "common.h"
 #include "wave.h"
 
@@ -21,12 +28,17 @@ namespace mp {
 using Rsrc3 = __amdgpu_buffer_rsrc_t;
 typedef unsigned int u32x4_3 __attribute__((ext_vector_type(4)));
 constexpr unsigned OFF_NONE3 = 0x80000000u;
+// cache policy of the data that no other workgroup rereads soon (outputs, the
+// cell's own previous level, g, image): non-temporal, so that L2 keeps the field
+// rows that neighbouring tiles read as halos
+constexpr int NT3 = 2;
 __device__ __forceinline__ Rsrc3 rsrc3(const void* base, long long bytes) {
   const int n = bytes >= 0xffffffffLL ? -1 : (int)(unsigned)bytes;
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
 }
+template <int CP = 0>
 __device__ __forceinline__ V4<float> bld4(Rsrc3 r, unsigned vo, unsigned so, float) {
-  const u32x4_3 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+  const u32x4_3 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, CP);
   V4<float> o;
   o.v[0] = __uint_as_float(v.x);
   o.v[1] = __uint_as_float(v.y);
@@ -34,15 +46,41 @@ __device__ __forceinline__ V4<float> bld4(Rsrc3 r, unsigned vo, unsigned so, flo
   o.v[3] = __uint_as_float(v.w);
   return o;
 }
+template <int CP = 0>
 __device__ __forceinline__ V4<double> bld4(Rsrc3 r, unsigned vo, unsigned so, double) {
-  const u32x4_3 a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
-  const u32x4_3 b = __builtin_amdgcn_raw_buffer_load_b128(r, vo + 16, so, 0);
+  const u32x4_3 a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, CP);
+  const u32x4_3 b = __builtin_amdgcn_raw_buffer_load_b128(r, vo + 16, so, CP);
   V4<double> o;
   o.v[0] = __longlong_as_double(((long long)a.y << 32) | a.x);
   o.v[1] = __longlong_as_double(((long long)a.w << 32) | a.z);
   o.v[2] = __longlong_as_double(((long long)b.y << 32) | b.x);
   o.v[3] = __longlong_as_double(((long long)b.w << 32) | b.z);
   return o;
+}
+template <int CP = 0>
+__device__ __forceinline__ void bst4(const V4<float>& a, Rsrc3 r, unsigned vo, unsigned so) {
+  u32x4_3 v;
+  v.x = __float_as_uint(a.v[0]);
+  v.y = __float_as_uint(a.v[1]);
+  v.z = __float_as_uint(a.v[2]);
+  v.w = __float_as_uint(a.v[3]);
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, CP);
+}
+template <int CP = 0>
+__device__ __forceinline__ void bst4(const V4<double>& a, Rsrc3 r, unsigned vo, unsigned so) {
+  u32x4_3 v0, v1;
+  const long long b0 = __double_as_longlong(a.v[0]), b1 = __double_as_longlong(a.v[1]);
+  const long long b2 = __double_as_longlong(a.v[2]), b3 = __double_as_longlong(a.v[3]);
+  v0.x = (unsigned)b0;
+  v0.y = (unsigned)(b0 >> 32);
+  v0.z = (unsigned)b1;
+  v0.w = (unsigned)(b1 >> 32);
+  v1.x = (unsigned)b2;
+  v1.y = (unsigned)(b2 >> 32);
+  v1.z = (unsigned)b3;
+  v1.w = (unsigned)(b3 >> 32);
+  __builtin_amdgcn_raw_buffer_store_b128(v0, r, vo, so, CP);
+  __builtin_amdgcn_raw_buffer_store_b128(v1, r, vo + 16, so, CP);
 }
 __device__ __forceinline__ int depth3(int i, int n, int nb) { return max(max(nb - i, i - (n + nb - 1)), 0); }
 // a = 1 / (1 + e), b = (1 - e) a with e = ec * dd (dd: sum of squared layer depths)
@@ -59,18 +97,20 @@ __device__ __forceinline__ void damp3(double ec, int dd, double& a, double& b) {
 
 constexpr int TX = 64;   // x cells per tile
 constexpr int TY = 16;   // y rows per tile
-constexpr int PY = TY + 8;
 
+// Laplacian of the lane's four cells.  x: DPP row shifts, the first and last lane
+// of a 16-lane row taking the halo xh; y: the LDS plane P (tile rows plus four
+// halo rows above and below); z: the register queue.
 template <typename T>
-__device__ __forceinline__ void lap_row(const V4<T>* qa, int r, const V4<T>& hl, const V4<T>& hr,
-                                        const T (*P)[TX], int yl, int c4, const Step<T>& p, T out[4]) {
+__device__ __forceinline__ void lap_row(const V4<T>* qa, int r, const V4<T>& xh, const T (*P)[TX], int yl,
+                                        int c4, const Step<T>& p, T out[4]) {
   const V4<T>& C = qa[(r + 4) % 9];
   T w[12];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    w[i] = rshr1(C.v[i], hl.v[i]);
+    w[i] = rshr1(C.v[i], xh.v[i]);
     w[4 + i] = C.v[i];
-    w[8 + i] = rshl1(C.v[i], hr.v[i]);
+    w[8 + i] = rshl1(C.v[i], xh.v[i]);
   }
   V4<T> ym[4], yp[4];
 #pragma unroll
@@ -97,22 +137,36 @@ __device__ __forceinline__ void lap_row(const V4<T>* qa, int r, const V4<T>& hl,
 template <typename T, int MODE, int CK>
 __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int ck_store, int ck_max) {
   constexpr bool TWO = (MODE == M_FUSED);
-  __shared__ __align__(32) T PA[2][PY][TX];
-  __shared__ __align__(32) T PB[TWO ? 2 : 1][TWO ? PY : 1][TX];
+  // LDS plane per field: the tile's rows plus four halo rows above and below
+  // (double buffered: one barrier per plane)
+  constexpr int NB = TWO ? 2 : 1;
+  __shared__ __align__(32) T PL[NB][2][TY + 8][TX];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int c = lane & 15;
   const int yl = wv * 4 + (lane >> 4);     // 0..15 within the tile
-  const int item = xcd_item(p.nwg);
-  if (item >= p.nwg) return;
-  const int chunk = item % p.nchunks;
-  int rest = item / p.nchunks;
+  // Persistent workgroups: the grid holds as many workgroups as the device keeps
+  // resident (a multiple of 8), workgroup b runs on XCD b % 8 and walks that XCD's
+  // contiguous range of items with the stride of the XCD's workgroups, so the
+  // workgroups that run together start their items together and march in step.
+  const int per = (p.nwg + 7) >> 3;
+  const int xcd = (int)(blockIdx.x & 7u);
+  const int spx = (int)(gridDim.x >> 3);
+  int buf = 0;   // LDS buffer parity, continued across items
+  for (int k = (int)(blockIdx.x >> 3); k < per; k += spx) {
+  const int item = xcd * per + k;
+  if (item >= p.nwg) break;
+  // x tiles fastest, then y tiles: the workgroups that run together on one XCD
+  // cover whole xy planes of a shot's chunk, so the halo rows and columns a tile
+  // reads were fetched into that XCD's L2 by its neighbours (marching in step)
+  const int tx = item % p.L.nstrips;
+  int rest = item / p.L.nstrips;
   const int ty = rest % p.L.nytiles;
   rest /= p.L.nytiles;
-  const int tx = rest % p.L.nstrips;
-  const int ls = rest / p.L.nstrips;
+  const int chunk = rest % p.nchunks;
+  const int ls = rest / p.nchunks;
   const int z0 = chunk * p.zc;
   const int z1 = min(z0 + p.zc, p.L.nzp);
 
@@ -126,8 +180,6 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
   const bool act = xin && yin;
   const bool hl_in = (c == 0) && (x - 4 >= 0) && (x - 4 < nxp) && yin;
   const bool hr_in = (c == 15) && (x + 4 < nxp) && yin;
-  const long long fo = (long long)ls * p.L.fstride + SLACK + (long long)GZ * plane + (long long)GY * pitch + XL;
-  const long long colrow = (long long)y * pitch + x;    // within a plane
   const int shot = p.shot0 + ls;
 
   bool xvalid[4];
@@ -138,7 +190,6 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
   bool xmod[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) xmod[i] = (xm + i >= 0) && (xm + i < p.L.nx);
-  const bool xmodall = xmod[0] && xmod[1] && xmod[2] && xmod[3];
   const bool xmodany = xmod[0] || xmod[1] || xmod[2] || xmod[3];
   const bool ymod = (ym >= 0) && (ym < p.L.ny);
 
@@ -165,216 +216,202 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
 
   // background in increment form (see the 2D kernel)
   constexpr bool BGM = (MODE == M_FUSED || MODE == M_BG);
-  const T* Acur;
-  T* Anext;
-  T* Ainc = nullptr;
-  const T* Bcur = nullptr;
-  T* Bnext = nullptr;
-  if (BGM) {
-    Acur = p.u_cur + fo;
-    Anext = p.u_next + fo;
-    Ainc = p.u_inc + fo;
-    if (MODE == M_FUSED) {
-      Bcur = p.du_cur + fo;
-      Bnext = p.du_prev + fo;
-    }
-  } else {
-    Acur = p.du_cur + fo;
-    Anext = p.du_prev + fo;
-  }
 
-  // buffer resources on the shot's field slices: a lane adds its offset within a
-  // z plane (OFF_NONE3 outside the grid), a plane the uniform offset soff(z)
+  // Buffer resources on the shot's field slices: a lane adds its offset within a
+  // z plane (OFF_NONE3 outside the grid: reads zero, writes dropped), a plane the
+  // uniform offset soff(z).  Field A is the background (u, D) or the single wave
+  // field of the Born / adjoint sweeps, B the Born field of the fused sweep.
   const long long sb = (long long)ls * p.L.fstride;
   const long long fbytes3 = p.L.fstride * (long long)sizeof(T);
   const Rsrc3 rAc = rsrc3((BGM ? p.u_cur : p.du_cur) + sb, fbytes3);
+  const Rsrc3 rAn = rsrc3((BGM ? p.u_next : p.du_prev) + sb, fbytes3);   // level n+1 (in place over n-1)
   const Rsrc3 rAp = rsrc3((BGM ? p.u_inc : p.du_prev) + sb, fbytes3);   // increment / level n-1
-  const Rsrc3 rBc = rsrc3(p.du_cur + sb, fbytes3);
-  const Rsrc3 rBp = rsrc3(p.du_prev + sb, fbytes3);
+  const Rsrc3 rBc = rsrc3(TWO ? p.du_cur + sb : p.u_cur, TWO ? fbytes3 : 0);
+  const Rsrc3 rBp = rsrc3(TWO ? p.du_prev + sb : p.u_cur, TWO ? fbytes3 : 0);
   const Rsrc3 rK = rsrc3(p.kappa, fbytes3);
   const Rsrc3 rM = rsrc3(p.dmbar + (long long)p.dm_slot[shot] * p.L.fstride, fbytes3);
   const unsigned esz = (unsigned)sizeof(T);
   const unsigned lvo = act ? (unsigned)((long long)(y + GY) * pitch + XL + x) * esz : OFF_NONE3;
-  const unsigned hlo = hl_in ? (unsigned)((long long)(y + GY) * pitch + XL + x - 4) * esz : OFF_NONE3;
-  const unsigned hro = hr_in ? (unsigned)((long long)(y + GY) * pitch + XL + x + 4) * esz : OFF_NONE3;
+  // x halo: the first lane of a 16-lane row loads the 4 cells left of the row,
+  // the last lane the 4 cells right of it
+  const unsigned xvo = hl_in   ? (unsigned)((long long)(y + GY) * pitch + XL + x - 4) * esz
+                       : hr_in ? (unsigned)((long long)(y + GY) * pitch + XL + x + 4) * esz
+                               : OFF_NONE3;
   auto soff = [&](int zz) -> unsigned { return (unsigned)((long long)SLACK + (long long)(zz + GZ) * plane) * esz; };
+  // model-grid resources (g slot of the shot, FP64 image of the shot): the plane
+  // offset is added to the lane offset as an unsigned value, so planes above or
+  // below the model wrap past the end of the resource and read zero
+  const long long hoff = (long long)ls * p.hstride + (long long)hslot * p.L.mstride;
+  const long long mbytes3 = p.L.mstride * (long long)sizeof(T);
+  const Rsrc3 rG = rsrc3(hslot >= 0 ? p.hist + hoff : p.hist, hslot >= 0 ? mbytes3 : 0);
+  const Rsrc3 rI = rsrc3(MODE == M_ADJ ? p.img + (long long)shot * p.L.mstride : p.img,
+                         MODE == M_ADJ ? p.L.mstride * 8LL : 0);
+  const bool mlane = act && ymod && xmodany;
+  const unsigned gvo = mlane ? (unsigned)((long long)ym * p.L.mpitch + xm) * esz : OFF_NONE3;
+  const unsigned ivo = mlane ? (unsigned)((long long)ym * p.L.mpitch + xm) * 8u : OFF_NONE3;
+  const unsigned gplane = (unsigned)(p.L.mplane * (long long)esz);
+  const unsigned iplane = (unsigned)(p.L.mplane * 8LL);
+  const int nb = p.L.nb;
 
+  // halo rows of the LDS plane: waves 0-1 load field A, waves 2-3 field B
+  const int wvu = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool hfieldB = wvu >= 2;
+  const int ht = tid & 127;
+  const int hrow = ht >> 4;                 // 0..3: rows -4..-1, 4..7: rows TY..TY+3
+  const int hcol = (ht & 15) * 4;
+  const int hy = (hrow < 4) ? ty * TY - 4 + hrow : ty * TY + TY + (hrow - 4);
+  const int hlds = (hrow < 4) ? hrow : TY + hrow;   // row of the LDS plane
+  const int hx = tx * TX + hcol - XL;
+  const bool hload = (hx >= 0) && (hx < nxp) && (hy >= 0) && (hy < nyp) && (TWO || !hfieldB);
+  const unsigned hvo = hload ? (unsigned)((long long)(hy + GY) * pitch + XL + hx) * esz : OFF_NONE3;
+  const Rsrc3 rHv = hfieldB ? rBc : rAc;
+
+  // Inputs of one z plane.  FP32 sweeps load them one plane ahead, so that their
+  // latency overlaps the work on the plane before; FP64 sweeps (small test grids,
+  // twice the registers) load them at the start of the plane.
+  struct In3 {
+    V4<T> qa, qb;          // plane z + 4 of fields A, B (enters the queue)
+    V4<T> hv;              // y-halo row of plane z (field A or B)
+    V4<T> xa, xb;          // x halos of plane z
+    V4<T> kap, ap, bp, dm; // kappa, A increment / level n-1, B level n-1, perturbation
+    V4<T> g;               // Born / adjoint: g of plane z
+    V4<double> im;         // adjoint: image of plane z
+  };
+  auto fetch = [&](int z, In3& f) {
+    const unsigned s = soff(z);
+    f.qa = bld4(rAc, lvo, soff(z + 4), T(0));
+    if (TWO) f.qb = bld4(rBc, lvo, soff(z + 4), T(0));
+    f.hv = bld4(rHv, hvo, s, T(0));
+    f.xa = bld4(rAc, xvo, s, T(0));
+    if (TWO) f.xb = bld4(rBc, xvo, s, T(0));
+    f.kap = bld4(rK, lvo, s, T(0));
+    f.ap = bld4<NT3>(rAp, lvo, s, T(0));
+    if (TWO) f.bp = bld4<NT3>(rBp, lvo, s, T(0));
+    if (TWO || MODE == M_BORN) f.dm = bld4<NT3>(rM, lvo, s, T(0));
+    const unsigned zm = (unsigned)(z - nb);
+    if (MODE == M_BORN || MODE == M_ADJ) f.g = bld4<NT3>(rG, gvo + zm * gplane, 0u, T(0));
+    if (MODE == M_ADJ) f.im = bld4<NT3>(rI, ivo + zm * iplane, 0u, double(0));
+  };
+  constexpr bool PF3 = sizeof(T) == 4;
+
+  float mx0 = 0.0f, mx1 = 0.0f;
   V4<T> qa[9], qb[9];
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     qa[s] = bld4(rAc, lvo, soff(z0 - 4 + s), T(0));
     if (TWO) qb[s] = bld4(rBc, lvo, soff(z0 - 4 + s), T(0));
   }
-
-  // halo rows of the LDS plane: threads 0..127 field A, 128..255 field B
-  const int ht = tid & 127;
-  const int hrow = ht >> 4;                 // 0..7
-  const int hcol = (ht & 15) * 4;
-  const int hy = (hrow < 4) ? ty * TY - 4 + hrow : ty * TY + TY + (hrow - 4);
-  const int hlds = (hrow < 4) ? hrow : TY + hrow;
-  const int hx = tx * TX + hcol - XL;
-  const bool hload = (hx >= 0) && (hx < nxp) && (hy >= 0) && (hy < nyp);
-  const bool hfieldB = (tid >= 128);
-  const unsigned hvo = hload ? (unsigned)((long long)(hy + GY) * pitch + XL + hx) * esz : OFF_NONE3;
-  const unsigned hvoA = hfieldB ? OFF_NONE3 : hvo;
-  const unsigned hvoB = hfieldB ? hvo : OFF_NONE3;
-
-  const long long kofs = (long long)SLACK + (long long)GZ * plane + (long long)GY * pitch + XL;
-  const T* hist_n = p.hist + (long long)ls * p.hstride + (long long)hslot * p.L.mstride;
-  double* img = (MODE == M_ADJ) ? p.img + (long long)shot * p.L.mstride : nullptr;
-  T* hist_w = (MODE == M_FUSED || MODE == M_BG) ? const_cast<T*>(hist_n) : nullptr;
-  float mx0 = 0.0f, mx1 = 0.0f;
-  int buf = 0;
+  In3 cur, nxt;
+  if (PF3) fetch(z0, cur);
 
   for (int zb = z0; zb < z1; zb += 9) {
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
       const int z = zb + r;
-      if (z >= z1) break;
-      {
-        const long long o = (long long)(z + 4) * plane + colrow;
-        (void)o;
-        qa[(r + 8) % 9] = bld4(rAc, lvo, soff(z + 4), T(0));
-        if (TWO) qb[(r + 8) % 9] = bld4(rBc, lvo, soff(z + 4), T(0));
-      }
-      const long long oz = (long long)z * plane;
-      // centre rows and y halo into LDS
-      *reinterpret_cast<V4<T>*>(&PA[buf][yl + 4][c * 4]) = qa[(r + 4) % 9];
-      if (TWO) *reinterpret_cast<V4<T>*>(&PB[buf][yl + 4][c * 4]) = qb[(r + 4) % 9];
-      const unsigned sz_ = soff(z);
-      {
-        V4<T> hv = bld4(rAc, hvoA, sz_, T(0));
-        if (TWO) {
-          const V4<T> hb = bld4(rBc, hvoB, sz_, T(0));
-          if (hfieldB) hv = hb;
-        }
-        if (!hfieldB) *reinterpret_cast<V4<T>*>(&PA[buf][hlds][hcol]) = hv;
-        else if (TWO) *reinterpret_cast<V4<T>*>(&PB[buf][hlds][hcol]) = hv;
-      }
-      // x halo of the lane's row
-      const V4<T> ahl = bld4(rAc, hlo, sz_, T(0)), ahr = bld4(rAc, hro, sz_, T(0));
-      V4<T> bhl = zero4<T>(), bhr = zero4<T>();
-      if (TWO) {
-        bhl = bld4(rBc, hlo, sz_, T(0));
-        bhr = bld4(rBc, hro, sz_, T(0));
-      }
-      lds_barrier();
-      T lapA[4], lapB[4];
-      lap_row(qa, r, ahl, ahr, PA[buf], yl, c * 4, p, lapA);
-      if (TWO) lap_row(qb, r, bhl, bhr, PB[TWO ? buf : 0], yl, c * 4, p, lapB);
-      buf ^= 1;
-      if (!act) continue;
+      if (z < z1) {   // uniform; a constant trip count keeps the loop fully unrolled
+        if (PF3) fetch(min(z + 1, z1 - 1), nxt);   // the last plane reloads itself
+        else fetch(z, cur);
+        qa[(r + 8) % 9] = cur.qa;
+        if (TWO) qb[(r + 8) % 9] = cur.qb;
+        // centre rows and y halo into LDS
+        *reinterpret_cast<V4<T>*>(&PL[0][buf][yl + 4][c * 4]) = qa[(r + 4) % 9];
+        if (TWO) *reinterpret_cast<V4<T>*>(&PL[NB - 1][buf][yl + 4][c * 4]) = qb[(r + 4) % 9];
+        if (!hfieldB) *reinterpret_cast<V4<T>*>(&PL[0][buf][hlds][hcol]) = cur.hv;
+        else if (TWO) *reinterpret_cast<V4<T>*>(&PL[NB - 1][buf][hlds][hcol]) = cur.hv;
+        lds_barrier();
+        T lapA[4], lapB[4];
+        lap_row(qa, r, cur.xa, PL[0][buf], yl, c * 4, p, lapA);
+        if (TWO) lap_row(qb, r, cur.xb, PL[NB - 1][buf], yl, c * 4, p, lapB);
+        buf ^= 1;
+        const unsigned sz_ = soff(z);
 
-      const long long orow = oz + colrow;
-      if ((MODE == M_FUSED || MODE == M_BG) && z == sz && y == sy) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (x + i == sx) lapA[i] += wsrc;
-      }
-      const int rp = (z < p.rec_lo || z > p.rec_hi) ? -1 : p.recplane[z];
-      const bool recrow = rp >= 0;
-      int rm[4] = {-1, -1, -1, -1};
-      if (recrow) {
-        const int4 m4 = *reinterpret_cast<const int4*>(p.recmap + ((long long)rp * nyp + y) * p.cpitch + x);
-        rm[0] = m4.x;
-        rm[1] = m4.y;
-        rm[2] = m4.z;
-        rm[3] = m4.w;
-        if (MODE == M_ADJ) {
-          const T* drow = p.data + ((long long)shot * p.nt + (n - 1)) * p.nr;
-#pragma unroll
+        if ((MODE == M_FUSED || MODE == M_BG) && z == sz && y == sy) {
+  #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (rm[i] >= 0) lapA[i] += drow[rm[i]];
+            if (x + i == sx) lapA[i] += wsrc;
         }
-      }
-
-      const V4<T> kap4 = bld4(rK, lvo, sz_, T(0));
-      const int dz = depth3(z, p.L.nz, p.L.nb);
-      T a[4], b[4];
-      if (tile_free && dz == 0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          a[i] = T(1);
-          b[i] = T(1);
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) damp3(p.eta_c, dxy2[i] + dz * dz, a[i], b[i]);
-      }
-
-      const int zm = z - p.L.nb;
-      const bool zmod = (zm >= 0) && (zm < p.L.nz) && ymod;
-      const long long mo = (long long)zm * p.L.mplane + (long long)ym * p.L.mpitch + xm;
-
-      T g[4] = {T(0), T(0), T(0), T(0)};
-      if (MODE == M_FUSED || MODE == M_BG) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) g[i] = kap4.v[i] * lapA[i] * p.inv_dt2;
-      } else if (zmod && xmodany) {
-        if (xmodall) {
-          const V4<T> gg = ld4(hist_n + mo);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) g[i] = gg.v[i];
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (xmod[i]) g[i] = hist_n[mo + i];
-        }
-      }
-
-      const V4<T> aprev = bld4(rAp, lvo, sz_, T(0));
-      V4<T> adm = zero4<T>();
-      if (MODE == M_BORN) adm = bld4(rM, lvo, sz_, T(0));
-      V4<T> anew, ainc;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const T cc = qa[(r + 4) % 9].v[i];
-        if (BGM) {
-          ainc.v[i] = b[i] * aprev.v[i] + a[i] * (kap4.v[i] * lapA[i]);
-          anew.v[i] = cc + ainc.v[i];
-        } else {
-          const T src = (MODE == M_BORN) ? kap4.v[i] * (lapA[i] - adm.v[i] * g[i]) : kap4.v[i] * lapA[i];
-          anew.v[i] = a[i] * (T(2) * cc + src) - b[i] * aprev.v[i];
-        }
-      }
-      if (xvalall) {
-        st4(Anext + orow, anew);
-        if (BGM) st4(Ainc + orow, ainc);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (xvalid[i]) {
-            Anext[orow + i] = anew.v[i];
-            if (BGM) Ainc[orow + i] = ainc.v[i];
+        const int rp = (z < p.rec_lo || z > p.rec_hi) ? -1 : p.recplane[z];
+        const bool recrow = rp >= 0;   // uniform
+        int rm[4] = {-1, -1, -1, -1};
+        if (recrow && act) {
+          const int4 m4 = *reinterpret_cast<const int4*>(p.recmap + ((long long)rp * nyp + y) * p.cpitch + x);
+          rm[0] = m4.x;
+          rm[1] = m4.y;
+          rm[2] = m4.z;
+          rm[3] = m4.w;
+          if (MODE == M_ADJ) {
+            const T* drow = p.data + ((long long)shot * p.nt + (n - 1)) * p.nr;
+  #pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (rm[i] >= 0) lapA[i] += drow[rm[i]];
           }
-      }
-
-      V4<T> bnew;
-      if (TWO) {
-        const V4<T> bprev = bld4(rBp, lvo, sz_, T(0));
-        const V4<T> dm4 = bld4(rM, lvo, sz_, T(0));
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const T cc = qb[(r + 4) % 9].v[i];
-          bnew.v[i] = a[i] * (T(2) * cc + kap4.v[i] * (lapB[i] - dm4.v[i] * g[i])) - b[i] * bprev.v[i];
         }
-        if (xvalall) {
-          st4(Bnext + orow, bnew);
+
+        const V4<T>& kap4 = cur.kap;
+        const int dz = depth3(z, p.L.nz, nb);
+        T a[4], b[4];
+        if (tile_free && dz == 0) {
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            a[i] = T(1);
+            b[i] = T(1);
+          }
         } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (xvalid[i]) Bnext[orow + i] = bnew.v[i];
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) damp3(p.eta_c, dxy2[i] + dz * dz, a[i], b[i]);
         }
-      }
 
-      if (CK != CK_NONE && (MODE == M_FUSED || MODE == M_BG)) {
-        if (ck_store >= 0) {
+        const int zm = z - nb;
+        const bool zmod = (zm >= 0) && (zm < p.L.nz);   // uniform
+
+        T g[4];
+        if (BGM) {
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) g[i] = kap4.v[i] * lapA[i] * p.inv_dt2;
+        } else {
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) g[i] = cur.g.v[i];
+        }
+
+        // cells past the grid's x extent (the last tile column) keep zero
+        const V4<T>& aprev = cur.ap;
+        V4<T> anew, ainc;
+  #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const T cc = qa[(r + 4) % 9].v[i];
+          if (BGM) {
+            ainc.v[i] = b[i] * aprev.v[i] + a[i] * (kap4.v[i] * lapA[i]);
+            anew.v[i] = cc + ainc.v[i];
+          } else {
+            const T src = (MODE == M_BORN) ? kap4.v[i] * (lapA[i] - cur.dm.v[i] * g[i]) : kap4.v[i] * lapA[i];
+            anew.v[i] = a[i] * (T(2) * cc + src) - b[i] * aprev.v[i];
+          }
+          if (!xvalid[i]) {
+            anew.v[i] = T(0);
+            ainc.v[i] = T(0);
+          }
+        }
+        bst4<NT3>(anew, rAn, lvo, sz_);
+        if (BGM) bst4<NT3>(ainc, rAp, lvo, sz_);
+
+        V4<T> bnew;
+        if (TWO) {
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const T cc = qb[(r + 4) % 9].v[i];
+            bnew.v[i] = a[i] * (T(2) * cc + kap4.v[i] * (lapB[i] - cur.dm.v[i] * g[i])) - b[i] * cur.bp.v[i];
+            if (!xvalid[i]) bnew.v[i] = T(0);
+          }
+          bst4<NT3>(bnew, rBp, lvo, sz_);
+        }
+
+        if (CK != CK_NONE && BGM && ck_store >= 0 && act) {
           const long long co = ((long long)z * nyp + y) * p.cpitch + x;
           const long long lv = ((long long)ls * p.nck + ck_store) * 2;
           if (CK == CK_F32) {
             T* c0 = static_cast<T*>(p.ck) + lv * p.cstride + co;
             T* c1 = c0 + p.cstride;
-#pragma unroll
+  #pragma unroll
             for (int i = 0; i < 4; ++i)
               if (xvalid[i]) {
                 c0[i] = qa[(r + 4) % 9].v[i];
@@ -387,7 +424,7 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
             unsigned short* c0 = static_cast<unsigned short*>(p.ck) + lv * p.cstride + co;
             unsigned short* c1 = c0 + p.cstride;
             unsigned short h0[4], h1[4];
-#pragma unroll
+  #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const float uc = (float)qa[(r + 4) % 9].v[i];
               h0[i] = bf16_rne(uc * i0);
@@ -397,7 +434,7 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
               *reinterpret_cast<uint2*>(c0) = make_uint2(h0[0] | ((unsigned)h0[1] << 16), h0[2] | ((unsigned)h0[3] << 16));
               *reinterpret_cast<uint2*>(c1) = make_uint2(h1[0] | ((unsigned)h1[1] << 16), h1[2] | ((unsigned)h1[3] << 16));
             } else {
-#pragma unroll
+  #pragma unroll
               for (int i = 0; i < 4; ++i)
                 if (xvalid[i]) {
                   c0[i] = h0[i];
@@ -406,47 +443,36 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
             }
           }
         }
-        if (CK == CK_BF16 && ck_max >= 0) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (xvalid[i]) {
-              mx0 = fmaxf(mx0, fabsf((float)anew.v[i]));
-              mx1 = fmaxf(mx1, fabsf((float)ainc.v[i]));
-            }
+        if (CK == CK_BF16 && BGM && ck_max >= 0 && act) {
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            mx0 = fmaxf(mx0, fabsf((float)anew.v[i]));   // zero past the grid
+            mx1 = fmaxf(mx1, fabsf((float)ainc.v[i]));
+          }
         }
-      }
 
-      if (CK == CK_NONE && (MODE == M_FUSED || MODE == M_BG) && zmod && xmodany) {
-        if (xmodall) {
+        if (CK == CK_NONE && BGM && zmod) {
           V4<T> gg;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) gg.v[i] = g[i];
-          st4(hist_w + mo, gg);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (xmod[i]) hist_w[mo + i] = g[i];
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) gg.v[i] = xmod[i] ? g[i] : T(0);   // model pad columns keep zero
+          bst4<NT3>(gg, rG, gvo + (unsigned)zm * gplane, 0u);
         }
-      }
 
-      if ((MODE == M_FUSED || MODE == M_BORN) && recrow) {
-        T* drow = p.data + ((long long)shot * p.nt + n) * p.nr;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (rm[i] >= 0) drow[rm[i]] = TWO ? bnew.v[i] : anew.v[i];
-      }
-
-      if (MODE == M_ADJ && zmod && xmodany) {
-        if (xmodall) {
-          V4<double> acc = *reinterpret_cast<V4<double>*>(img + mo);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) acc.v[i] -= (double)g[i] * (double)anew.v[i];
-          *reinterpret_cast<V4<double>*>(img + mo) = acc;
-        } else {
-#pragma unroll
+        if ((MODE == M_FUSED || MODE == M_BORN) && recrow && act) {
+          T* drow = p.data + ((long long)shot * p.nt + n) * p.nr;
+  #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (xmod[i]) img[mo + i] -= (double)g[i] * (double)anew.v[i];
+            if (rm[i] >= 0) drow[rm[i]] = TWO ? bnew.v[i] : anew.v[i];
         }
+
+        if (MODE == M_ADJ && zmod) {
+          V4<double> acc = cur.im;
+  #pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (xmod[i]) acc.v[i] -= (double)g[i] * (double)anew.v[i];
+          bst4<NT3>(acc, rI, ivo + (unsigned)zm * iplane, 0u);
+        }
+        if (PF3) cur = nxt;
       }
     }
   }
@@ -461,11 +487,33 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
       atomicMax(sc + 1, __float_as_uint(mx1));
     }
   }
+  }   // items
+}
+
+static int device_cus3() {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      ncu = v;
+    else
+      ncu = 256;
+  }
+  return ncu;
 }
 
 template <typename T, int MODE, int CK>
 static void go3(const Step<T>& p, int n, int hslot, int cs, int cm, hipStream_t st) {
-  hipLaunchKernelGGL((k_step3d<T, MODE, CK>), dim3(xcd_grid(p.nwg)), dim3(256), 0, st, p, n, hslot, cs, cm);
+  static int occ = 0;   // resident workgroups per CU
+  if (occ == 0) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_step3d<T, MODE, CK>, 256, 0) != hipSuccess || b < 1) b = 1;
+    occ = b;
+  }
+  const long long resident = std::max(8LL, (long long)device_cus3() * occ / 8 * 8);
+  const long long grid = std::min<long long>(xcd_grid(p.nwg), resident);
+  hipLaunchKernelGGL((k_step3d<T, MODE, CK>), dim3((unsigned)grid), dim3(256), 0, st, p, n, hslot, cs, cm);
 }
 
 template <typename T>
