@@ -65,26 +65,30 @@ __device__ __forceinline__ Rsrc rsrc(const void* base, long long bytes) {
   const int n = bytes >= 0xffffffffLL ? -1 : (int)(unsigned)bytes;
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
 }
+template <int CP = 0>
 __device__ __forceinline__ V2<float> bld2(Rsrc r, unsigned vo, unsigned so, float) {
-  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, CP);
   V2<float> o;
   o.v[0] = __uint_as_float(v.x);
   o.v[1] = __uint_as_float(v.y);
   return o;
 }
+template <int CP = 0>
 __device__ __forceinline__ V2<double> bld2(Rsrc r, unsigned vo, unsigned so, double) {
-  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, CP);
   V2<double> o;
   o.v[0] = __longlong_as_double(((long long)v.y << 32) | v.x);
   o.v[1] = __longlong_as_double(((long long)v.w << 32) | v.z);
   return o;
 }
+template <int CP = 0>
 __device__ __forceinline__ void bst2(const V2<float>& a, Rsrc r, unsigned vo, unsigned so) {
   u32x2 v;
   v.x = __float_as_uint(a.v[0]);
   v.y = __float_as_uint(a.v[1]);
-  __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, CP);
 }
+template <int CP = 0>
 __device__ __forceinline__ void bst2(const V2<double>& a, Rsrc r, unsigned vo, unsigned so) {
   const long long b0 = __double_as_longlong(a.v[0]), b1 = __double_as_longlong(a.v[1]);
   u32x4 v;
@@ -92,7 +96,7 @@ __device__ __forceinline__ void bst2(const V2<double>& a, Rsrc r, unsigned vo, u
   v.y = (unsigned)(b0 >> 32);
   v.z = (unsigned)b1;
   v.w = (unsigned)(b1 >> 32);
-  __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, CP);
 }
 // Cells x-4 .. x+5 around the lane's pair (x, x+1): the pairs of lanes l-2, l-1,
 // l, l+1, l+2 (lanes past either end of the wavefront read zero; their results
@@ -206,6 +210,9 @@ struct RowIn {
 
 // Per-lane byte offset that every buffer access of an inactive lane uses: past
 // the end of any resource, so reads return zero and writes are dropped.
+// cache policy of g and the image (read or written once per launch, never reused
+// from L2 or the last-level cache): non-temporal
+constexpr int NT2 = 2;
 constexpr unsigned OFF_NONE = 0x80000000u;
 
 // Damping of the 2D sweeps: e = (eta_x + eta_z) dt / 2 = ec (dx^2 + dz^2) with dx, dz
@@ -331,7 +338,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
                            red[rbuf][3][gj].v[i];
         acc.v[i] += sum;
       }
-      bst2(acc, rIm, ivo + (unsigned)zm * irowb, 0u);
+      bst2<NT2>(acc, rIm, ivo + (unsigned)zm * irowb, 0u);
     }
     rbuf ^= 1;
   };
@@ -342,13 +349,13 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
   // g rows: a pair that ends past nx stores zero into the model row's pad column,
   // so loads of such a pair need no mask
   auto gld = [&](const Rsrc& r, unsigned vo_lane, int zm) -> V2<T> {
-    return bld2(r, vo_lane + (unsigned)zm * mrowb, 0u, T(0));
+    return bld2<NT2>(r, vo_lane + (unsigned)zm * mrowb, 0u, T(0));
   };
   auto gst = [&](const Rsrc& r, int zm, const T g[2]) {
     V2<T> gg;
     gg.v[0] = g[0];
     gg.v[1] = xmod1 ? g[1] : T(0);
-    bst2(gg, r, gvs + (unsigned)zm * mrowb, 0u);
+    bst2<NT2>(gg, r, gvs + (unsigned)zm * mrowb, 0u);
   };
   // receiver indices of the pair on row z (-1: none); false if the row has none
   auto recs = [&](int z, int rm[2]) -> bool {
@@ -442,7 +449,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
       const int zm = (NS == 2 ? z - 4 * d : z) - nb;   // imaging row
       f.g1 = gld(rH1, gvs, zm);
       if (NS == 2) f.g2 = gld(rH2, gvs, zm);
-      f.im = bld2(rIm, ivo + (unsigned)zm * irowb, 0u, 0.0);
+      f.im = bld2<NT2>(rIm, ivo + (unsigned)zm * irowb, 0u, 0.0);
     }
   };
 
