@@ -202,8 +202,8 @@ template <typename T>
 struct RowIn {
   V2<T> q;          // level-0 row z + 4d (enters the queue)
   V2<T> pv;         // row z: level -1 (Born, adjoint) or background increment D^n
-  V2<T> k1, k2;     // kappa on rows z and z - 4d
-  V2<T> m1, m2;     // Born: extended perturbation on rows z and z - 4d
+  V2<T> k1;         // kappa on row z (row z - 4d of level 2: kept from four rows back)
+  V2<T> m1;         // Born: extended perturbation on row z (likewise)
   V2<T> g1, g2;     // Born: g^n (row z), g^{n+1} (row z - 4d); adjoint: g^{k-1}, g^{k-2} (imaging row)
   V2<double> im;    // adjoint: image pair on the imaging row
 };
@@ -438,13 +438,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
       f.m1 = bld2(rM, frow(z), 0u, T(0));
       f.g1 = gld(rH1, gvo, z - nb);   // level 1 runs on the halo lanes too
     }
-    if (NS == 2) {
-      f.k2 = bld2(rK, frow(z - 4 * d), 0u, T(0));
-      if (MODE == M_BORN) {
-        f.m2 = bld2(rM, frow(z - 4 * d), 0u, T(0));
-        f.g2 = gld(rH2, gvs, z - 4 * d - nb);
-      }
-    }
+    if (NS == 2 && MODE == M_BORN) f.g2 = gld(rH2, gvs, z - 4 * d - nb);
     if (MODE == M_ADJ) {
       const int zm = (NS == 2 ? z - 4 * d : z) - nb;   // imaging row
       f.g1 = gld(rH1, gvs, zm);
@@ -455,6 +449,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
 
   V2<T> q0[9], q1[9];   // level-0 rows, level-1 rows
   V2<T> e0[9], e1[9];   // their first differences along the march
+  V2<T> kq[9], mq[9];   // kappa and (Born) perturbation of the level-1 rows, reused by level 2
   auto diff = [](const V2<T>& a, const V2<T>& b) {
     V2<T> r;
     r.v[0] = a.v[0] - b.v[0];
@@ -485,6 +480,10 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
       if (PF == 2) fetch(z + 2 * d, nx2);
       else fetch(z + d, nx1);
       q0[(r + 8) % 9] = cur.q;
+      if (NS == 2) {   // level 2 reaches row z four iterations from now
+        kq[r] = cur.k1;
+        if (MODE == M_BORN) mq[r] = cur.m1;
+      }
       e0[(r + 7) % 9] = diff(q0[(r + 8) % 9], q0[(r + 7) % 9]);
       const bool out_row = (z >= z0) && (z < z1);
 
@@ -579,14 +578,14 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
         const V2<T> pv = BG ? dq[wv][(r + 5) % 9][lane] : q0[r % 9];
         T g[2];
         if (BG) {
-          g[0] = rmul(rmul(cur.k2.v[0], lap[0]), p.inv_dt2);
-          g[1] = rmul(rmul(cur.k2.v[1], lap[1]), p.inv_dt2);
+          g[0] = rmul(rmul(kq[(r + 5) % 9].v[0], lap[0]), p.inv_dt2);
+          g[1] = rmul(rmul(kq[(r + 5) % 9].v[1], lap[1]), p.inv_dt2);
         } else {
           g[0] = cur.g2.v[0];
           g[1] = cur.g2.v[1];
         }
         V2<T> nv, nd;
-        level(y, c1, lap, cur.k2, cur.m2, pv, g, nv, nd);
+        level(y, c1, lap, kq[(r + 5) % 9], mq[(r + 5) % 9], pv, g, nv, nd);
         if (BG) {
           bst2(nv, rO0, vs + so, 0u);
           bst2(nd, rO1, vs + so, 0u);
