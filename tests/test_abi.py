@@ -39,3 +39,25 @@ def test_python_binding_imports_without_device():
     assert callable(M.probe_fit) and callable(M.apply_Hinv)
     from paper_1101_3615_amd._lib import EXPORTS
     assert set(EXPORTS) <= set(declared())
+
+
+def test_create_rejects_grids_past_the_32_bit_offset_limit():
+    """mp_create refuses a grid whose padded wavefield slice or FP64 image reaches 1 GiB (the
+    sweeps address them with 32-bit buffer offsets) before any device call; the same call with
+    a small grid gets past that check (and fails later only for want of a GPU here)."""
+    import numpy as np
+    from paper_1101_3615_amd import _lib as L
+    lib = ctypes.CDLL(LIB)
+    lib.mp_last_error.restype = ctypes.c_char_p
+    src = np.zeros((1, 3), dtype=np.int32)
+    rec = np.array([[1, 0, 0]], dtype=np.int32)
+    a = L.Acq(1, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), 1,
+              rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), 10.0, 0.1, 1e-3, 10)
+    o = L.Opts(1, 0, 1, 0, 1e-3, 0)   # MP_F32, MP_SNAP_FULL
+    ctx = ctypes.c_void_p()
+    big = L.Grid(3, (ctypes.c_int * 3)(640, 640, 640), 10.0, 20)
+    assert lib.mp_create(ctypes.byref(big), ctypes.byref(a), ctypes.byref(o), ctypes.byref(ctx)) == -1
+    assert b"too large" in lib.mp_last_error()
+    small = L.Grid(3, (ctypes.c_int * 3)(64, 64, 64), 10.0, 20)
+    lib.mp_create(ctypes.byref(small), ctypes.byref(a), ctypes.byref(o), ctypes.byref(ctx))
+    assert b"too large" not in lib.mp_last_error()
