@@ -201,6 +201,33 @@ def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_m
     return rec
 
 
+def volume_run(nt):
+    """apply_H on the 256^3 workload with nt time steps (inputs resident on the device): wall
+    time, cell-steps per second and per-sweep device time per launch from the HIP events."""
+    import torch
+
+    import fixtures as F
+    import paper_1101_3615_amd as M
+    w = F.c5().with_(nt=nt)
+    c = F.medium(w)
+    P = M.Problem.from_spec(w, timing=True)
+    P.set_background(torch.from_numpy(c).to("cuda:0"))
+    y = torch.from_numpy(F.wavepackets(w, c, 15, 64)).to("cuda:0")
+    torch.cuda.synchronize()
+    P.stats()
+    t0 = time.perf_counter()
+    P.apply_H(y)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = P.stats()
+    sweeps = {k: {"ms": round(st["ms_sweep"][k], 3), "launches": st["launches_sweep"][k],
+                  "us_per_launch": round(1e3 * st["ms_sweep"][k] / st["launches_sweep"][k], 1)}
+              for k in st["ms_sweep"] if st["launches_sweep"][k]}
+    cs = w.prop_cells * nt * w.ns
+    return {"workload": w.name, "steps": nt, "shots": w.ns, "snapshots": w.snap, "apply_H_s": round(wall, 3),
+            "gcell_steps_per_s": round(cs / wall / 1e9, 2), "sweeps": sweeps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +239,9 @@ def main():
                          "the printed line is then marked and is not a benchmark result)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--volume-steps", type=int, default=0,
+                    help="only run apply_H on the 256^3 workload (32 shots, BF16 checkpoints) with this "
+                         "many time steps and print its sweep times (3D measurement and profiling)")
     ap.add_argument("--cpu-workers", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -237,6 +267,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}))
+        return
+    if args.volume_steps:
+        print(json.dumps(volume_run(args.volume_steps)))
         return
 
     # CPU baseline first: forked workers must not inherit an initialised GPU runtime
