@@ -141,9 +141,9 @@ int mp_set_background(mp_ctx* ctx, const void* c_dev, void* stream);
 
 /* Device bytes an operator needs with the current settings (MP_OP_*) for a
  * job of nshots shots (nshots <= 0: every acquisition shot), counting the
- * context's resident state; used for admission control.  2D jobs are laid out
- * in groups of four shots per request (padded), so for a batch pass the sum of
- * the requests' shot counts each rounded up to a multiple of 4. */
+ * context's resident state; used for admission control.  Jobs are laid out in
+ * image groups per request (four shots in 2D, two in 3D; padded), so for a batch
+ * pass the sum of the requests' shot counts each rounded up to the group size. */
 int mp_footprint(const mp_ctx* ctx, int op, int nshots, size_t* bytes);
 
 /* F: model perturbation dm_dev -> data d_dev (overwritten), Sec. 1.1 / Sec. 2. */

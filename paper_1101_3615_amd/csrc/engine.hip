@@ -161,10 +161,10 @@ class EngineT final : public Engine {
     if (ckpt_mode()) b += (size_t)nck() * 2 * (ck_elem() * (size_t)cstride_ + sizeof(float));
     return b;
   }
-  // Shots per image: the 2D adjoint images the four shots of a workgroup into one
-  // FP64 image, so 2D jobs are laid out in groups of four (each request padded
-  // with null shots); 3D images every shot on its own.
-  int gsz() const { return cfg_.ndim == 2 ? 4 : 1; }
+  // Shots per image: the adjoint images the shots of a workgroup (four in 2D, a
+  // pair in 3D) into one FP64 image, so jobs are laid out in such groups (each
+  // request padded with null shots).
+  int gsz() const { return cfg_.ndim == 2 ? 4 : 2; }
   int pad_group(int n) const { return (n + gsz() - 1) / gsz() * gsz(); }
   // bytes that scale with the job (data, images, perturbation slots)
   size_t job_bytes(int nb, int nslots) const {
@@ -285,12 +285,12 @@ class EngineT final : public Engine {
     p.nt = cfg_.nt;
     p.shot0 = s0;
     if (cfg_.ndim == 3) {
-      // one workgroup per 64 x 16 tile and z chunk: as few chunks as keep about
-      // 2048 workgroups in the launch (each chunk rereads 8 planes of its field)
+      // one item per 64 x 16 tile of a pair of shots and z chunk: as few chunks
+      // as keep about 1024 items in the launch (each chunk rereads 8 planes)
       int zc = zc_target_;
-      const long long tiles = (long long)nsh * L_.nstrips * L_.nytiles;
+      const long long tiles = (long long)(nsh / 2) * L_.nstrips * L_.nytiles;
       if (zc <= 0) {
-        const long long want = std::min<long long>((2048 + tiles - 1) / tiles, std::max(1, L_.nzp / 8));
+        const long long want = std::min<long long>((1024 + tiles - 1) / tiles, std::max(1, L_.nzp / 8));
         zc = (int)((L_.nzp + want - 1) / want);
       }
       p.nchunks = (L_.nzp + zc - 1) / zc;
@@ -607,6 +607,10 @@ class EngineT final : public Engine {
   int forward(int mode, int s0, int nsh, int W, T* data) {
     if (cfg_.ndim == 2) return forward2d(mode, s0, nsh, W, data);
     int rc;
+    if (nsh % gsz() || s0 % gsz()) {
+      set_error("internal: a 3D sweep takes whole pairs of shots");
+      return MP_EINVAL;
+    }
     if ((rc = zero_fields(W, true))) return rc;
     Step<T> p = params(s0, nsh, W);
     p.data = data;
@@ -637,8 +641,13 @@ class EngineT final : public Engine {
   int adjoint(int s0, int nsh, int W, const T* data) {
     if (cfg_.ndim == 2) return adjoint2d(s0, nsh, W, data);
     int rc;
+    if (nsh % gsz() || s0 % gsz()) {
+      set_error("internal: a 3D sweep takes whole pairs of shots");
+      return MP_EINVAL;
+    }
     if ((rc = zero_fields(W, false))) return rc;
-    fill(img_.as<double>() + (long long)s0 * L_.mstride, (long long)nsh * L_.mstride, 0.0, stream_);
+    fill(img_.as<double>() + (long long)(s0 / gsz()) * L_.mstride, (long long)(nsh / gsz()) * L_.mstride, 0.0,
+         stream_);
     Step<T> p = params(s0, nsh, W);
     p.data = const_cast<T*>(data);
     Span* sp;

@@ -27,6 +27,7 @@ namespace mp {
 // zero and its writes are dropped).  Word 3: gfx9-family raw-buffer configuration.
 using Rsrc3 = __amdgpu_buffer_rsrc_t;
 typedef unsigned int u32x4_3 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2_3 __attribute__((ext_vector_type(2)));
 constexpr unsigned OFF_NONE3 = 0x80000000u;
 // cache policy of the data that no other workgroup rereads soon (outputs, the
 // cell's own previous level, g, image): non-temporal, so that L2 keeps the field
@@ -134,15 +135,23 @@ __device__ __forceinline__ void lap_row(const V4<T>* qa, int r, const V4<T>& xh,
   }
 }
 
+// A workgroup (512 threads) carries one tile for a pair of consecutive job shots:
+// threads 0..255 the even shot, 256..511 the odd one.  The two halves march in
+// step (one barrier per plane serves both), so the second read of kappa and the
+// perturbation hits in cache, and the adjoint images the pair into one FP64 image
+// (the pair's contributions summed in shot order in LDS, one read-modify-write).
 template <typename T, int MODE, int CK>
-__global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int ck_store, int ck_max) {
+__global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int ck_store, int ck_max) {
   constexpr bool TWO = (MODE == M_FUSED);
-  // LDS plane per field: the tile's rows plus four halo rows above and below
-  // (double buffered: one barrier per plane)
+  // LDS plane per half and field: the tile's rows plus four halo rows above and
+  // below (double buffered: one barrier per plane)
   constexpr int NB = TWO ? 2 : 1;
-  __shared__ __align__(32) T PL[NB][2][TY + 8][TX];
+  __shared__ __align__(32) T PL[2][NB][2][TY + 8][TX];
+  // adjoint: each half's image contribution to a plane, read one plane later
+  __shared__ __align__(32) V4<double> RED[(MODE == M_ADJ) ? 2 : 1][2][(MODE == M_ADJ) ? 256 : 1];
 
-  const int tid = threadIdx.x;
+  const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 8);
+  const int tid = threadIdx.x & 255;
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int c = lane & 15;
@@ -166,7 +175,7 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
   const int ty = rest % p.L.nytiles;
   rest /= p.L.nytiles;
   const int chunk = rest % p.nchunks;
-  const int ls = rest / p.nchunks;
+  const int ls = (rest / p.nchunks) * 2 + half;
   const int z0 = chunk * p.zc;
   const int z1 = min(z0 + p.zc, p.L.nzp);
 
@@ -181,11 +190,11 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
   const bool hl_in = (c == 0) && (x - 4 >= 0) && (x - 4 < nxp) && yin;
   const bool hr_in = (c == 15) && (x + 4 < nxp) && yin;
   const int shot = p.shot0 + ls;
+  const bool live = p.srcx[shot] >= 0;   // a null shot (group padding) has no source and no data
 
   bool xvalid[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) xvalid[i] = (x + i >= 0) && (x + i < nxp);
-  const bool xvalall = xvalid[0] && xvalid[1] && xvalid[2] && xvalid[3];
   const int xm = x - p.L.nb, ym = y - p.L.nb;
   bool xmod[4];
 #pragma unroll
@@ -244,11 +253,11 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
   const long long hoff = (long long)ls * p.hstride + (long long)hslot * p.L.mstride;
   const long long mbytes3 = p.L.mstride * (long long)sizeof(T);
   const Rsrc3 rG = rsrc3(hslot >= 0 ? p.hist + hoff : p.hist, hslot >= 0 ? mbytes3 : 0);
-  const Rsrc3 rI = rsrc3(MODE == M_ADJ ? p.img + (long long)shot * p.L.mstride : p.img,
+  const Rsrc3 rI = rsrc3(MODE == M_ADJ ? p.img + (long long)(shot >> 1) * p.L.mstride : p.img,
                          MODE == M_ADJ ? p.L.mstride * 8LL : 0);
   const bool mlane = act && ymod && xmodany;
   const unsigned gvo = mlane ? (unsigned)((long long)ym * p.L.mpitch + xm) * esz : OFF_NONE3;
-  const unsigned ivo = mlane ? (unsigned)((long long)ym * p.L.mpitch + xm) * 8u : OFF_NONE3;
+  const unsigned ivo = (mlane && half == 0) ? (unsigned)((long long)ym * p.L.mpitch + xm) * 8u : OFF_NONE3;
   const unsigned gplane = (unsigned)(p.L.mplane * (long long)esz);
   const unsigned iplane = (unsigned)(p.L.mplane * 8LL);
   const int nb = p.L.nb;
@@ -275,7 +284,7 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
     V4<T> xa, xb;          // x halos of plane z
     V4<T> kap, ap, bp, dm; // kappa, A increment / level n-1, B level n-1, perturbation
     V4<T> g;               // Born / adjoint: g of plane z
-    V4<double> im;         // adjoint: image of plane z
+    V4<double> im;         // adjoint: the pair's image on plane z - 1 (even half)
   };
   auto fetch = [&](int z, In3& f) {
     const unsigned s = soff(z);
@@ -290,10 +299,23 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
     if (TWO || MODE == M_BORN) f.dm = bld4<NT3>(rM, lvo, s, T(0));
     const unsigned zm = (unsigned)(z - nb);
     if (MODE == M_BORN || MODE == M_ADJ) f.g = bld4<NT3>(rG, gvo + zm * gplane, 0u, T(0));
-    if (MODE == M_ADJ) f.im = bld4<NT3>(rI, ivo + zm * iplane, 0u, double(0));
+    if (MODE == M_ADJ) f.im = bld4<NT3>(rI, ivo + (zm - 1u) * iplane, 0u, double(0));
   };
   constexpr bool PF3 = sizeof(T) == 4;
 
+  // Image of plane zz for the pair: old + (even half's + odd half's contribution),
+  // written by the even half (the contributions were put in LDS before a barrier)
+  auto pair_image = [&](int zz, const V4<double>& old) {
+    const int zmm = zz - nb;
+    if (half == 0 && zmm >= 0 && zmm < p.L.nz) {   // uniform
+      V4<double> acc = old;
+      const V4<double>& a0 = RED[0][zz & 1][tid];
+      const V4<double>& a1 = RED[MODE == M_ADJ ? 1 : 0][zz & 1][tid];
+  #pragma unroll
+      for (int i = 0; i < 4; ++i) acc.v[i] += a0.v[i] + a1.v[i];
+      bst4<NT3>(acc, rI, ivo + (unsigned)zmm * iplane, 0u);
+    }
+  };
   float mx0 = 0.0f, mx1 = 0.0f;
   V4<T> qa[9], qb[9];
 #pragma unroll
@@ -314,15 +336,16 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
         qa[(r + 8) % 9] = cur.qa;
         if (TWO) qb[(r + 8) % 9] = cur.qb;
         // centre rows and y halo into LDS
-        *reinterpret_cast<V4<T>*>(&PL[0][buf][yl + 4][c * 4]) = qa[(r + 4) % 9];
-        if (TWO) *reinterpret_cast<V4<T>*>(&PL[NB - 1][buf][yl + 4][c * 4]) = qb[(r + 4) % 9];
-        if (!hfieldB) *reinterpret_cast<V4<T>*>(&PL[0][buf][hlds][hcol]) = cur.hv;
-        else if (TWO) *reinterpret_cast<V4<T>*>(&PL[NB - 1][buf][hlds][hcol]) = cur.hv;
+        *reinterpret_cast<V4<T>*>(&PL[half][0][buf][yl + 4][c * 4]) = qa[(r + 4) % 9];
+        if (TWO) *reinterpret_cast<V4<T>*>(&PL[half][NB - 1][buf][yl + 4][c * 4]) = qb[(r + 4) % 9];
+        if (!hfieldB) *reinterpret_cast<V4<T>*>(&PL[half][0][buf][hlds][hcol]) = cur.hv;
+        else if (TWO) *reinterpret_cast<V4<T>*>(&PL[half][NB - 1][buf][hlds][hcol]) = cur.hv;
         lds_barrier();
         T lapA[4], lapB[4];
-        lap_row(qa, r, cur.xa, PL[0][buf], yl, c * 4, p, lapA);
-        if (TWO) lap_row(qb, r, cur.xb, PL[NB - 1][buf], yl, c * 4, p, lapB);
+        lap_row(qa, r, cur.xa, PL[half][0][buf], yl, c * 4, p, lapA);
+        if (TWO) lap_row(qb, r, cur.xb, PL[half][NB - 1][buf], yl, c * 4, p, lapB);
         buf ^= 1;
+        if (MODE == M_ADJ && z > z0) pair_image(z - 1, cur.im);
         const unsigned sz_ = soff(z);
 
         if ((MODE == M_FUSED || MODE == M_BG) && z == sz && y == sy) {
@@ -333,7 +356,7 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
         const int rp = (z < p.rec_lo || z > p.rec_hi) ? -1 : p.recplane[z];
         const bool recrow = rp >= 0;   // uniform
         int rm[4] = {-1, -1, -1, -1};
-        if (recrow && act) {
+        if (recrow && act && live) {
           const int4 m4 = *reinterpret_cast<const int4*>(p.recmap + ((long long)rp * nyp + y) * p.cpitch + x);
           rm[0] = m4.x;
           rm[1] = m4.y;
@@ -409,20 +432,16 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
           const long long co = ((long long)z * nyp + y) * p.cpitch + x;
           const long long lv = ((long long)ls * p.nck + ck_store) * 2;
           if (CK == CK_F32) {
-            T* c0 = static_cast<T*>(p.ck) + lv * p.cstride + co;
-            T* c1 = c0 + p.cstride;
-  #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if (xvalid[i]) {
-                c0[i] = qa[(r + 4) % 9].v[i];
-                c1[i] = aprev.v[i];
-              }
+            // one 16-byte store per level; the lane's cells past nxp land in the
+            // checkpoint row's padding (cpitch is a multiple of 4), holding zero
+            const Rsrc3 rc = rsrc3(static_cast<T*>(p.ck) + lv * p.cstride, 2 * p.cstride * (long long)sizeof(T));
+            const unsigned cvo = (unsigned)co * esz;
+            bst4(qa[(r + 4) % 9], rc, cvo, 0u);
+            bst4(aprev, rc, cvo + (unsigned)(p.cstride * (long long)sizeof(T)), 0u);
           } else {
             const float* sc = p.ck_scale + lv;
             const float s0 = sc[0], s1 = sc[1];
             const float i0 = s0 > 0.0f ? 1.0f / s0 : 1.0f, i1 = s1 > 0.0f ? 1.0f / s1 : 1.0f;
-            unsigned short* c0 = static_cast<unsigned short*>(p.ck) + lv * p.cstride + co;
-            unsigned short* c1 = c0 + p.cstride;
             unsigned short h0[4], h1[4];
   #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -430,17 +449,16 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
               h0[i] = bf16_rne(uc * i0);
               h1[i] = bf16_rne((float)aprev.v[i] * i1);
             }
-            if (xvalall) {
-              *reinterpret_cast<uint2*>(c0) = make_uint2(h0[0] | ((unsigned)h0[1] << 16), h0[2] | ((unsigned)h0[3] << 16));
-              *reinterpret_cast<uint2*>(c1) = make_uint2(h1[0] | ((unsigned)h1[1] << 16), h1[2] | ((unsigned)h1[3] << 16));
-            } else {
-  #pragma unroll
-              for (int i = 0; i < 4; ++i)
-                if (xvalid[i]) {
-                  c0[i] = h0[i];
-                  c1[i] = h1[i];
-                }
-            }
+            // one 8-byte store per level (cells past nxp: zero, into the row's padding)
+            const Rsrc3 rc = rsrc3(static_cast<unsigned short*>(p.ck) + lv * p.cstride, 2 * p.cstride * 2LL);
+            const unsigned cvo = (unsigned)co * 2u;
+            u32x2_3 w0, w1;
+            w0.x = h0[0] | ((unsigned)h0[1] << 16);
+            w0.y = h0[2] | ((unsigned)h0[3] << 16);
+            w1.x = h1[0] | ((unsigned)h1[1] << 16);
+            w1.y = h1[2] | ((unsigned)h1[3] << 16);
+            __builtin_amdgcn_raw_buffer_store_b64(w0, rc, cvo, 0u, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(w1, rc, cvo + (unsigned)(p.cstride * 2LL), 0u, 0);
           }
         }
         if (CK == CK_BF16 && BGM && ck_max >= 0 && act) {
@@ -458,23 +476,26 @@ __global__ __launch_bounds__(256) void k_step3d(Step<T> p, int n, int hslot, int
           bst4<NT3>(gg, rG, gvo + (unsigned)zm * gplane, 0u);
         }
 
-        if ((MODE == M_FUSED || MODE == M_BORN) && recrow && act) {
+        if ((MODE == M_FUSED || MODE == M_BORN) && recrow && act && live) {
           T* drow = p.data + ((long long)shot * p.nt + n) * p.nr;
   #pragma unroll
           for (int i = 0; i < 4; ++i)
             if (rm[i] >= 0) drow[rm[i]] = TWO ? bnew.v[i] : anew.v[i];
         }
 
-        if (MODE == M_ADJ && zmod) {
-          V4<double> acc = cur.im;
+        if (MODE == M_ADJ) {   // this half's contribution, added to the image one plane later
+          V4<double> cw;
   #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (xmod[i]) acc.v[i] -= (double)g[i] * (double)anew.v[i];
-          bst4<NT3>(acc, rI, ivo + (unsigned)zm * iplane, 0u);
+          for (int i = 0; i < 4; ++i) cw.v[i] = xmod[i] ? -((double)g[i] * (double)anew.v[i]) : 0.0;
+          RED[half][z & 1][tid] = cw;
         }
         if (PF3) cur = nxt;
       }
     }
+  }
+  if (MODE == M_ADJ) {   // the item's last plane
+    lds_barrier();
+    pair_image(z1 - 1, bld4<NT3>(rI, ivo + (unsigned)(z1 - 1 - nb) * iplane, 0u, double(0)));
   }
   if (CK == CK_BF16 && (MODE == M_FUSED || MODE == M_BG) && ck_max >= 0) {
     for (int o = 32; o > 0; o >>= 1) {
@@ -508,12 +529,12 @@ static void go3(const Step<T>& p, int n, int hslot, int cs, int cm, hipStream_t 
   static int occ = 0;   // resident workgroups per CU
   if (occ == 0) {
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_step3d<T, MODE, CK>, 256, 0) != hipSuccess || b < 1) b = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_step3d<T, MODE, CK>, 512, 0) != hipSuccess || b < 1) b = 1;
     occ = b;
   }
   const long long resident = std::max(8LL, (long long)device_cus3() * occ / 8 * 8);
   const long long grid = std::min<long long>(xcd_grid(p.nwg), resident);
-  hipLaunchKernelGGL((k_step3d<T, MODE, CK>), dim3((unsigned)grid), dim3(256), 0, st, p, n, hslot, cs, cm);
+  hipLaunchKernelGGL((k_step3d<T, MODE, CK>), dim3((unsigned)grid), dim3(512), 0, st, p, n, hslot, cs, cm);
 }
 
 template <typename T>

@@ -126,7 +126,8 @@ class Server:
             if r.shape != shape:
                 continue
             n = nshots + len(r.shots)
-            # each request occupies whole groups of four job entries on the device
+            # each request occupies whole image groups of job entries on the device
+            # (four shots in 2D, two in 3D; four bounds both)
             nj = njob + -(-len(r.shots) // 4) * 4
             if batch and n > self.max_batch_shots:
                 break

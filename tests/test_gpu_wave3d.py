@@ -83,3 +83,46 @@ def test_3d_checkpoints(snap, k):
     print(f"3D {snap} every {k}: apply_H rel L2 vs FP64 oracle = {err:.3e}")
     # 70 steps is the short, harsh end for BF16 checkpoints (see the 2D test)
     assert err <= (1e-5 if snap == "ckpt_f32" else 2e-2)
+
+
+def test_3d_odd_shot_count_and_batches():
+    """Three shots: the device images shots in pairs, so the job is padded with a null shot
+    (no source, no data); apply_F / Fadj / H still match the oracle, and apply_H_batch gives
+    each request (one and two shots) the same bits alone and in the mix."""
+    M = _gpu()
+    w = cube("f32", nt=50)
+    w = w.with_(src=np.array([[3, 5, 0], [w.nx - 2, w.ny // 2, 2], [50, 11, 9]], np.int32))
+    c = F.medium(w)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c))
+    O = Oracle(w, c)
+    dm = F.normal_field(w.model_shape, 61)
+    d = F.normal_field((w.ns, w.nt, w.nr), 62)
+    assert rel(P.apply_F(torch.from_numpy(dm)).cpu().numpy(), O.apply_F(dm)) <= 1e-5
+    assert rel(P.apply_Fadj(torch.from_numpy(d)).cpu().numpy(), O.apply_Fadj(d)) <= 1e-5
+    assert rel(P.apply_H(torch.from_numpy(dm)).cpu().numpy(), O.apply_H(dm)) <= 1e-5
+    lists = [[2], [0, 1]]
+    dms = [F.normal_field(w.model_shape, 63 + i) for i in range(2)]
+    mixed = [o.cpu().numpy() for o in P.apply_H_batch([torch.from_numpy(x) for x in dms], lists)]
+    for i, (sl, x) in enumerate(zip(lists, dms)):
+        alone = P.apply_H_batch([torch.from_numpy(x)], [sl])[0].cpu().numpy()
+        assert np.array_equal(alone, mixed[i])
+        assert rel(mixed[i], Oracle(w.with_(src=w.src[sl]), c).apply_H(x)) <= 1e-5
+
+
+@pytest.mark.parametrize("snap,k", [("full", 0), ("ckpt_f32", 8), ("ckpt_f32", 1), ("ckpt_bf16", 8)])
+def test_3d_repeatable(snap, k):
+    """Repeated calls give the same bits in every snapshot mode (a regression test: an
+    earlier form of the FP32 checkpoint store gave the odd shot of a workgroup's pair
+    different data from call to call)."""
+    M = _gpu()
+    w = cube("f32", nt=40, snap=snap, k=k)
+    c = F.medium(w)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c))
+    dm = torch.from_numpy(F.normal_field(w.model_shape, 57))
+    first = P.apply_F(dm).cpu().numpy()
+    for _ in range(3):
+        assert np.array_equal(P.apply_F(dm).cpu().numpy(), first)
+    h = P.apply_H(dm).cpu().numpy()
+    assert np.array_equal(P.apply_H(dm).cpu().numpy(), h)
