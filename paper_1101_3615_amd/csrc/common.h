@@ -21,6 +21,7 @@ constexpr int SLACK = 64;
 constexpr int LANES = 64;        // wavefront size on gfx950
 constexpr int HL2 = 4;           // 2D sweeps: halo lanes at each end of a strip
 constexpr int SW2 = 2 * (LANES - 2 * HL2);   // 2D sweeps: output cells per strip (2 per lane)
+constexpr int GW2 = 4;           // 2D sweeps: shots (wavefronts) per workgroup and per FP64 image
 
 template <typename T>
 struct alignas(4 * sizeof(T)) V4 {

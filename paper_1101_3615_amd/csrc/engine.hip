@@ -164,7 +164,7 @@ class EngineT final : public Engine {
   // Shots per image: the adjoint images the shots of a workgroup (four in 2D, a
   // pair in 3D) into one FP64 image, so jobs are laid out in such groups (each
   // request padded with null shots).
-  int gsz() const { return cfg_.ndim == 2 ? 4 : 2; }
+  int gsz() const { return cfg_.ndim == 2 ? GW2 : 2; }
   int pad_group(int n) const { return (n + gsz() - 1) / gsz() * gsz(); }
   // bytes that scale with the job (data, images, perturbation slots)
   size_t job_bytes(int nb, int nslots) const {

@@ -14,9 +14,10 @@
 // inputs, which neighbouring waves are still reading.
 //
 // Rows march in z through 9-row register queues (level 0 and level 1); x
-// neighbours come from adjacent lanes through DPP wavefront shifts.  No LDS and
-// no barriers: the four waves of a workgroup take four shots on one strip and
-// chunk, so the rows of the arrays all shots share hit in L1/L2.  Row indices are uniform across
+// neighbours come from adjacent lanes through DPP wavefront shifts.  The GW2 waves
+// of a workgroup take GW2 shots on one strip and chunk, so the rows of the arrays
+// all shots share hit in L1/L2 (LDS only for the background's level-1 increment and
+// the adjoint's group image).  Row indices are uniform across
 // the wavefront.  Rows outside [0, nzp) are zero and never read; cells outside
 // [0, nxp) read as zero from the ghost columns and are never written.
 //
@@ -246,18 +247,18 @@ __device__ __forceinline__ int layer_depth(int i, int n, int nb) { return max(ma
 // value computed for a cell outside the grid is replaced by zero.  Row indices
 // are wave-uniform.
 template <typename T, int MODE, int NS, int CK>
-__global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int hs2, int ck_store, int ck_max) {
+__global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1, int hs2, int ck_store, int ck_max) {
   constexpr bool BG = (MODE == M_BG);
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = xcd_item(p.nwg);
   if (item >= p.nwg) return;
-  // workgroup = four shots on one (strip, chunk): the rows of the arrays they
-  // share (kappa, damping, perturbation) are read by the four waves together
+  // workgroup = GW2 shots on one (strip, chunk): the rows of the arrays they
+  // share (kappa, perturbation) are read by its waves together
   const int chunk = item % p.nchunks;
   const int rest = item / p.nchunks;
   const int strip = rest % p.L.nstrips;
-  const int ls = (rest / p.L.nstrips) * 4 + wv;   // the launch holds whole groups of 4 shots
+  const int ls = (rest / p.L.nstrips) * GW2 + wv;   // the launch holds whole groups of GW2 shots
   const int nzp = p.L.nzp;
   const int nxp = p.L.nxp;
   const int nb = p.L.nb;
@@ -310,32 +311,34 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
   const int mxl = p.L.mxl;
   const Rsrc rH1 = rsrc(hs1 >= 0 ? p.hist + hbase + (long long)hs1 * p.L.mstride + mxl : p.hist, hs1 >= 0 ? mbytes : 0);
   const Rsrc rH2 = rsrc(hs2 >= 0 ? p.hist + hbase + (long long)hs2 * p.L.mstride + mxl : p.hist, hs2 >= 0 ? mbytes : 0);
-  // adjoint: one FP64 image per group of four consecutive shots (the workgroup)
-  const Rsrc rIm = rsrc(MODE == M_ADJ ? p.img + (long long)(shot >> 2) * p.L.mstride + mxl : p.img,
+  // adjoint: one FP64 image per group of GW2 consecutive shots (the workgroup)
+  const Rsrc rIm = rsrc(MODE == M_ADJ ? p.img + (long long)((unsigned)shot / GW2) * p.L.mstride + mxl : p.img,
                         MODE == M_ADJ ? (long long)nz * p.L.mpitch * 8 : 0);
   const unsigned mrowb = (unsigned)p.L.mpitch * (unsigned)sizeof(T);
   const unsigned gvo = xmod ? (unsigned)xm * (unsigned)sizeof(T) : OFF_NONE;             // g on every lane
   const unsigned gvs = (xmod && outl) ? (unsigned)xm * (unsigned)sizeof(T) : OFF_NONE;   // g on output lanes
   const unsigned irowb = (unsigned)p.L.mpitch * 8u;
-  // Imaging of the group: the four waves' contributions to a row are summed in LDS
-  // in shot order, then wave w updates the image of lane pairs 16w .. 16w+15
-  // (lanes 0..15 of the wave).  gj: the pair this lane updates.
-  __shared__ V2<double> red[(MODE == M_ADJ) ? 2 : 1][4][(MODE == M_ADJ) ? LANES : 1];
-  const int gj = (wv << 4) + (lane & 15);
+  // Imaging of the group: the GW2 waves' contributions to a row are summed in LDS
+  // in shot order, then wave w updates the image of lane pairs PPW*w .. PPW*w + PPW-1
+  // (lanes 0..PPW-1 of the wave).  gj: the pair this lane updates.
+  constexpr int PPW = LANES / GW2;
+  __shared__ V2<double> red[(MODE == M_ADJ) ? 2 : 1][GW2][(MODE == M_ADJ) ? LANES : 1];
+  const int gj = wv * PPW + (lane & (PPW - 1));
   const int gx = sx0 + 2 * gj;
-  const bool gout = (lane < 16) && (gj >= HL2) && (gj < LANES - HL2) && (gx < nxp) && (gx - nb >= 0) &&
+  const bool gout = (lane < PPW) && (gj >= HL2) && (gj < LANES - HL2) && (gx < nxp) && (gx - nb >= 0) &&
                     (gx - nb < p.L.nx);
   const unsigned ivo = gout ? (unsigned)(gx - nb) * 8u : OFF_NONE;
   int rbuf = 0;
   auto image = [&](int zm, const V2<double>& cw, const V2<double>& old) {
     red[rbuf][wv][lane] = cw;
     lds_barrier();
-    if (lane < 16) {
+    if (lane < PPW) {
       V2<double> acc = old;
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const double sum = ((red[rbuf][0][gj].v[i] + red[rbuf][1][gj].v[i]) + red[rbuf][2][gj].v[i]) +
-                           red[rbuf][3][gj].v[i];
+        double sum = red[rbuf][0][gj].v[i];
+#pragma unroll
+        for (int w = 1; w < GW2; ++w) sum += red[rbuf][w][gj].v[i];
         acc.v[i] += sum;
       }
       bst2<NT2>(acc, rIm, ivo + (unsigned)zm * irowb, 0u);
@@ -458,7 +461,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(Step<T> p, int n, int hs1, int 
   };
   // background: the increment D^{n+1} of level-1 rows, read back four rows later
   // at the centre of level 2 (kept in LDS: each wave reads only its own entries)
-  __shared__ V2<T> dq[(BG && NS == 2) ? 4 : 1][9][(BG && NS == 2) ? LANES : 1];
+  __shared__ V2<T> dq[(BG && NS == 2) ? GW2 : 1][9][(BG && NS == 2) ? LANES : 1];
 #pragma unroll
   for (int s = 0; s < 8; ++s) q0[s] = bld2(rI0, frow(zs + (s - 4) * d), 0u, T(0));
 #pragma unroll
@@ -678,9 +681,10 @@ static int device_cus() {
   return ncu;
 }
 
-// z chunking: one wave per (shot, strip, chunk), four shots per workgroup.
-// Cost of a launch with nch chunks (calibrated on MI355X): rounds x m^e x
-// (zc + H), with m the workgroups on the busiest CU in a round, zc the chunk
+// z chunking: one wave per (shot, strip, chunk), GW2 shots per workgroup.
+// Cost of a launch with nch chunks (calibrated on MI355X with four-wave
+// workgroups): rounds x m^e x (zc + H), with m the four-wave units on the busiest
+// CU in a round, zc the chunk
 // height and H = 30 rows of halo traffic per two-step chunk (12 for one step).
 // e = 0.7 for the Born and adjoint kernels, 0.38 for the background kernel,
 // which gains more from a fuller CU.  One workgroup per CU (four waves) hides too
@@ -690,7 +694,7 @@ static void chunking(Step<T>& p, int mode, int nsh, int nsteps, int wg_per_cu, i
   const int nzp = p.L.nzp;
   const long long ncu = device_cus();
   const long long cap = ncu * std::max(1, wg_per_cu);
-  const long long cols = (long long)((nsh + 3) / 4) * p.L.nstrips;
+  const long long cols = (long long)((nsh + GW2 - 1) / GW2) * p.L.nstrips;
   const double ex = (mode == M_BG) ? 0.38 : 0.7;
   const double halo = (nsteps == 2) ? 30.0 : 12.0;
   int best_zc = nzp;
@@ -701,7 +705,8 @@ static void chunking(Step<T>& p, int mode, int nsh, int nsteps, int wg_per_cu, i
     const long long wgs = cols * nch;
     const long long rounds = (wgs + cap - 1) / cap;
     const long long m = (wgs + rounds * ncu - 1) / (rounds * ncu);
-    const double cost = (double)rounds * std::pow((double)std::max<long long>(m, 2), ex) * (zc + halo);
+    const long long m4 = m * GW2 / 4;   // in workgroups of four waves, the unit the model was fitted in
+    const double cost = (double)rounds * std::pow((double)std::max<long long>(m4, 2), ex) * (zc + halo);
     if (cost < best) {
       best = cost;
       best_zc = zc;
@@ -720,12 +725,12 @@ static void go(Step<T> p, int nsh, int n, int hs1, int hs2, int cs, int cm, int 
   static int occ = 0;   // resident workgroups per CU for this kernel
   if (occ == 0) {
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_sweep2d<T, MODE, NS, CK>, 256, 0) != hipSuccess || b < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_sweep2d<T, MODE, NS, CK>, 64 * GW2, 0) != hipSuccess || b < 1)
       b = 1;
     occ = b;
   }
   chunking(p, MODE, nsh, NS, occ, zc_fixed);
-  hipLaunchKernelGGL((k_sweep2d<T, MODE, NS, CK>), dim3(xcd_grid(p.nwg)), dim3(256), 0, st, p, n, hs1, hs2, cs, cm);
+  hipLaunchKernelGGL((k_sweep2d<T, MODE, NS, CK>), dim3(xcd_grid(p.nwg)), dim3(64 * GW2), 0, st, p, n, hs1, hs2, cs, cm);
 }
 
 template <typename T, int MODE, int NS>
