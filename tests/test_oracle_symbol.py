@@ -161,3 +161,105 @@ def test_expected_gram_is_trace_formula(tinyH):
     # and the oracle's Gram routine gives the same M for one sample
     M1, _ = S.gram([X[0].reshape(shape)], [Y[0].reshape(shape)], P.h, leg, qs)
     np.testing.assert_allclose(M1, Ms[0], rtol=1e-10)
+
+
+# ---- the paper's expansion (Fourier modes x angular harmonics x rational Chebyshev) ----
+
+def test_rational_chebyshev_against_library():
+    r = np.concatenate([np.linspace(0.0, 2.0, 41), [10.0, 1e3]])
+    for L in (0.25, 0.5, 1.0):
+        t = (r - L) / (r + L)
+        for n in range(7):
+            np.testing.assert_allclose(S.rational_chebyshev(n, r, L),
+                                       np.polynomial.chebyshev.chebval(t, [0] * n + [1]), atol=1e-13)
+            # TL_n(0) = T_n(-1) = (-1)^n, TL_n(L) = T_n(0) = cos(n pi / 2)
+            assert abs(S.rational_chebyshev(n, 0.0, L) - (-1.0) ** n) < 1e-14
+            assert abs(S.rational_chebyshev(n, L, L) - np.cos(n * np.pi / 2)) < 1e-14
+
+
+def test_angular_2d_is_chebyshev_in_the_direction_cosine():
+    shape, h = (8, 16), 10.0
+    kz, kx = S.wavevector(shape, h)
+    kn = np.hypot(kx, kz)
+    c = np.where(kn > 0, kx / np.where(kn > 0, kn, 1), 0.0)
+    s = np.where(kn > 0, kz / np.where(kn > 0, kn, 1), 0.0)
+    np.testing.assert_allclose(S.angular(0, shape, h), 1.0)
+    for j in range(1, 4):
+        Tj = np.polynomial.chebyshev.chebval(c, [0] * j + [1])
+        Uj1 = np.polynomial.chebyshev.chebval(c, np.polynomial.chebyshev.chebder([0] * j + [1])) / j
+        np.testing.assert_allclose(S.angular(2 * j - 1, shape, h), np.where(kn > 0, Tj, 0.0), atol=1e-13)
+        np.testing.assert_allclose(S.angular(2 * j, shape, h), np.where(kn > 0, s * Uj1, 0.0), atol=1e-13)
+
+
+def test_angular_3d_spans_the_spherical_harmonics():
+    from scipy.special import sph_harm_y
+    shape, h = (6, 8, 10), 12.5
+    kz, ky, kx = S.wavevector(shape, h)
+    kn = np.sqrt(kx * kx + ky * ky + kz * kz)
+    m = kn > 0
+    pol = np.arccos(np.clip(kz[m] / kn[m], -1, 1))
+    azi = np.arctan2(ky[m], kx[m])
+    ours = {0: [0], 1: [1, 2, 3], 2: [4, 5, 6, 7, 8]}
+    for l, idx in ours.items():
+        ref = []
+        for mm in range(-l, l + 1):
+            y = sph_harm_y(l, mm, pol, azi)
+            ref += [y.real, y.imag]
+        R = np.stack(ref, 1)
+        Ours = np.stack([S.angular(i, shape, h)[m] for i in idx], 1)
+        # each of ours lies in the span of the library's degree-l harmonics, and they span it
+        coef, *_ = np.linalg.lstsq(R, Ours, rcond=None)
+        assert np.linalg.norm(R @ coef - Ours) <= 1e-10 * np.linalg.norm(Ours)
+        assert np.linalg.matrix_rank(Ours, tol=1e-8) == 2 * l + 1
+
+
+def test_fourier_factor_is_a_dct_ii_mode():
+    from scipy.fft import dct
+    n = 16
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(n)
+    y = dct(v, type=2)
+    for mm in range(n // 2):
+        got = np.sum(v * S.fourier_factor((mm, 0), (n,)))
+        assert abs(got - (-1) ** mm * y[2 * mm] / 2) < 1e-12
+    # sin modes: sin(pi m x~) at the cell centres against the definition of x~
+    np.testing.assert_allclose(S.fourier_factor((3, 1), (n,)), np.sin(3 * np.pi * (np.arange(n) + 0.5) * 2 / n - 3 * np.pi),
+                               atol=1e-13)
+
+
+def test_paper_basis_plane_wave_response():
+    """B_(const, mult) cos(k.x) = (m(k) + m(-k))/2 cos(k.x), m from the library forms."""
+    shape, h, L = (16, 32), 5.0, 0.5
+    jz, jx = 3, 5
+    z = np.arange(shape[0])[:, None]
+    x = np.arange(shape[1])[None, :]
+    wave = np.cos(2 * np.pi * (jz * z / shape[0] + jx * x / shape[1]))
+    kx, kz = 2 * np.pi * jx / (shape[1] * h), 2 * np.pi * jz / (shape[0] * h)
+    r = np.hypot(kx, kz) * h / np.pi
+    th = np.arctan2(kz, kx)
+    for (a, q2), order in [((0, 2), 1), ((1, 0), 1), ((2, 3), -1), ((4, 1), 0), ((3, 2), 1)]:
+        tl = np.polynomial.chebyshev.chebval((r - L) / (r + L), [0] * q2 + [1])
+        def ang(t):
+            if a == 0:
+                return 1.0
+            j = (a + 1) // 2
+            return np.cos(j * t) if a % 2 else np.sin(j * t)
+        mk = ang(th) * tl * r ** order
+        mmk = ang(th + np.pi) * tl * r ** order
+        Bv = S.apply_paper_basis(wave, h, [(0, 0, 0)], [(a, q2)], order, L)[0]
+        np.testing.assert_allclose(Bv, 0.5 * (mk + mmk) * wave, atol=1e-12)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_paper_basis_fit_recovers_coefficients(ndim):
+    rng = np.random.default_rng(11 + ndim)
+    shape = (8, 16) if ndim == 2 else (4, 8, 8)
+    h, L, order = 10.0, 0.5, 1
+    modes = [(0,) * ndim + (0,), (1,) + (0,) * (ndim - 1) + (0,), (0,) * (ndim - 1) + (1, 1)]
+    mults = [(0, 0), (1, 1), (2, 0), (0, 2)] if ndim == 2 else [(0, 0), (3, 1), (6, 0), (0, 2)]
+    c_true = rng.standard_normal(len(modes) * len(mults))
+    xs = [rng.standard_normal(shape) for _ in range(2)]
+    ys = [np.tensordot(c_true, S.apply_paper_basis(x, h, modes, mults, order, L), axes=1) for x in xs]
+    c, relres, deficient = S.fit_with(lambda v: S.apply_paper_basis(v, h, modes, mults, order, L), ys, xs)
+    assert not deficient and relres < 1e-12
+    np.testing.assert_allclose(c, c_true, atol=1e-9)
