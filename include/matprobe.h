@@ -171,16 +171,38 @@ int mp_apply_H_batch(mp_ctx* ctx, int nreq, const int* counts, const int* shots,
 int mp_release_cache(mp_ctx* ctx);
 
 /* Probing basis (Sec. 1.2, eq. (1); Sec. 1.3): element i = a * nq + q is
- * B_i v = P_a(x~) * Re IFFT(rho^q FFT v), P_a = prod over axes of Legendre
- * polynomials of degree degs[a][axis] in the cell centres x~ = -1 + (2i+1)/N,
- * rho = |k| h / pi, periodic FFT on the model grid.
- * degs: host int32 [na][ndim] in axis order (x, [y,] z); qs: host int32 [nq]. */
+ * B_i v = P_a(x~) * Re IFFT(m_q(k) FFT v), a position factor P_a of the cell
+ * centres x~ = -1 + (2i+1)/N times a Fourier multiplier m_q, periodic FFT on the
+ * model grid, rho = |k| h / pi.  Two families:
+ *  MP_BASIS_LEGENDRE_RHO (0): P_a = prod over axes of Legendre polynomials of
+ *    degree degs[a][axis]; m_q = rho^qs[q].
+ *    degs: host int32 [na][ndim] in axis order (x, [y,] z); qs: host int32 [nq].
+ *  MP_BASIS_FOURIER_ANGULAR (1), the expansion of Sec. 1.2 (Fourier modes in x,
+ *    angular harmonics of k, rational Chebyshev functions of |k|, times |k|^e):
+ *    P_a = cos (phase 0) or sin (phase 1) of pi (m_x x~ + m_y y~ + m_z z~) with
+ *    modes[a] = (m_x, m_y, m_z, phase) (m_y = 0 in 2D);
+ *    m_q = A_{mults[q][0]}(k/|k|) * TL_{mults[q][1]}(rho) * rho^order with
+ *    TL_n(r) = T_n((r - L)/(r + L)), L = tl_scale > 0; A_0 = 1 and, in 2D,
+ *    A_{2j-1} = cos(j theta), A_{2j} = sin(j theta) (theta the angle of k from the
+ *    x axis toward z, j <= 8), in 3D the real spherical harmonics of degree <= 2
+ *    of n = k/|k| (1, n_x, n_y, n_z, n_x n_y, n_y n_z, 3 n_z^2 - 1, n_x n_z,
+ *    n_x^2 - n_y^2); at k = 0, A_0 = 1, every other A and rho^order (order != 0)
+ *    are 0.  modes: host int32 [na][4]; mults: host int32 [nq][2];
+ *    |m| <= 64, TL degree <= 16, -2 <= order <= 2.
+ * The descriptor is copied; the arrays may be freed after mp_basis_create. */
+#define MP_BASIS_LEGENDRE_RHO 0
+#define MP_BASIS_FOURIER_ANGULAR 1
 typedef struct mp_basis_desc {
   int ndim;
   int na;
-  const int* degs;
+  const int* degs;    /* family 0 */
   int nq;
-  const int* qs;
+  const int* qs;      /* family 0 */
+  int family;         /* MP_BASIS_* */
+  const int* modes;   /* family 1 */
+  const int* mults;   /* family 1 */
+  int order;          /* family 1 */
+  double tl_scale;    /* family 1 */
 } mp_basis_desc;
 
 int mp_basis_create(const mp_basis_desc* desc, mp_basis** out);

@@ -62,7 +62,9 @@ class Stats(ctypes.Structure):
 
 class BasisDesc(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("na", ctypes.c_int), ("degs", ctypes.POINTER(ctypes.c_int)),
-                ("nq", ctypes.c_int), ("qs", ctypes.POINTER(ctypes.c_int))]
+                ("nq", ctypes.c_int), ("qs", ctypes.POINTER(ctypes.c_int)), ("family", ctypes.c_int),
+                ("modes", ctypes.POINTER(ctypes.c_int)), ("mults", ctypes.POINTER(ctypes.c_int)),
+                ("order", ctypes.c_int), ("tl_scale", ctypes.c_double)]
 
 
 class MatprobeError(RuntimeError):

@@ -259,16 +259,56 @@ int mp_basis_create(const mp_basis_desc* d, mp_basis** out) {
   if (!d || !out) return fail(MP_EINVAL, "null argument");
   *out = nullptr;
   if (d->ndim != 2 && d->ndim != 3) return fail(MP_EINVAL, "ndim must be 2 or 3");
-  if (d->na < 1 || d->nq < 1 || !d->degs || !d->qs) return fail(MP_EINVAL, "empty basis");
-  for (int i = 0; i < d->na * d->ndim; ++i)
-    if (d->degs[i] < 0 || d->degs[i] > 16) return fail(MP_EINVAL, "Legendre degrees must be in [0, 16]");
-  for (int i = 0; i < d->nq; ++i)
-    if (d->qs[i] < 0 || d->qs[i] > 8) return fail(MP_EINVAL, "powers of rho must be in [0, 8]");
+  if (d->family != MP_BASIS_LEGENDRE_RHO && d->family != MP_BASIS_FOURIER_ANGULAR)
+    return fail(MP_EINVAL, "unknown basis family");
+  if (d->na < 1 || d->nq < 1) return fail(MP_EINVAL, "empty basis");
   if (d->na * d->nq > 64) return fail(MP_EUNSUPPORTED, "at most 64 basis terms");
   mp_basis* b = new mp_basis();
   b->b.ndim = d->ndim;
-  b->b.degs.assign(d->degs, d->degs + (size_t)d->na * d->ndim);
-  b->b.qs.assign(d->qs, d->qs + d->nq);
+  b->b.family = d->family;
+  if (d->family == MP_BASIS_LEGENDRE_RHO) {
+    if (!d->degs || !d->qs) {
+      delete b;
+      return fail(MP_EINVAL, "empty basis");
+    }
+    for (int i = 0; i < d->na * d->ndim; ++i)
+      if (d->degs[i] < 0 || d->degs[i] > 16) {
+        delete b;
+        return fail(MP_EINVAL, "Legendre degrees must be in [0, 16]");
+      }
+    for (int i = 0; i < d->nq; ++i)
+      if (d->qs[i] < 0 || d->qs[i] > 8) {
+        delete b;
+        return fail(MP_EINVAL, "powers of rho must be in [0, 8]");
+      }
+    b->b.degs.assign(d->degs, d->degs + (size_t)d->na * d->ndim);
+    b->b.qs.assign(d->qs, d->qs + d->nq);
+  } else {
+    std::string bad;
+    if (!d->modes || !d->mults) bad = "the Fourier-angular basis needs modes and mults";
+    else if (!(d->tl_scale > 0.0) || !std::isfinite(d->tl_scale)) bad = "tl_scale must be positive";
+    else if (d->order < -2 || d->order > 2) bad = "order must be in [-2, 2]";
+    for (int a = 0; bad.empty() && a < d->na; ++a) {
+      const int* m = d->modes + 4 * a;
+      for (int k = 0; k < 3; ++k)
+        if (m[k] < -64 || m[k] > 64) bad = "Fourier mode numbers must be in [-64, 64]";
+      if (d->ndim == 2 && m[1] != 0) bad = "2D Fourier modes need m_y = 0";
+      if (m[3] != 0 && m[3] != 1) bad = "mode phase must be 0 (cos) or 1 (sin)";
+    }
+    const int amax = d->ndim == 2 ? 16 : 8;
+    for (int q = 0; bad.empty() && q < d->nq; ++q) {
+      if (d->mults[2 * q] < 0 || d->mults[2 * q] > amax) bad = "angular index out of range";
+      if (d->mults[2 * q + 1] < 0 || d->mults[2 * q + 1] > 16) bad = "rational Chebyshev degree must be in [0, 16]";
+    }
+    if (!bad.empty()) {
+      delete b;
+      return fail(MP_EINVAL, bad);
+    }
+    b->b.modes.assign(d->modes, d->modes + (size_t)4 * d->na);
+    b->b.mults.assign(d->mults, d->mults + (size_t)2 * d->nq);
+    b->b.order = d->order;
+    b->b.tl_scale = d->tl_scale;
+  }
   *out = b;
   return MP_OK;
 }

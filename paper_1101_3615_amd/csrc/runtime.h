@@ -83,10 +83,15 @@ Engine* make_engine(const Config& c, Budget* b);
 // probing basis
 struct Basis {
   int ndim;
-  std::vector<int> degs;  // [na][ndim], axis order (x, [y,] z)
-  std::vector<int> qs;
-  int na() const { return (int)(degs.size() / ndim); }
-  int nq() const { return (int)qs.size(); }
+  int family = 0;         // MP_BASIS_*
+  std::vector<int> degs;  // family 0: [na][ndim], axis order (x, [y,] z)
+  std::vector<int> qs;    // family 0: [nq] powers of rho
+  std::vector<int> modes; // family 1: [na][4] (m_x, m_y, m_z, phase)
+  std::vector<int> mults; // family 1: [nq][2] (angular index, rational Chebyshev degree)
+  int order = 0;          // family 1: power of rho
+  double tl_scale = 1.0;  // family 1: L of TL_n
+  int na() const { return family == 0 ? (int)(degs.size() / ndim) : (int)(modes.size() / 4); }
+  int nq() const { return family == 0 ? (int)qs.size() : (int)(mults.size() / 2); }
 };
 
 }  // namespace mp

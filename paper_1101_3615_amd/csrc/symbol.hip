@@ -143,52 +143,127 @@ __device__ __forceinline__ R rho_at(long long i, const Grid3& g) {
   return R(2) * sqrt(fx * fx + fy * fy + fz * fz);
 }
 
-// out = X * sum_q coef[q] rho^qs[q]
+// signed frequencies j/N of FFT cell i per axis (x, y, z)
 template <typename R>
-__global__ void k_multiplier(Cx<R>* out, const Cx<R>* X, Grid3 g, int nq, const int* qs, const double* coef) {
+__device__ __forceinline__ void freq_at(long long i, const Grid3& g, R f[3]) {
+  const int c[3] = {(int)(i % g.n[0]), (int)((i / g.n[0]) % g.n[1]), (int)(i / ((long long)g.n[0] * g.n[1]))};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int j = (c[a] <= g.n[a] / 2 - (g.n[a] % 2 == 0 ? 1 : 0)) ? c[a] : c[a] - g.n[a];
+    f[a] = (R)j / (R)g.n[a];
+  }
+}
+
+// Angular harmonic `a` of the direction of k (f: frequencies per axis, fn = |f| > 0):
+// 2D (x, z): 1, cos(j theta), sin(j theta) for a = 0, 2j-1, 2j, theta = atan2(f_z, f_x);
+// 3D: the real spherical harmonics of degree <= 2 as polynomials of n = f / |f|.
+template <typename R>
+__device__ __forceinline__ R angular(int a, const R f[3], R fn, int ndim) {
+  if (ndim == 2) {
+    const R th = atan2(f[2], f[0]);
+    const R j = (R)((a + 1) / 2);
+    return (a & 1) ? cos(j * th) : sin(j * th);
+  }
+  const R nx = f[0] / fn, ny = f[1] / fn, nz = f[2] / fn;
+  switch (a) {
+    case 1: return nx;
+    case 2: return ny;
+    case 3: return nz;
+    case 4: return nx * ny;
+    case 5: return ny * nz;
+    case 6: return R(3) * nz * nz - R(1);
+    case 7: return nx * nz;
+    default: return nx * nx - ny * ny;
+  }
+}
+
+// rational Chebyshev TL_n(r) = T_n((r - L)/(r + L)) by the three-term recurrence
+template <typename R>
+__device__ __forceinline__ R rational_chebyshev(int n, R r, R L) {
+  const R t = (r - L) / (r + L);
+  R t0 = R(1), t1 = t;
+  if (n == 0) return t0;
+  for (int k = 1; k < n; ++k) {
+    const R t2 = R(2) * t * t1 - t0;
+    t0 = t1;
+    t1 = t2;
+  }
+  return t1;
+}
+
+// Multiplier of basis family `family` (see mp_basis_desc) times X:
+// out = X * sum_k coef[k] m_k.  Family 0: m_k = rho^qs[k]; family 1:
+// m_k = A_{qs[2k]}(k/|k|) TL_{qs[2k+1]}(rho) rho^order.
+template <typename R>
+__global__ void k_multiplier(Cx<R>* out, const Cx<R>* X, Grid3 g, int nq, const int* qs, const double* coef,
+                             int family, int ndim, int order, double tl_scale) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.cells; i += (long long)gridDim.x * blockDim.x) {
     const R r = rho_at<R>(i, g);
     R m = R(0);
-    for (int k = 0; k < nq; ++k) {
-      R pw = R(1);
-      for (int e = 0; e < qs[k]; ++e) pw *= r;
-      m += (R)coef[k] * pw;
+    if (family == 0) {
+      for (int k = 0; k < nq; ++k) {
+        R pw = R(1);
+        for (int e = 0; e < qs[k]; ++e) pw *= r;
+        m += (R)coef[k] * pw;
+      }
+    } else {
+      R f[3];
+      freq_at<R>(i, g, f);
+      const R fn = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+      R rp = R(1);   // rho^order, 0 at k = 0 unless order = 0
+      if (order != 0 && r == R(0)) rp = R(0);
+      else
+        for (int e = 0; e < abs(order); ++e) rp *= (order > 0) ? r : R(1) / r;
+      for (int k = 0; k < nq; ++k) {
+        const int a = qs[2 * k];
+        const R ang = (a == 0) ? R(1) : (fn == R(0) ? R(0) : angular<R>(a, f, fn, ndim));
+        m += (R)coef[k] * ang * rational_chebyshev<R>(qs[2 * k + 1], r, (R)tl_scale) * rp;
+      }
     }
     const Cx<R> v = X[i];
     out[i] = {v.x * m, v.y * m};
   }
 }
 
-// position factor P_a at cell i from per-axis Legendre tables leg[axis][deg][N_axis]
-__device__ __forceinline__ double pfac(long long i, const Grid3& g, const double* leg, int maxdeg, const int* deg) {
+// Position factor at cell i of the term spec sp = (kind, n_x, n_y, n_z, phase):
+// kind 0: product of Legendre polynomials of degrees n (per-axis tables
+// leg[axis][deg][N_axis]); kind 1: cos (phase 0) or sin (phase 1) of
+// pi (n_x x~ + n_y y~ + n_z z~) at the cell centres x~ = -1 + (2i+1)/N.
+__device__ __forceinline__ double pfac(long long i, const Grid3& g, const double* leg, int maxdeg, const int* sp) {
   const int x = (int)(i % g.n[0]);
   const long long t = i / g.n[0];
   const int y = (int)(t % g.n[1]);
   const int z = (int)(t / g.n[1]);
+  if (sp[0] == 1) {
+    const double pi = 3.14159265358979323846;
+    const double arg = pi * (sp[1] * (-1.0 + (2.0 * x + 1.0) / g.n[0]) + sp[2] * (-1.0 + (2.0 * y + 1.0) / g.n[1]) +
+                             sp[3] * (-1.0 + (2.0 * z + 1.0) / g.n[2]));
+    return sp[4] ? sin(arg) : cos(arg);
+  }
+  const int* deg = sp + 1;
   const int nmax = max(g.n[0], max(g.n[1], g.n[2]));
   const long long as = (long long)(maxdeg + 1) * nmax;
   return leg[0 * as + (long long)deg[0] * nmax + x] * leg[1 * as + (long long)deg[1] * nmax + y] *
          leg[2 * as + (long long)deg[2] * nmax + z];
 }
 
-// out (+)= P_a * Re(V) / N
+// out (+)= P_a * Re(V) / N, sp: the term's position-factor spec
 template <typename R, typename T>
-__global__ void k_accum_out(T* out, const Cx<R>* V, Grid3 g, const double* leg, int maxdeg, int d0, int d1, int d2,
+__global__ void k_accum_out(T* out, const Cx<R>* V, Grid3 g, const double* leg, int maxdeg, const int* sp,
                             double scale, int first) {
-  const int deg[3] = {d0, d1, d2};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.cells; i += (long long)gridDim.x * blockDim.x) {
-    const R v = (R)(pfac(i, g, leg, maxdeg, deg) * scale) * V[i].x;
+    const R v = (R)(pfac(i, g, leg, maxdeg, sp) * scale) * V[i].x;
     out[i] = first ? (T)v : (T)(out[i] + (T)v);
   }
 }
 
 // A[col(a, q)][row0 + i] = P_a(i) * Re(V[i]) / N for every a (one q)
 __global__ void k_columns(double* A, long long lda, long long row0, const Cx<double>* V, Grid3 g, const double* leg,
-                          int maxdeg, int na, int nq, int q, const int* degs, double scale) {
+                          int maxdeg, int na, int nq, int q, const int* specs, double scale) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.cells; i += (long long)gridDim.x * blockDim.x) {
     const double v = V[i].x * scale;
     for (int a = 0; a < na; ++a) {
-      A[(long long)(a * nq + q) * lda + row0 + i] = pfac(i, g, leg, maxdeg, degs + 3 * a) * v;
+      A[(long long)(a * nq + q) * lda + row0 + i] = pfac(i, g, leg, maxdeg, specs + 5 * a) * v;
     }
   }
 }
@@ -707,31 +782,48 @@ static Grid3 grid3(const Config& c) {
   return g;
 }
 
-// degrees (x, [y,] z) of the basis -> 3-axis (x, y, z) table, y = 0 in 2D
-static std::vector<int> degs3(const Basis& b) {
-  std::vector<int> d((size_t)b.na() * 3, 0);
+// position-factor specs (kind, n_x, n_y, n_z, phase) of the basis terms: Legendre
+// degrees (family 0, y = 0 in 2D) or Fourier mode numbers and phase (family 1)
+static std::vector<int> specs5(const Basis& b) {
+  std::vector<int> d((size_t)b.na() * 5, 0);
   for (int a = 0; a < b.na(); ++a) {
-    d[3 * a + 0] = b.degs[(size_t)a * b.ndim + 0];
-    if (b.ndim == 3) d[3 * a + 1] = b.degs[(size_t)a * b.ndim + 1];
-    d[3 * a + 2] = b.degs[(size_t)a * b.ndim + (b.ndim - 1)];
+    int* o = &d[5 * (size_t)a];
+    if (b.family == 0) {
+      o[1] = b.degs[(size_t)a * b.ndim + 0];
+      if (b.ndim == 3) o[2] = b.degs[(size_t)a * b.ndim + 1];
+      o[3] = b.degs[(size_t)a * b.ndim + (b.ndim - 1)];
+    } else {
+      o[0] = 1;
+      for (int k = 0; k < 4; ++k) o[1 + k] = b.modes[4 * (size_t)a + k];
+    }
   }
   return d;
 }
+static int max_degree(const Basis& b) {
+  int m = 0;
+  if (b.family == 0)
+    for (int v : b.degs) m = std::max(m, v);
+  return m;
+}
+// multiplier parameters as the kernel reads them: powers of rho (family 0) or
+// (angular index, rational Chebyshev degree) pairs (family 1)
+static const std::vector<int>& mult_table(const Basis& b) { return b.family == 0 ? b.qs : b.mults; }
 
 template <typename T, typename R>
 static int apply_t(mp_ctx* ctx, const Basis& b, const double* c, const void* img, void* out, hipStream_t s) {
   SymbolWS* ws = ws_of(ctx);
   const Config& cf = ctx->cfg;
   const long long n = cells_of(cf);
-  const std::vector<int> d3 = degs3(b);
-  int maxdeg = 0;
-  for (int v : d3) maxdeg = std::max(maxdeg, v);
+  const std::vector<int> sp = specs5(b);
+  const std::vector<int>& mt = mult_table(b);
   int rc;
-  if ((rc = ensure_tables(ctx, ws, maxdeg, s))) return rc;
+  if ((rc = ensure_tables(ctx, ws, max_degree(b), s))) return rc;
   if ((rc = ws->cx0.ensure(sizeof(Cx<R>) * n, &ctx->budget, "fft work"))) return rc;
   if ((rc = ws->cx1.ensure(sizeof(Cx<R>) * n, &ctx->budget, "fft work"))) return rc;
-  if ((rc = ws->qs.ensure(sizeof(int) * MAXP, &ctx->budget, "basis"))) return rc;
+  if ((rc = ws->qs.ensure(sizeof(int) * 2 * MAXP, &ctx->budget, "basis"))) return rc;
   if ((rc = ws->coef.ensure(sizeof(double) * MAXP, &ctx->budget, "basis"))) return rc;
+  if ((rc = ws->degs.ensure(sizeof(int) * 5 * MAXP, &ctx->budget, "basis"))) return rc;
+  SY_HIP(hipMemcpyAsync(ws->degs.get(), sp.data(), sizeof(int) * sp.size(), hipMemcpyHostToDevice, s));
   Cx<R>* X = ws->cx0.as<Cx<R>>();
   Cx<R>* Y = ws->cx1.as<Cx<R>>();
   hipLaunchKernelGGL((k_to_complex<R, T>), egrid(n), dim3(256), 0, s, X, static_cast<const T*>(img), n);
@@ -739,7 +831,7 @@ static int apply_t(mp_ctx* ctx, const Basis& b, const double* c, const void* img
   if ((rc = fft_nd<R>(ctx, ws, X, 0, s))) return rc;
   const Grid3 g = grid3(cf);
   const int nq = b.nq();
-  SY_HIP(hipMemcpyAsync(ws->qs.get(), b.qs.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
+  SY_HIP(hipMemcpyAsync(ws->qs.get(), mt.data(), sizeof(int) * mt.size(), hipMemcpyHostToDevice, s));
   std::vector<double> coef((size_t)b.na() * nq);
   for (size_t i = 0; i < coef.size(); ++i) coef[i] = c[i];
   DevBuf coefs;
@@ -747,12 +839,11 @@ static int apply_t(mp_ctx* ctx, const Basis& b, const double* c, const void* img
   SY_HIP(hipMemcpyAsync(coefs.get(), coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, s));
   for (int a = 0; a < b.na(); ++a) {
     hipLaunchKernelGGL(k_multiplier<R>, egrid(n), dim3(256), 0, s, Y, X, g, nq, ws->qs.as<int>(),
-                       coefs.as<double>() + (size_t)a * nq);
+                       coefs.as<double>() + (size_t)a * nq, b.family, b.ndim, b.order, b.tl_scale);
     SY_LAUNCH();
     if ((rc = fft_nd<R>(ctx, ws, Y, 1, s))) return rc;
     hipLaunchKernelGGL((k_accum_out<R, T>), egrid(n), dim3(256), 0, s, static_cast<T*>(out), Y, g,
-                       ws->leg.as<double>(), ws->maxdeg, d3[3 * a], d3[3 * a + 1], d3[3 * a + 2],
-                       1.0 / (double)n, a == 0 ? 1 : 0);
+                       ws->leg.as<double>(), ws->maxdeg, ws->degs.as<int>() + 5 * a, 1.0 / (double)n, a == 0 ? 1 : 0);
     SY_LAUNCH();
   }
   SY_HIP(hipStreamSynchronize(s));   // keeps the coefficient buffer alive until used
@@ -775,11 +866,10 @@ static int fit_t(mp_ctx* ctx, const Basis& b, int T_, const void* const* y, cons
   const int p = b.na() * b.nq();
   const long long nrows = n * T_;
   const long long lda = (nrows + 63) / 64 * 64;
-  const std::vector<int> d3 = degs3(b);
-  int maxdeg = 0;
-  for (int v : d3) maxdeg = std::max(maxdeg, v);
+  const std::vector<int> sp = specs5(b);
+  const std::vector<int>& mt = mult_table(b);
   int rc;
-  if ((rc = ensure_tables(ctx, ws, maxdeg, s))) return rc;
+  if ((rc = ensure_tables(ctx, ws, max_degree(b), s))) return rc;
   if ((rc = ws->cx0.ensure(sizeof(Cx<double>) * n, &ctx->budget, "fft work"))) return rc;
   if ((rc = ws->cx1.ensure(sizeof(Cx<double>) * n, &ctx->budget, "fft work"))) return rc;
   if ((rc = ws->A.ensure(sizeof(double) * (size_t)(p + 1) * lda, &ctx->budget, "fit columns"))) return rc;
@@ -788,27 +878,28 @@ static int fit_t(mp_ctx* ctx, const Basis& b, int T_, const void* const* y, cons
     return rc;
   if ((rc = ws->G0.ensure(sizeof(double) * GCOL * GCOL, &ctx->budget, "gram"))) return rc;
   if ((rc = ws->small.ensure(sizeof(Small), &ctx->budget, "solve"))) return rc;
-  if ((rc = ws->qs.ensure(sizeof(int) * MAXP, &ctx->budget, "basis"))) return rc;
+  if ((rc = ws->qs.ensure(sizeof(int) * 2 * MAXP, &ctx->budget, "basis"))) return rc;
   if ((rc = ws->coef.ensure(sizeof(double) * MAXP, &ctx->budget, "basis"))) return rc;
-  if ((rc = ws->degs.ensure(sizeof(int) * 3 * MAXP, &ctx->budget, "basis"))) return rc;
-  SY_HIP(hipMemcpyAsync(ws->degs.get(), d3.data(), sizeof(int) * d3.size(), hipMemcpyHostToDevice, s));
+  if ((rc = ws->degs.ensure(sizeof(int) * 5 * MAXP, &ctx->budget, "basis"))) return rc;
+  SY_HIP(hipMemcpyAsync(ws->degs.get(), sp.data(), sizeof(int) * sp.size(), hipMemcpyHostToDevice, s));
   double* A = ws->A.as<double>();
   Cx<double>* X = ws->cx0.as<Cx<double>>();
   Cx<double>* Y = ws->cx1.as<Cx<double>>();
   const Grid3 g = grid3(cf);
   const int nq = b.nq();
-  SY_HIP(hipMemcpyAsync(ws->qs.get(), b.qs.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
+  SY_HIP(hipMemcpyAsync(ws->qs.get(), mt.data(), sizeof(int) * mt.size(), hipMemcpyHostToDevice, s));
   const double one = 1.0;
   SY_HIP(hipMemcpyAsync(ws->coef.get(), &one, sizeof(double), hipMemcpyHostToDevice, s));
   SY_HIP(hipStreamSynchronize(s));
-  // columns: A[(a, q)][t*n + i] = P_a(i) Re IFFT(rho^q FFT x_t)(i); A[p][t*n + i] = y_t(i)
+  // columns: A[(a, q)][t*n + i] = P_a(i) Re IFFT(m_q FFT x_t)(i); A[p][t*n + i] = y_t(i)
   for (int t = 0; t < T_; ++t) {
     hipLaunchKernelGGL((k_to_complex<double, T>), egrid(n), dim3(256), 0, s, X, static_cast<const T*>(x[t]), n);
     SY_LAUNCH();
     if ((rc = fft_nd<double>(ctx, ws, X, 0, s))) return rc;
     for (int q = 0; q < nq; ++q) {
-      hipLaunchKernelGGL(k_multiplier<double>, egrid(n), dim3(256), 0, s, Y, X, g, 1, ws->qs.as<int>() + q,
-                         ws->coef.as<double>());
+      hipLaunchKernelGGL(k_multiplier<double>, egrid(n), dim3(256), 0, s, Y, X, g, 1,
+                         ws->qs.as<int>() + (b.family == 0 ? q : 2 * q), ws->coef.as<double>(), b.family, b.ndim,
+                         b.order, b.tl_scale);
       SY_LAUNCH();
       if ((rc = fft_nd<double>(ctx, ws, Y, 1, s))) return rc;
       hipLaunchKernelGGL(k_columns, egrid(n), dim3(256), 0, s, A, lda, (long long)t * n, Y, g, ws->leg.as<double>(),

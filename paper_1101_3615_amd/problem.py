@@ -157,18 +157,51 @@ class Problem:
 
 
 class Basis:
-    """Probing basis: Legendre position factors (numpy axis order) x powers of rho."""
+    """Probing basis (see mp_basis_desc).  Basis(legendre, qs, ndim): Legendre position
+    factors (degrees in numpy axis order) x powers of rho.  Basis.fourier_angular(...):
+    the expansion of Sec. 1.2 — Fourier modes in x x angular harmonics of k x rational
+    Chebyshev functions of |k| x |k|^order."""
+
+    _P = ctypes.POINTER(ctypes.c_int)
 
     def __init__(self, legendre, qs, ndim):
-        lib = L.lib()
+        self.family = 0
         self.legendre = [tuple(int(v) for v in a) for a in legendre]
         self.qs = [int(q) for q in qs]
         self.ndim = int(ndim)
         # C ABI takes degrees in axis order (x, [y,] z)
         degs = np.ascontiguousarray([list(reversed(a)) for a in self.legendre], dtype=np.int32)
         qs_arr = np.ascontiguousarray(self.qs, dtype=np.int32)
-        d = L.BasisDesc(self.ndim, len(self.legendre), degs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
-                        len(self.qs), qs_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+        self._create(L.BasisDesc(self.ndim, len(self.legendre), degs.ctypes.data_as(self._P), len(self.qs),
+                                 qs_arr.ctypes.data_as(self._P), 0, None, None, 0, 1.0))
+        self._na, self._nq = len(self.legendre), len(self.qs)
+
+    @classmethod
+    def fourier_angular(cls, modes, mults, ndim, order=1, tl_scale=0.5):
+        """modes: (m per numpy axis..., phase 0 cos / 1 sin); mults: (angular index,
+        rational Chebyshev degree); order: power of rho; tl_scale: L of TL_n."""
+        self = cls.__new__(cls)
+        self.family = 1
+        self.ndim = int(ndim)
+        self.modes = [tuple(int(v) for v in m) for m in modes]
+        self.mults = [tuple(int(v) for v in q) for q in mults]
+        self.order, self.tl_scale = int(order), float(tl_scale)
+        rows = []
+        for m in self.modes:   # numpy axis order (z, [y,] x) -> ABI (x, y, z)
+            ms, phase = list(m[:-1]), m[-1]
+            x, z = ms[-1], ms[0]
+            y = ms[1] if self.ndim == 3 else 0
+            rows.append([x, y, z, phase])
+        marr = np.ascontiguousarray(rows, dtype=np.int32)
+        qarr = np.ascontiguousarray(self.mults, dtype=np.int32)
+        self._create(L.BasisDesc(self.ndim, len(self.modes), None, len(self.mults), None, 1,
+                                 marr.ctypes.data_as(self._P), qarr.ctypes.data_as(self._P), self.order,
+                                 self.tl_scale))
+        self._na, self._nq = len(self.modes), len(self.mults)
+        return self
+
+    def _create(self, d):
+        lib = L.lib()
         h = ctypes.c_void_p()
         L.check(lib.mp_basis_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -176,7 +209,7 @@ class Basis:
 
     @property
     def p(self):
-        return len(self.legendre) * len(self.qs)
+        return self._na * self._nq
 
     def __del__(self):
         try:

@@ -61,3 +61,35 @@ def test_create_rejects_grids_past_the_32_bit_offset_limit():
     small = L.Grid(3, (ctypes.c_int * 3)(64, 64, 64), 10.0, 20)
     lib.mp_create(ctypes.byref(small), ctypes.byref(a), ctypes.byref(o), ctypes.byref(ctx))
     assert b"too large" not in lib.mp_last_error()
+
+
+def test_basis_descriptor_validation_without_device():
+    """mp_basis_create checks the descriptor on the host: the Fourier-angular family
+    (Sec. 1.2) needs its tables, a positive TL scale, bounded orders, indices and modes."""
+    import numpy as np
+    from paper_1101_3615_amd import _lib as L
+    lib = ctypes.CDLL(LIB)
+    lib.mp_last_error.restype = ctypes.c_char_p
+    P = ctypes.POINTER(ctypes.c_int)
+    modes = np.array([[0, 0, 0, 0], [1, 0, 2, 1]], np.int32)
+    mults = np.array([[0, 0], [3, 2]], np.int32)
+
+    def make(ndim=2, family=1, modes=modes, mults=mults, order=1, L_=0.5):
+        d = L.BasisDesc(ndim, len(modes), None, len(mults), None, family, modes.ctypes.data_as(P),
+                        mults.ctypes.data_as(P), order, L_)
+        h = ctypes.c_void_p()
+        rc = lib.mp_basis_create(ctypes.byref(d), ctypes.byref(h))
+        if rc == 0:
+            lib.mp_basis_destroy(h)
+        return rc, lib.mp_last_error()
+
+    assert make()[0] == 0
+    assert make(ndim=3)[0] == 0
+    assert make(family=7) == (-1, b"unknown basis family")
+    assert make(L_=0.0)[1] == b"tl_scale must be positive"
+    assert make(order=3)[1] == b"order must be in [-2, 2]"
+    assert make(mults=np.array([[17, 0]], np.int32))[1] == b"angular index out of range"
+    assert make(ndim=3, mults=np.array([[9, 0]], np.int32))[1] == b"angular index out of range"
+    assert make(mults=np.array([[0, 17]], np.int32))[1] == b"rational Chebyshev degree must be in [0, 16]"
+    assert make(modes=np.array([[0, 1, 0, 0]], np.int32))[1] == b"2D Fourier modes need m_y = 0"
+    assert make(modes=np.array([[0, 0, 0, 2]], np.int32))[1] == b"mode phase must be 0 (cos) or 1 (sin)"

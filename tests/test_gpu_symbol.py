@@ -109,3 +109,81 @@ def test_non_power_of_two_rejected():
     with pytest.raises(M.MatprobeError) as e:
         M.apply_Hinv(P, B, np.array([1.0]), torch.zeros(32, 48, dtype=torch.float64))
     assert e.value.code == -6
+
+
+# ---- the paper's expansion: Fourier modes x angular harmonics x rational Chebyshev ----
+
+MODES2 = [(0, 0, 0), (1, 0, 0), (0, 2, 1), (1, 1, 1), (2, 3, 0)]          # (m_z, m_x, phase)
+MULTS2 = [(0, 0), (1, 1), (2, 0), (3, 2), (4, 1), (6, 3)]                 # (angle, TL degree)
+MODES3 = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 1, 2, 1)]                        # (m_z, m_y, m_x, phase)
+MULTS3 = [(0, 0), (1, 1), (3, 0), (6, 2), (8, 1)]
+
+
+def _cube_pow2(dtype, nx=16, ny=8, nz=8):
+    from fixtures.configs import Workload
+    src = np.array([[1, 1, 0]], np.int32)
+    rec = np.array([[2, 2, 0], [5, 3, 1]], np.int32)
+    return Workload(name="cube_p2", ndim=3, nx=nx, ny=ny, nz=nz, h=12.5, nb=4, dt=1.0e-3, nt=10,
+                    f_peak=15.0, src=src, rec=rec, dtype=dtype, snap="full", ckpt_every=0,
+                    medium=dict(kind="smooth_random", cmin=1500.0, cmax=3500.0, corr=60.0, seed=41))
+
+
+@pytest.mark.parametrize("dtype,order", [("f64", 1), ("f64", -1), ("f64", 0), ("f64", 2), ("f32", 1), ("f32", -1)])
+def test_paper_basis_apply_Hinv_matches_oracle_2d(dtype, order):
+    M = _gpu()
+    shape = (32, 64)
+    w = F.tiny(n=8, nr=8, dtype=dtype).with_(nx=shape[1], nz=shape[0])
+    P = _problem(M, w)
+    B = M.Basis.fourier_angular(MODES2, MULTS2, 2, order=order, tl_scale=0.5)
+    c = np.random.default_rng(21).standard_normal(B.p)
+    img = F.normal_field(shape, 13)
+    got = M.apply_Hinv(P, B, c, torch.from_numpy(img)).cpu().numpy()
+    ref = np.tensordot(c, S.apply_paper_basis(img.astype(np.float64), w.h, MODES2, MULTS2, order, 0.5), axes=1)
+    assert rel(got, ref) <= (1e-12 if dtype == "f64" else 2e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_paper_basis_apply_Hinv_matches_oracle_3d(dtype):
+    M = _gpu()
+    w = _cube_pow2(dtype)
+    P = _problem(M, w)
+    B = M.Basis.fourier_angular(MODES3, MULTS3, 3, order=1, tl_scale=0.75)
+    c = np.random.default_rng(22).standard_normal(B.p)
+    img = F.normal_field(w.model_shape, 14)
+    got = M.apply_Hinv(P, B, c, torch.from_numpy(img)).cpu().numpy()
+    ref = np.tensordot(c, S.apply_paper_basis(img.astype(np.float64), w.h, MODES3, MULTS3, 1, 0.75), axes=1)
+    assert rel(got, ref) <= (1e-12 if dtype == "f64" else 2e-6)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_paper_basis_fit_exact_recovery(ndim):
+    M = _gpu()
+    if ndim == 2:
+        w = F.tiny(n=8, nr=8, dtype="f64").with_(nx=64, nz=32)
+        modes, mults = MODES2[:4], MULTS2[:4]
+    else:
+        w = _cube_pow2("f64")
+        modes, mults = MODES3, MULTS3[:4]
+    P = _problem(M, w)
+    B = M.Basis.fourier_angular(modes, mults, ndim, order=1, tl_scale=0.5)
+    ctrue = np.random.default_rng(23).standard_normal(B.p)
+    xs = [F.normal_field(w.model_shape, 90 + t).astype(np.float64) for t in range(2)]
+    ys = [np.tensordot(ctrue, S.apply_paper_basis(x, w.h, modes, mults, 1, 0.5), axes=1) for x in xs]
+    c, relres = M.probe_fit(P, B, [torch.from_numpy(y) for y in ys], [torch.from_numpy(x) for x in xs])
+    assert np.max(np.abs(c - ctrue)) <= 1e-10 * np.max(np.abs(ctrue))
+    assert relres < 1e-10
+
+
+def test_paper_basis_fit_matches_oracle_least_squares():
+    M = _gpu()
+    w = F.tiny(n=8, nr=8, dtype="f64").with_(nx=64, nz=64)
+    P = _problem(M, w)
+    modes, mults = MODES2[:3], MULTS2[:4]
+    B = M.Basis.fourier_angular(modes, mults, 2, order=-1, tl_scale=0.5)
+    xs = [F.normal_field((64, 64), 100 + t) for t in range(2)]
+    ys = [F.normal_field((64, 64), 110 + t) for t in range(2)]
+    c, relres = M.probe_fit(P, B, [torch.from_numpy(y) for y in ys], [torch.from_numpy(x) for x in xs])
+    cref, rref, _ = S.fit_with(lambda v: S.apply_paper_basis(v, w.h, modes, mults, -1, 0.5),
+                               [y.astype(np.float64) for y in ys], [x.astype(np.float64) for x in xs])
+    assert rel(c, cref) <= 1e-10
+    assert abs(relres - rref) <= 1e-10 * rref
