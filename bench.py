@@ -228,6 +228,31 @@ def volume_run(nt):
             "gcell_steps_per_s": round(cs / wall / 1e9, 2), "sweeps": sweeps}
 
 
+GEN_SIZES = [(0, 0, 0), (0, 1, 1), (0, 2, 2), (1, 0, 2), (1, 2, 2)]   # (Fourier m, angular a, TL degree r): p = 1, 4, 9, 21, 63
+
+
+def generalization_run(ns=(1, 2, 4)):
+    """Rn generalization (relative MSE on an independent trial function) against the
+    number of basis terms p, on the 128x128 FP64 workload."""
+    import torch
+
+    import fixtures as F
+    import paper_1101_3615_amd as M
+    from paper_1101_3615_amd.study import generalization, paper_bases
+    w = F.c1()
+    c = F.medium(w)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c).to("cuda:0"))
+    trials = [torch.from_numpy(F.wavepackets(w, c, 100 + s, w.packets_per_trial)).to("cuda:0") for s in range(5)]
+    bases = paper_bases(2, GEN_SIZES)
+    out = []
+    for n in ns:
+        for p, mse, relres, deficient in generalization(P, bases, trials[:n], trials[4]):
+            out.append({"study": "generalization", "workload": w.name, "preconditioner": f"R{n}", "p": p,
+                        "relative_mse": round(mse, 6), "fit_relres": round(relres, 6), "rank_deficient": deficient})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +267,10 @@ def main():
     ap.add_argument("--volume-steps", type=int, default=0,
                     help="only run apply_H on the 256^3 workload (32 shots, BF16 checkpoints) with this "
                          "many time steps and print its sweep times (3D measurement and profiling)")
+    ap.add_argument("--generalization", action="store_true",
+                    help="only run the generalization study of the probed inverse (128x128 FP64 workload, "
+                         "R1/R2/R4 fitted on 1/2/4 trial functions, tested on an independent one, bases of the "
+                         "paper's expansion with growing p) and print one JSON line per fit")
     ap.add_argument("--cpu-workers", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -270,6 +299,10 @@ def main():
         return
     if args.volume_steps:
         print(json.dumps(volume_run(args.volume_steps)))
+        return
+    if args.generalization:
+        for rec in generalization_run():
+            print(json.dumps(rec), flush=True)
         return
 
     # CPU baseline first: forked workers must not inherit an initialised GPU runtime

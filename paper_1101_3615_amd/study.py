@@ -1,0 +1,52 @@
+"""Generalization of the probed inverse (Sec. 3.2 of the paper, "Rn" preconditioners).
+
+The preconditioner Rn fits the inverse-Hessian symbol from n trial functions y_t
+and their images x_t = H y_t (Sec. 1.3), then is judged on a trial function y'
+drawn independently of them: the relative mean-square error of reconstructing
+y' from H y' through the fitted series,
+
+    MSE = || sum_i c_i B_i (H y') - y' ||^2 / || y' ||^2,
+
+as a function of the number p of basis terms.  Below 1, the preconditioner helps.
+Everything runs through the library's operators (apply_H, probe_fit, apply_Hinv).
+"""
+import numpy as np
+
+from .problem import apply_Hinv, probe_fit
+
+
+def paper_bases(ndim, sizes, order=-1, tl_scale=0.5):
+    """Nested bases of the paper's expansion with growing p: for each (m, a, r) in
+    sizes, Fourier modes with |m_axis| <= m (cos and sin, the constant once), angular
+    indices 0..a and rational Chebyshev degrees 0..r (order -1: the symbol order of
+    the inverse Hessian)."""
+    import itertools
+
+    from .problem import Basis
+    out = []
+    for m, a, r in sizes:
+        modes = [(0,) * ndim + (0,)]
+        for ms in itertools.product(range(m + 1), repeat=ndim):
+            if any(ms):
+                modes += [tuple(ms) + (0,), tuple(ms) + (1,)]
+        mults = [(ai, ri) for ai in range(a + 1) for ri in range(r + 1)]
+        if len(modes) * len(mults) > 64:
+            raise ValueError("at most 64 basis terms")
+        out.append(Basis.fourier_angular(modes, mults, ndim, order=order, tl_scale=tl_scale))
+    return out
+
+
+def generalization(problem, bases, ys_fit, y_new):
+    """[(p, relative MSE on y_new, relative residual of the fit, rank deficient), ...]
+    for the preconditioner fitted on ys_fit with each basis (torch tensors on the
+    problem's device)."""
+    xs = [problem.apply_H(y).clone() for y in ys_fit]
+    x_new = problem.apply_H(y_new).clone()
+    ref = y_new.to(device=x_new.device).double()
+    out = []
+    for B in bases:
+        c, relres, deficient = probe_fit(problem, B, ys_fit, xs, strict=False)
+        rec = apply_Hinv(problem, B, c, x_new).double()
+        mse = float(((rec - ref) ** 2).sum() / (ref ** 2).sum())
+        out.append((B.p, mse, float(relres), bool(deficient)))
+    return out
