@@ -1,0 +1,77 @@
+"""FP64 CPU oracle of the linearised inversion around the probed inverse (test
+infrastructure only).
+
+Sec. 1 of the paper: the normal equations H dm = b with b = F* d the migrated image
+(least squares for the linearised modelling), solved by brute-force descent (Sec. 2:
+200 gradient-descent steps give the reference image) or, as the paper suggests, by a
+Krylov solver with the fitted inverse as preconditioner.  Two kinds of fitted
+preconditioners (Sec. 2):
+  Rn  fitted from n random trial functions y_t and x_t = H y_t (Sec. 1.3);
+  Kn  fitted from the Krylov subspace of the migrated image: the pairs
+      (y_j, x_j) = (H^(j-1) b, H^j b), j = 1..n, so that the fit maps H^j b back to
+      H^(j-1) b (K1: migrated and remigrated image).
+The solvers take the operator as a function (matvec) so that they can be pinned on
+small dense matrices.  Errors between models are relative mean-square errors.
+"""
+import numpy as np
+
+
+def relative_mse(m, ref):
+    """||m - ref||^2 / ||ref||^2 (the paper's relative mean-squared error)."""
+    m = np.asarray(m, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.sum((m - ref) ** 2) / np.sum(ref ** 2))
+
+
+def krylov_pairs(matvec, b, n):
+    """[(y_j, x_j)] = [(H^(j-1) b, H^j b)] for j = 1..n."""
+    out = []
+    y = np.asarray(b, dtype=np.float64)
+    for _ in range(n):
+        x = matvec(y)
+        out.append((y, x))
+        y = x
+    return out
+
+
+def steepest_descent(matvec, b, steps, x0=None):
+    """Gradient descent on 1/2 x.Hx - b.x with the exact step along the residual:
+    r = b - H x, alpha = r.r / r.Hr, x <- x + alpha r."""
+    x = np.zeros_like(np.asarray(b, dtype=np.float64)) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - matvec(x)
+    for _ in range(steps):
+        Hr = matvec(r)
+        rr, rHr = float(np.sum(r * r)), float(np.sum(r * Hr))
+        if rHr <= 0.0 or rr == 0.0:
+            break
+        alpha = rr / rHr
+        x = x + alpha * r
+        r = r - alpha * Hr
+    return x
+
+
+def conjugate_gradient(matvec, b, iters, precond=None, x0=None):
+    """(Preconditioned) conjugate gradients on H x = b:
+    r0 = b - H x0, z = M r, p = z; alpha = r.z / p.Hp; x += alpha p; r -= alpha Hp;
+    z' = M r; beta = r'.z' / r.z; p = z' + beta p.  Returns x and the residual norms."""
+    x = np.zeros_like(np.asarray(b, dtype=np.float64)) if x0 is None else np.array(x0, dtype=np.float64)
+    M = precond if precond is not None else (lambda v: v)
+    r = b - matvec(x)
+    z = M(r)
+    p = z.copy()
+    rz = float(np.sum(r * z))
+    norms = [float(np.linalg.norm(r))]
+    for _ in range(iters):
+        Hp = matvec(p)
+        pHp = float(np.sum(p * Hp))
+        if pHp == 0.0:
+            break
+        alpha = rz / pHp
+        x = x + alpha * p
+        r = r - alpha * Hp
+        norms.append(float(np.linalg.norm(r)))
+        z = M(r)
+        rz_new = float(np.sum(r * z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, norms
