@@ -253,6 +253,68 @@ def generalization_run(ns=(1, 2, 4)):
     return out
 
 
+def inversion_run(gd_steps=200, cg_iters=20):
+    """Linearised inversion of a synthetic reflectivity on the 128x128 FP64 workload: the
+    migrated image b = H m, the reference image after gd_steps exact-step descent steps,
+    the Rn / Kn fitted inverses applied to b (relative MSE against the reference and
+    against m, for each basis size), and CG with and without a fitted preconditioner."""
+    import numpy as np
+    import torch
+
+    import fixtures as F
+    import paper_1101_3615_amd as M
+    from paper_1101_3615_amd import inversion as I
+    from paper_1101_3615_amd.study import paper_bases
+    w = F.c1()
+    c = F.medium(w)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c).to("cuda:0"))
+    m = torch.from_numpy(F.reflectivity(w, c, seed=5).astype(np.float64)).to("cuda:0")
+    b = P.apply_H(m)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    x_gd, phis = I.steepest_descent(P, b, gd_steps)
+    torch.cuda.synchronize()
+    ms_gd = (time.perf_counter() - t) * 1e3 / gd_steps
+    r = b - P.apply_H(x_gd)
+    out = [{"study": "inversion", "workload": w.name, "image": f"descent{gd_steps}", "ms_per_step": round(ms_gd, 3),
+            "relres": round(float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)), 6),
+            "mse_vs_true": round(I.relative_mse(x_gd, m), 6)}]
+    a = float((b * x_gd).sum() / (b * b).sum())
+    out.append({"study": "inversion", "workload": w.name, "image": "migrated (best scalar multiple)",
+                "mse_vs_descent": round(I.relative_mse(a * b, x_gd), 6), "mse_vs_true": round(I.relative_mse(a * b, m), 6)})
+    trials = [torch.from_numpy(F.wavepackets(w, c, 100 + s, w.packets_per_trial)).to("cuda:0") for s in range(4)]
+    Htrials = [P.apply_H(y) for y in trials]
+    kys, kxs = I.krylov_pairs(P, b, 4)
+    fits = {"R1": (trials[:1], Htrials[:1]), "R4": (trials, Htrials),
+            "K1": (kys[:1], kxs[:1]), "K2": (kys[:2], kxs[:2]), "K4": (kys, kxs)}
+    bases = paper_bases(2, GEN_SIZES)
+    precs = {}
+    for name, (ys, xs) in fits.items():
+        for B in bases:
+            coef, relres, deficient = M.probe_fit(P, B, ys, xs, strict=False)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            img = M.apply_Hinv(P, B, coef, b)
+            torch.cuda.synchronize()
+            out.append({"study": "inversion", "workload": w.name, "preconditioner": name, "p": B.p,
+                        "mse_vs_descent": round(I.relative_mse(img, x_gd), 6),
+                        "mse_vs_true": round(I.relative_mse(img, m), 6), "fit_relres": round(relres, 6),
+                        "rank_deficient": deficient, "apply_ms": round((time.perf_counter() - t) * 1e3, 3)})
+            if B.p == 21:
+                precs[name] = I.preconditioner(P, B, coef)
+    for name in ("none", "R4", "K1"):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, norms = I.conjugate_gradient(P, b, cg_iters, precond=precs.get(name))
+        torch.cuda.synchronize()
+        out.append({"study": "inversion", "workload": w.name, "solver": "CG", "preconditioner": name, "p": 21,
+                    "iters": len(norms) - 1, "ms_per_iter": round((time.perf_counter() - t) * 1e3 / cg_iters, 3),
+                    "relres": [round(v / norms[0], 6) for v in norms],
+                    "mse_vs_descent": round(I.relative_mse(x, x_gd), 6), "mse_vs_true": round(I.relative_mse(x, m), 6)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +333,10 @@ def main():
                     help="only run the generalization study of the probed inverse (128x128 FP64 workload, "
                          "R1/R2/R4 fitted on 1/2/4 trial functions, tested on an independent one, bases of the "
                          "paper's expansion with growing p) and print one JSON line per fit")
+    ap.add_argument("--inversion", action="store_true",
+                    help="only run the linearised inversion study (128x128 FP64 workload: 200 descent steps as "
+                         "the reference image, Rn/Kn fitted inverses applied to the migrated image, CG with and "
+                         "without a fitted preconditioner) and print one JSON line per result")
     ap.add_argument("--cpu-workers", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -302,6 +368,10 @@ def main():
         return
     if args.generalization:
         for rec in generalization_run():
+            print(json.dumps(rec), flush=True)
+        return
+    if args.inversion:
+        for rec in inversion_run():
             print(json.dumps(rec), flush=True)
         return
 

@@ -3,7 +3,7 @@
 Every array is produced in float64 and rounded to float32 once; the rounded
 values are what both the oracle and the GPU path consume.  The recipes stand in
 for the Marmousi model and the curvelet-masked noise of the paper (Sec. 2 and
-Sec. 1.4), which are not available here:
+Sec. 1.5), which are not available here:
 
 * smooth random media: seeded N(0,1) noise filtered by a periodic Gaussian of
   standard deviation ``corr`` metres, then mapped affinely onto

@@ -11,8 +11,8 @@
  *          (Sec. 1.1);
  *   H      the normal operator F*F (Sec. 1.1), stacked over shots (Sec. 2);
  *   fit    least-squares coefficients of H^-1 ~ sum_i c_i B_i from x_t = H y_t
- *          (Sec. 1.3, expansion H^-1 = sum c_i B_i of Sec. 1.2);
- *   Hinv   the fast application of the fitted series (end of Sec. 1.4).
+ *          (Sec. 1.4, expansion H^-1 = sum c_i B_i of Sec. 1.2);
+ *   Hinv   the fast application of the fitted series (end of Sec. 1.5).
  *
  * Discretisation (fixed by this library, identical in its CPU reference):
  *   - model grid nx x nz (x ny in 3D), spacing h; an absorbing layer of nb
@@ -170,7 +170,7 @@ int mp_apply_H_batch(mp_ctx* ctx, int nreq, const int* counts, const int* shots,
 /* Drop the cached background wavefield and free the memory it holds. */
 int mp_release_cache(mp_ctx* ctx);
 
-/* Probing basis (Sec. 1.2, eq. (1); Sec. 1.3): element i = a * nq + q is
+/* Probing basis (Sec. 1.2, eq. (1); Sec. 1.4): element i = a * nq + q is
  * B_i v = P_a(x~) * Re IFFT(m_q(k) FFT v), a position factor P_a of the cell
  * centres x~ = -1 + (2i+1)/N times a Fourier multiplier m_q, periodic FFT on the
  * model grid, rho = |k| h / pi.  Two families:
@@ -209,7 +209,7 @@ int mp_basis_create(const mp_basis_desc* desc, mp_basis** out);
 void mp_basis_destroy(mp_basis* b);
 
 /* Least-squares fit of c (host, FP64, p = na * nq entries) minimising
- * sum_t || sum_i c_i B_i x_t - y_t ||^2 over T trials (Sec. 1.3).
+ * sum_t || sum_i c_i B_i x_t - y_t ||^2 over T trials (Sec. 1.4).
  * y_dev[t], x_dev[t]: device model vectors in the field precision (x_t = H y_t).
  * The stacked system is solved on the device in FP64 by shifted
  * Cholesky-QR (three passes), its Gram products on the FP64 matrix cores.
@@ -219,7 +219,7 @@ void mp_basis_destroy(mp_basis* b);
 int mp_probe_fit(mp_ctx* ctx, const mp_basis* basis, int T, const void* const* y_dev,
                  const void* const* x_dev, double* c, double* relres, void* stream);
 
-/* out_dev = sum_i c_i B_i img_dev (c: host FP64 [p]); end of Sec. 1.4. */
+/* out_dev = sum_i c_i B_i img_dev (c: host FP64 [p]); end of Sec. 1.5. */
 int mp_apply_Hinv(mp_ctx* ctx, const mp_basis* basis, const double* c, const void* img_dev,
                   void* out_dev, void* stream);
 

@@ -6,7 +6,7 @@ Sec. 1 of the paper: the normal equations H dm = b with b = F* d the migrated im
 200 gradient-descent steps give the reference image) or, as the paper suggests, by a
 Krylov solver with the fitted inverse as preconditioner.  Two kinds of fitted
 preconditioners (Sec. 2):
-  Rn  fitted from n random trial functions y_t and x_t = H y_t (Sec. 1.3);
+  Rn  fitted from n random trial functions y_t and x_t = H y_t (Sec. 1.4);
   Kn  fitted from the Krylov subspace of the migrated image: the pairs
       (y_j, x_j) = (H^(j-1) b, H^j b), j = 1..n, so that the fit maps H^j b back to
       H^(j-1) b (K1: migrated and remigrated image).
@@ -17,10 +17,11 @@ import numpy as np
 
 
 def relative_mse(m, ref):
-    """||m - ref||^2 / ||ref||^2 (the paper's relative mean-squared error)."""
+    """||m - ref||_2 / ||ref||_2: the paper's relative mean-squared error between a
+    reference model and another one (Sec. 2), a ratio of 2-norms (not squared)."""
     m = np.asarray(m, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
-    return float(np.sum((m - ref) ** 2) / np.sum(ref ** 2))
+    return float(np.linalg.norm(m - ref) / np.linalg.norm(ref))
 
 
 def krylov_pairs(matvec, b, n):

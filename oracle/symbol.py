@@ -12,12 +12,12 @@ coordinates ``x~ = -1 + (2i+1)/N`` of each model axis, ``rho = |k| h / pi`` the
 wavenumber normalised to 1 at the Nyquist frequency of each axis, and a
 periodic FFT on the model grid.
 
-Fit (Sec. 1.3): with x_t = H y_t, minimise over c the stacked residual
+Fit (Sec. 1.4): with x_t = H y_t, minimise over c the stacked residual
 ||sum_i c_i B_i x_t - y_t|| over all trials t (the normal equations of this
 least-squares problem are the paper's M c = (B x)^T y with
 M_ij = x^T B_i^T B_j x).  Solved here by Householder QR of the stacked matrix.
 
-Fast application (Sec. 1.4, last paragraph): out = sum_i c_i B_i img.
+Fast application (Sec. 1.5, last paragraph): out = sum_i c_i B_i img.
 """
 import numpy as np
 

@@ -1,5 +1,5 @@
 // Probing basis on the model grid: FFT multipliers, the FP64 least-squares
-// fit (paper Sec. 1.3) and the fast application of the fitted series.
+// fit (paper Sec. 1.4) and the fast application of the fitted series.
 //
 //   B_(a,q) v = P_a(x~) * Re IFFT( rho^q FFT v ),   rho = |k| h / pi
 //

@@ -1,0 +1,95 @@
+"""Linearised inversion around the probed inverse (Sec. 1 and Sec. 2 of the paper).
+
+The normal equations H dm = b, b = F* d the migrated image, solved by steepest
+descent with exact steps (Sec. 2 takes 200 gradient-descent steps as the reference
+image) or by conjugate gradients preconditioned with a fitted inverse (the paper's
+motivation, Sec. 1).  Two fitted preconditioners (Sec. 2): Rn from n random trial
+functions (probe_fit on (y_t, H y_t)) and Kn from the Krylov subspace of the
+migrated image, the pairs (H^(j-1) b, H^j b), j = 1..n.
+
+Every operator application runs in the library's kernels (apply_H, apply_Hinv,
+probe_fit); the few vector updates per iteration (dot products, axpy) are torch
+operations on the problem's device.
+"""
+import torch
+
+from .problem import apply_Hinv, probe_fit
+
+
+def relative_mse(m, ref):
+    """||m - ref||_2 / ||ref||_2 (the paper's relative MSE between models, Sec. 2: a ratio
+    of norms, not of squared norms)."""
+    m, ref = m.double(), ref.to(m.device).double()
+    return float(torch.linalg.vector_norm(m - ref) / torch.linalg.vector_norm(ref))
+
+
+def _dot(a, b):
+    return float((a.double() * b.double()).sum())
+
+
+def krylov_pairs(problem, b, n):
+    """([y_1..y_n], [x_1..x_n]) with y_1 = b, x_j = H y_j, y_{j+1} = x_j."""
+    ys, xs = [], []
+    y = b
+    for _ in range(n):
+        x = problem.apply_H(y)
+        ys.append(y)
+        xs.append(x)
+        y = x
+    return ys, xs
+
+
+def fit_krylov(problem, basis, b, n):
+    """Kn: coefficients fitted on the Krylov pairs of b (c, relres, rank_deficient)."""
+    ys, xs = krylov_pairs(problem, b, n)
+    return probe_fit(problem, basis, ys, xs, strict=False)
+
+
+def preconditioner(problem, basis, c):
+    """v -> sum_i c_i B_i v (the fitted inverse as a function)."""
+    return lambda v: apply_Hinv(problem, basis, c, v)
+
+
+def steepest_descent(problem, b, steps):
+    """x <- x + alpha r with r = b - H x and alpha = r.r / r.Hr, from x = 0.  Returns x
+    and the values of the functional 1/2 x.Hx - b.x = -1/2 x.(b + r), one per iterate
+    (the first for x = 0); exact steps make them non-increasing."""
+    x = torch.zeros_like(b)
+    r = b.clone()
+    phis = [0.0]
+    for _ in range(steps):
+        Hr = problem.apply_H(r)
+        rr, rHr = _dot(r, r), _dot(r, Hr)
+        if rHr <= 0.0 or rr == 0.0:
+            break
+        alpha = rr / rHr
+        x += alpha * r
+        r -= alpha * Hr
+        phis.append(-0.5 * _dot(x, b + r))
+    return x, phis
+
+
+def conjugate_gradient(problem, b, iters, precond=None):
+    """(Preconditioned) conjugate gradients on H x = b from x = 0; returns x and the
+    residual norms (one per iteration, the first for x = 0)."""
+    M = precond if precond is not None else (lambda v: v)
+    x = torch.zeros_like(b)
+    r = b.clone()
+    z = M(r)
+    p = z.clone()
+    rz = _dot(r, z)
+    norms = [_dot(r, r) ** 0.5]
+    for _ in range(iters):
+        Hp = problem.apply_H(p)
+        pHp = _dot(p, Hp)
+        if pHp == 0.0:
+            break
+        alpha = rz / pHp
+        x += alpha * p
+        r -= alpha * Hp
+        norms.append(_dot(r, r) ** 0.5)
+        z = M(r)
+        rz_new = _dot(r, z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, norms

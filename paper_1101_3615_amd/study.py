@@ -1,17 +1,19 @@
-"""Generalization of the probed inverse (Sec. 3.2 of the paper, "Rn" preconditioners).
+"""Generalization of the probed inverse (Sec. 2.2 of the paper, "Rn" preconditioners).
 
 The preconditioner Rn fits the inverse-Hessian symbol from n trial functions y_t
-and their images x_t = H y_t (Sec. 1.3), then is judged on a trial function y'
-drawn independently of them: the relative mean-square error of reconstructing
-y' from H y' through the fitted series,
+and their images x_t = H y_t (Sec. 1.4), then is judged on a trial function y'
+drawn independently of them: the relative mean-squared error (defined in the
+paper's numerical section as a ratio of 2-norms, not of their squares) of
+reconstructing y' from H y' through the fitted series,
 
-    MSE = || sum_i c_i B_i (H y') - y' ||^2 / || y' ||^2,
+    MSE = || sum_i c_i B_i (H y') - y' ||_2 / || y' ||_2,
 
 as a function of the number p of basis terms.  Below 1, the preconditioner helps.
 Everything runs through the library's operators (apply_H, probe_fit, apply_Hinv).
 """
 import numpy as np
 
+from .inversion import relative_mse
 from .problem import apply_Hinv, probe_fit
 
 
@@ -47,6 +49,6 @@ def generalization(problem, bases, ys_fit, y_new):
     for B in bases:
         c, relres, deficient = probe_fit(problem, B, ys_fit, xs, strict=False)
         rec = apply_Hinv(problem, B, c, x_new).double()
-        mse = float(((rec - ref) ** 2).sum() / (ref ** 2).sum())
+        mse = relative_mse(rec, ref)
         out.append((B.p, mse, float(relres), bool(deficient)))
     return out

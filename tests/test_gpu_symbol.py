@@ -57,7 +57,7 @@ def test_single_multiplier_terms():
 
 @pytest.mark.parametrize("ntrial", [1, 2])
 def test_probe_fit_exact_recovery(ntrial):
-    """y = sum_i c_i B_i x exactly -> the GPU fit returns c to 1e-10 (Sec. 1.3)."""
+    """y = sum_i c_i B_i x exactly -> the GPU fit returns c to 1e-10 (Sec. 1.4)."""
     M = _gpu()
     w = F.tiny(n=8, nr=8, dtype="f64").with_(nx=128, nz=64)
     P = _problem(M, w)

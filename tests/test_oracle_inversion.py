@@ -48,3 +48,7 @@ def test_krylov_pairs_and_relative_mse():
     np.testing.assert_allclose(pairs[1][0], pairs[0][1])
     assert I.relative_mse(2 * b, b) == 1.0
     assert I.relative_mse(b, b) == 0.0
+    # a ratio of norms, not of squared norms: an error of half the reference's norm is 0.5
+    e = np.zeros(6)
+    e[0] = 0.5 * np.linalg.norm(b)
+    assert abs(I.relative_mse(b + e, b) - 0.5) < 1e-15

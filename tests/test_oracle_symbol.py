@@ -83,7 +83,7 @@ def test_apply_Hinv_is_linear_combination():
 
 @pytest.mark.parametrize("ntrial", [1, 2])
 def test_fit_recovers_coefficients_exactly(ntrial):
-    """If y = sum_i c_i B_i x exactly, the fit returns c (Sec. 1.3, exact expansion)."""
+    """If y = sum_i c_i B_i x exactly, the fit returns c (Sec. 1.4, exact expansion)."""
     shape = (32, 64)
     h = 10.0
     leg = [(a, 0) for a in range(5)]
@@ -141,7 +141,7 @@ def test_dense_H_symmetric_psd_and_matches_apply_H(tinyH):
 
 
 def test_expected_gram_is_trace_formula(tinyH):
-    """E M_ij = Tr(H B_i^T B_j H) for y ~ N(0, I), x = H y (Sec. 1.3, Sec. 3.1)."""
+    """E M_ij = Tr(H B_i^T B_j H) for y ~ N(0, I), x = H y (Sec. 1.4, Sec. 3.1)."""
     P, H = tinyH
     shape = P.w.model_shape
     leg = [(0, 0), (1, 0)]
