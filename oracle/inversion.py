@@ -76,3 +76,35 @@ def conjugate_gradient(matvec, b, iters, precond=None, x0=None):
         p = z + (rz_new / rz) * p
         rz = rz_new
     return x, norms
+
+
+def misfit(P, c, d_obs):
+    """Residual data r = d - F[m] at m = 1/c^2 and J = 1/2 r.r (Sec. 1.1, output least squares)."""
+    r = np.asarray(d_obs, dtype=np.float64) - P.model_data(1.0 / P.c_pad ** 2)
+    return r, 0.5 * float(np.sum(r * r))
+
+
+def gauss_newton(problem_at, c0, d_obs, outer, inner, precond_at=None):
+    """Gauss-Newton iterations on J[m] = 1/2 ||d - F[m]||^2 over m = 1/c^2 (Sec. 1.1).
+
+    At c_k (problem_at(c_k) gives the operators linearised there): residual data
+    r = d - F[m_k]; the gradient is -F* r, so the Newton step with the Hessian
+    replaced by H = F*F solves H dm = F* r, here by `inner` CG iterations from zero
+    (preconditioned by precond_at(P) when given); m_{k+1} = m_k + dm on the model grid,
+    c_{k+1} = m_{k+1}^(-1/2).  Returns the velocity iterates and the misfits J(c_k),
+    the last one at the final velocity."""
+    c = np.asarray(c0, dtype=np.float64)
+    cs, Js = [c], []
+    for _ in range(outer):
+        P = problem_at(c)
+        r, J = misfit(P, c, d_obs)
+        Js.append(J)
+        b = P.apply_Fadj(r)
+        dm, _ = conjugate_gradient(P.apply_H, b, inner, precond=None if precond_at is None else precond_at(P))
+        m = 1.0 / c ** 2 + dm
+        if np.any(m <= 0.0):
+            raise ValueError("Gauss-Newton step leaves m = 1/c^2 non-positive")
+        c = 1.0 / np.sqrt(m)
+        cs.append(c)
+    Js.append(misfit(problem_at(c), c, d_obs)[1])
+    return cs, Js

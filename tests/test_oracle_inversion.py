@@ -52,3 +52,62 @@ def test_krylov_pairs_and_relative_mse():
     e = np.zeros(6)
     e[0] = 0.5 * np.linalg.norm(b)
     assert abs(I.relative_mse(b + e, b) - 0.5) < 1e-15
+
+
+# ---- Gauss-Newton on the wave-equation problem (Sec. 1.1), tiny grid ----
+
+def _tiny_wave():
+    import fixtures as F
+    from oracle import Problem
+    w = F.tiny(n=16, nr=16, nt=120, ns=2, dtype="f64", kind="smooth")
+    c = F.medium(w)
+    return w, c, (lambda cc: Problem(w, cc))
+
+
+def _blob(w, c, amp, zc=0.35, xc=0.5, width=2.0):
+    nz, nx = w.model_shape
+    z, x = np.meshgrid(np.arange(nz), np.arange(nx), indexing="ij")
+    m0 = 1.0 / np.asarray(c, np.float64) ** 2
+    return amp * float(np.mean(m0)) * np.exp(-((z - zc * nz) ** 2 + (x - xc * nx) ** 2) / (2 * width ** 2))
+
+
+def test_migrated_residual_is_minus_the_gradient_of_the_misfit():
+    """b = F*(d - F[m0]) = -dJ/dm: a central difference of J along a direction v on the
+    model grid (damping and the layer's velocity held, as in the Born map) matches -b.v:
+    the sign and the pairing of modelling, Born and migration."""
+    w, c0, at = _tiny_wave()
+    P = at(c0)
+    m_pad = 1.0 / P.c_pad ** 2
+    d_obs = P.model_data(m_pad + P.extend(_blob(w, c0, 0.05)))
+    r, J0 = I.misfit(P, c0, d_obs)
+    b = P.apply_Fadj(r)
+    v = _blob(w, c0, 1.0, zc=0.45, xc=0.4, width=2.5)
+    eps = 1e-3
+    Jp = 0.5 * np.sum((d_obs - P.model_data(m_pad + eps * P.extend(v))) ** 2)
+    Jm = 0.5 * np.sum((d_obs - P.model_data(m_pad - eps * P.extend(v))) ** 2)
+    fd = (Jp - Jm) / (2 * eps)
+    assert J0 > 0
+    assert abs(fd + float(np.sum(b * v))) <= 1e-4 * abs(fd)
+
+
+def test_gauss_newton_step_is_zero_on_exact_data():
+    w, c0, at = _tiny_wave()
+    P = at(c0)
+    d_obs = P.model_data(1.0 / P.c_pad ** 2)
+    cs, Js = I.gauss_newton(at, c0, d_obs, 1, 3)
+    assert Js[0] == 0.0
+    # dm = 0 exactly; c -> (c^-2)^(-1/2) only rounds
+    np.testing.assert_allclose(cs[1], c0, rtol=4e-16, atol=0)
+    assert Js[1] <= 1e-24 * float(np.sum(d_obs ** 2))
+
+
+def test_gauss_newton_lowers_the_misfit():
+    """A weak, smooth perturbation: each Gauss-Newton step (three CG iterations) lowers J."""
+    w, c0, at = _tiny_wave()
+    m_true = 1.0 / c0 ** 2 + _blob(w, c0, 0.03)
+    P = at(1.0 / np.sqrt(m_true))
+    d_obs = P.model_data(1.0 / P.c_pad ** 2)
+    cs, Js = I.gauss_newton(at, c0, d_obs, 2, 3)
+    assert Js[1] < 0.5 * Js[0] and Js[2] < Js[1], Js
+    err = [np.linalg.norm(1.0 / c ** 2 - m_true) for c in cs]
+    assert err[2] < err[1] < err[0]
