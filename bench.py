@@ -253,6 +253,47 @@ def generalization_run(ns=(1, 2, 4)):
     return out
 
 
+def gauss_newton_records(P, w, c, refl, basis, trial, outer=3, inner=5):
+    """Gauss-Newton from the background c towards m = 1/c^2 + refl, on data modelled at the
+    true velocity: misfits and model errors per outer iteration, with CG inner solves
+    (plain or preconditioned) and with steps given by a probed inverse alone (K1 fitted on
+    the migrated residual, or R1 on a trial function, refitted at every iterate)."""
+    import torch
+
+    from paper_1101_3615_amd import inversion as I
+    import paper_1101_3615_amd as M
+    c0 = torch.from_numpy(c).to("cuda:0").double()
+    m0 = 1.0 / (c0 * c0)
+    P.set_background(1.0 / torch.sqrt(m0 + refl))
+    d_obs = P.model().clone()
+
+    def r1(problem, b):
+        coef, _, _ = M.probe_fit(problem, basis, [trial], [problem.apply_H(trial)], strict=False)
+        return I.preconditioner(problem, basis, coef)
+
+    def k1(problem, b):
+        coef, _, _ = I.fit_krylov(problem, basis, b, 1)
+        return I.preconditioner(problem, basis, coef)
+
+    out = []
+    for name, pre, cg in (("none", None, inner), ("K1", k1, inner), ("K1", k1, 0), ("R1", r1, 0)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rec = {"study": "gauss_newton", "workload": w.name, "preconditioner": name, "p": basis.p, "outer": outer,
+               "inner_cg": cg}
+        try:
+            cs, Js = I.gauss_newton(P, c0, d_obs, outer, cg, precond_at=pre)
+        except ValueError as e:   # a step that leaves m = 1/c^2 non-positive
+            out.append(dict(rec, error=str(e)))
+            continue
+        torch.cuda.synchronize()
+        err = [round(I.relative_mse(1.0 / (ck * ck) - m0, refl), 6) for ck in cs]
+        out.append(dict(rec, ms_per_outer=round((time.perf_counter() - t) * 1e3 / outer, 1),
+                        misfit=[float(f"{j:.6g}") for j in Js], model_error=err))
+    P.set_background(c0)
+    return out
+
+
 def inversion_run(gd_steps=200, cg_iters=20):
     """Linearised inversion of a synthetic reflectivity on the 128x128 FP64 workload: the
     migrated image b = H m, the reference image after gd_steps exact-step descent steps,
@@ -303,6 +344,7 @@ def inversion_run(gd_steps=200, cg_iters=20):
                         "rank_deficient": deficient, "apply_ms": round((time.perf_counter() - t) * 1e3, 3)})
             if B.p == 21:
                 precs[name] = I.preconditioner(P, B, coef)
+    out += gauss_newton_records(P, w, c, m, bases[3], trials[0])
     for name in ("none", "R4", "K1"):
         torch.cuda.synchronize()
         t = time.perf_counter()

@@ -149,6 +149,16 @@ int mp_footprint(const mp_ctx* ctx, int op, int nshots, size_t* bytes);
 /* F: model perturbation dm_dev -> data d_dev (overwritten), Sec. 1.1 / Sec. 2. */
 int mp_apply_F(mp_ctx* ctx, const void* dm_dev, void* d_dev, void* stream);
 
+/* Nonlinear modelling (Sec. 1.1, the map from m = 1/c^2 to data): d_dev
+ * (overwritten; layout and precision of mp_apply_F's data, [ns][nt][nr]) gets
+ * the background wavefield of every shot at the receivers, d[s][n][r] =
+ * u_s^{n+1}(x_r), for the velocity given to mp_set_background (same scheme,
+ * source, sponge and time axis as the background of F, whose Born field is the
+ * derivative of this map with respect to m on the model grid, damping held
+ * fixed).  Stores no background history, so a cached one stays valid.
+ * MP_ESTATE without a background; MP_EINVAL for a null buffer. */
+int mp_model(mp_ctx* ctx, void* d_dev, void* stream);
+
 /* F*: data d_dev -> image img_dev (overwritten); the exact transpose of F. */
 int mp_apply_Fadj(mp_ctx* ctx, const void* d_dev, void* img_dev, void* stream);
 

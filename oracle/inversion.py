@@ -90,9 +90,12 @@ def gauss_newton(problem_at, c0, d_obs, outer, inner, precond_at=None):
     At c_k (problem_at(c_k) gives the operators linearised there): residual data
     r = d - F[m_k]; the gradient is -F* r, so the Newton step with the Hessian
     replaced by H = F*F solves H dm = F* r, here by `inner` CG iterations from zero
-    (preconditioned by precond_at(P) when given); m_{k+1} = m_k + dm on the model grid,
-    c_{k+1} = m_{k+1}^(-1/2).  Returns the velocity iterates and the misfits J(c_k),
-    the last one at the final velocity."""
+    (preconditioned by precond_at(P, b) when given; b = F* r lets it fit Kn).  With
+    inner = 0 the step is the preconditioner applied to the migrated residual,
+    dm = P F* r: the fitted inverse in place of H^-1, as Sec. 2.2 describes for the
+    iterations after the first.
+    m_{k+1} = m_k + dm on the model grid, c_{k+1} = m_{k+1}^(-1/2).  Returns the velocity
+    iterates and the misfits J(c_k), the last one at the final velocity."""
     c = np.asarray(c0, dtype=np.float64)
     cs, Js = [c], []
     for _ in range(outer):
@@ -100,7 +103,11 @@ def gauss_newton(problem_at, c0, d_obs, outer, inner, precond_at=None):
         r, J = misfit(P, c, d_obs)
         Js.append(J)
         b = P.apply_Fadj(r)
-        dm, _ = conjugate_gradient(P.apply_H, b, inner, precond=None if precond_at is None else precond_at(P))
+        if inner == 0:
+            dm = precond_at(P, b)(b)
+        else:
+            M = None if precond_at is None else precond_at(P, b)
+            dm, _ = conjugate_gradient(P.apply_H, b, inner, precond=M)
         m = 1.0 / c ** 2 + dm
         if np.any(m <= 0.0):
             raise ValueError("Gauss-Newton step leaves m = 1/c^2 non-positive")

@@ -29,7 +29,7 @@ MP_OP_F, MP_OP_FADJ, MP_OP_H, MP_OP_FIT, MP_OP_HINV = 1, 2, 3, 4, 5
 SWEEP_KINDS = ("fused", "born", "background", "adjoint")
 
 EXPORTS = [
-    "mp_create", "mp_destroy", "mp_set_background", "mp_footprint", "mp_apply_F",
+    "mp_create", "mp_destroy", "mp_set_background", "mp_footprint", "mp_apply_F", "mp_model",
     "mp_apply_Fadj", "mp_apply_H", "mp_apply_H_batch", "mp_release_cache", "mp_basis_create",
     "mp_basis_destroy", "mp_probe_fit", "mp_apply_Hinv", "mp_last_stats", "mp_strerror",
     "mp_last_error",
@@ -107,6 +107,7 @@ def lib():
                                    ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     for name in ("mp_apply_F", "mp_apply_Fadj", "mp_apply_H"):
         getattr(L, name).argtypes = [vp, vp, vp, vp]
+    L.mp_model.argtypes = [vp, vp, vp]
     L.mp_release_cache.argtypes = [vp]
     L.mp_basis_create.argtypes = [ctypes.POINTER(BasisDesc), ctypes.POINTER(vp)]
     L.mp_basis_destroy.argtypes = [vp]

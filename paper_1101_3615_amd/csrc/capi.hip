@@ -224,6 +224,14 @@ int mp_apply_F(mp_ctx* ctx, const void* dm, void* d, void* stream) {
   return finish(ctx, ctx->eng->apply_F(dm, d, (hipStream_t)stream));
 }
 
+int mp_model(mp_ctx* ctx, void* d, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!d) return fail(MP_EINVAL, "null buffer");
+  if (!ctx->has_bg) return fail(MP_ESTATE, "no background set");
+  return finish(ctx, ctx->eng->model(d, (hipStream_t)stream));
+}
+
 int mp_apply_Fadj(mp_ctx* ctx, const void* d, void* img, void* stream) {
   int rc = guard(ctx);
   if (rc) return rc;

@@ -253,6 +253,7 @@ class EngineT final : public Engine {
   Step<T> params(int s0, int nsh, int W) {
     Step<T> p;
     p.L = L_;
+    p.rec_bg = nullptr;
     const double ih2 = 1.0 / (cfg_.h * cfg_.h);
     p.c0x = (T)(cfg_.ndim * FD8[0] * ih2);
     p.c1 = (T)(FD8[1] * ih2);
@@ -328,16 +329,15 @@ class EngineT final : public Engine {
     unsigned int* st = small_.as<unsigned int>();
     cstats(c, cfg_.model_cells(), st, s);
     MP_CHECK_LAUNCH();
-    unsigned int h[2];
+    unsigned int h[3];
     MP_HIP(hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, s));
     MP_HIP(hipStreamSynchronize(s));
-    if (h[1] != 0) {
+    if (h[2] != 0) {
       set_error("background velocity has non-finite or non-positive entries");
       return MP_ENUMERIC;
     }
-    float cmaxf;
-    std::memcpy(&cmaxf, &h[0], 4);
-    const double cmax = cmaxf;
+    double cmax;
+    std::memcpy(&cmax, &h[0], 8);
     const double courant = cmax * cfg_.dt / cfg_.h;
     if (courant > cfl_limit(cfg_.ndim)) {
       set_error("CFL violated: c_max dt / h = " + std::to_string(courant) + " > " +
@@ -499,7 +499,8 @@ class EngineT final : public Engine {
   // Forward sweep of shots [s0, s0+nsh) in segments (the checkpoint interval, or
   // all nt steps): the background over the segment (g into the segment's slots,
   // checkpoint of the segment's first level), then the Born field over it.
-  // mode 0: background + Born, 1: Born from the stored g, 2: background only.
+  // mode 0: background + Born, 1: Born from the stored g, 2: background only,
+  // 3: background only with its receiver traces into data (no g, no checkpoints).
   int forward2d(int mode, int s0, int nsh, int W, T* data) {
     int rc;
     if (nsh % gsz() || s0 % gsz()) {
@@ -507,16 +508,19 @@ class EngineT final : public Engine {
       return MP_EINVAL;
     }
     if ((rc = zero_fields(W, true))) return rc;
+    const bool model = (mode == 3);
     Step<T> p = params(s0, nsh, W);
-    p.data = data;
+    p.data = model ? nullptr : data;
+    p.rec_bg = model ? data : nullptr;
     Rot2 r = rot2(W);
-    const int ck = ck_kind();
+    const int ck = model ? CK_NONE : ck_kind();
     if (ck == CK_BF16 && mode != 1) {
       fill(cks_.as<float>(), (long long)nsh * nck() * 2, 0.0f, stream_);
       MP_CHECK_LAUNCH();
     }
-    const int kk = ckpt_mode() ? cfg_.ckpt_every : cfg_.nt;
-    const bool keep_g = !(mode == 2 && ckpt_mode());   // g is only needed by a Born sweep or the cache
+    const int kk = (ckpt_mode() && !model) ? cfg_.ckpt_every : cfg_.nt;
+    // g is only needed by a Born sweep or the cache
+    const bool keep_g = !model && !(mode == 2 && ckpt_mode());
     for (int n0 = 0; n0 < cfg_.nt; n0 += kk) {
       const int len = std::min(kk, cfg_.nt - n0);
       const int j = n0 / kk;
@@ -535,7 +539,7 @@ class EngineT final : public Engine {
         }
         if ((rc = span_end(sp))) return rc;
       }
-      if (mode != 2) {
+      if (mode < 2) {
         if ((rc = span_begin(MP_SWEEP_BORN, (len + 1) / 2, &sp, len))) return rc;
         for (int n = n0; n < n0 + len;) {
           const int ns = std::min(2, n0 + len - n);
@@ -601,7 +605,8 @@ class EngineT final : public Engine {
     return MP_OK;
   }
 
-  // forward sweep of shots [s0, s0+nsh): mode 0 fused, 1 Born from stored g, 2 background only.
+  // forward sweep of shots [s0, s0+nsh): mode 0 fused, 1 Born from stored g, 2 background only,
+  // 3 background only with its receiver traces into data (no g, no checkpoints).
   // In the checkpoint modes the background levels are stored every ckpt_every steps
   // instead of g.
   int forward(int mode, int s0, int nsh, int W, T* data) {
@@ -612,9 +617,11 @@ class EngineT final : public Engine {
       return MP_EINVAL;
     }
     if ((rc = zero_fields(W, true))) return rc;
+    const bool model = (mode == 3);
     Step<T> p = params(s0, nsh, W);
-    p.data = data;
-    const int ck = ck_kind();
+    p.data = model ? nullptr : data;
+    p.rec_bg = model ? data : nullptr;
+    const int ck = model ? CK_NONE : ck_kind();
     if (ck == CK_BF16 && mode != 1) {
       fill(cks_.as<float>(), (long long)nsh * nck() * 2, 0.0f, stream_);
       MP_CHECK_LAUNCH();
@@ -627,7 +634,8 @@ class EngineT final : public Engine {
     for (int n = 0; n < cfg_.nt; ++n) {
       const int cs = (ck != CK_NONE && n % k == 0) ? n / k : -1;
       const int cm = (ck == CK_BF16 && (n + 1) % k == 0 && (n + 1) / k < nck()) ? (n + 1) / k : -1;
-      const int hs = (ck == CK_NONE) ? n : 0;    // g is not stored while checkpointing
+      // g is not stored while checkpointing, nor by modelling
+      const int hs = model ? -1 : (ck == CK_NONE) ? n : 0;
       if (mode == 0) step(M_FUSED, p, n, hs, ck, cs, cm);
       else if (mode == 1) step(M_BORN, p, n, n, CK_NONE, -1, -1);
       else step(M_BG, p, n, hs, ck, cs, cm);
@@ -718,6 +726,23 @@ class EngineT final : public Engine {
     }
     cached_ = whole_;
     finish_stats(waves, use_cache, cfg_.ns);
+    return MP_OK;
+  }
+
+  // Nonlinear modelling: the background field of every acquisition shot at the
+  // receivers, d[s][n][r] = u^{n+1}(x_r).  Writes no g and no checkpoints, so a
+  // cached background history stays valid.
+  int model(void* d, hipStream_t s) override {
+    stream_ = s;
+    int W, rc;
+    if ((rc = plain_job(&W))) return rc;
+    const int nb = pad_group(cfg_.ns);
+    int waves = 0;
+    for (int s0 = 0; s0 < nb; s0 += W, ++waves) {
+      const int nsh = std::min(W, nb - s0);
+      if ((rc = forward(3, s0, nsh, W, static_cast<T*>(d)))) return rc;
+    }
+    finish_stats(waves, false, cfg_.ns);
     return MP_OK;
   }
 

@@ -23,7 +23,8 @@ void extend(float* dst, const float* model, const Pad& p, hipStream_t s);
 void extend(double* dst, const double* model, const Pad& p, hipStream_t s);
 void kappa(float* dst, const float* c, const Pad& p, double dt, hipStream_t s);
 void kappa(double* dst, const double* c, const Pad& p, double dt, hipStream_t s);
-// out[0] = bits of max c (as float), out[1] = count of non-finite / non-positive entries
+// out[0..1] = bits of max c as a double (8-byte aligned), out[2] = count of non-finite /
+// non-positive entries
 void cstats(const float* c, long long n, unsigned int* out, hipStream_t s);
 void cstats(const double* c, long long n, unsigned int* out, hipStream_t s);
 // dense model out = sum over shots of FP64 images (model layout with pitch mpitch, myp y-rows)

@@ -74,22 +74,23 @@ __global__ void k_kappa(T* dst, const T* c, PadMap m, T dt2) {
 
 // max |c| and the count of non-finite or non-positive entries.
 template <typename T>
-__global__ void k_cstats(const T* c, long long n, unsigned int* maxbits, unsigned int* bad) {
+__global__ void k_cstats(const T* c, long long n, unsigned long long* maxbits, unsigned int* bad) {
+  // maximum in the field precision, exact: positive doubles order as their bit patterns
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long step = (long long)gridDim.x * blockDim.x;
-  float m = 0.0f;
+  double m = 0.0;
   unsigned int nb = 0;
   for (; i < n; i += step) {
     const T v = c[i];
     if (!(v > T(0)) || !(v < T(1e30))) ++nb;
-    else m = fmaxf(m, (float)v);
+    else m = fmax(m, (double)v);
   }
   for (int o = 32; o > 0; o >>= 1) {
-    m = fmaxf(m, __shfl_xor(m, o));
+    m = fmax(m, __shfl_xor(m, o));
     nb += __shfl_xor(nb, o);
   }
   if ((threadIdx.x & 63) == 0) {
-    atomicMax(maxbits, __float_as_uint(m));
+    atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
     if (nb) atomicAdd(bad, nb);
   }
 }
@@ -149,8 +150,9 @@ void kappa(double* d, const double* c, const Pad& p, double dt, hipStream_t s) {
 
 template <typename T>
 static void cstats_t(const T* c, long long n, unsigned int* out2, hipStream_t s) {
-  fill((int*)out2, 2, 0, s);
-  hipLaunchKernelGGL(k_cstats<T>, grid_for(n), dim3(256), 0, s, c, n, out2, out2 + 1);
+  fill((int*)out2, 3, 0, s);
+  hipLaunchKernelGGL(k_cstats<T>, grid_for(n), dim3(256), 0, s, c, n, reinterpret_cast<unsigned long long*>(out2),
+                     out2 + 2);
 }
 void cstats(const float* c, long long n, unsigned int* o, hipStream_t s) { cstats_t(c, n, o, s); }
 void cstats(const double* c, long long n, unsigned int* o, hipStream_t s) { cstats_t(c, n, o, s); }

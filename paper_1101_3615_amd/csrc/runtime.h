@@ -66,6 +66,7 @@ class Engine {
   virtual ~Engine() = default;
   virtual int set_background(const void* c, hipStream_t s) = 0;
   virtual int apply_F(const void* dm, void* d, hipStream_t s) = 0;
+  virtual int model(void* d, hipStream_t s) = 0;
   virtual int apply_Fadj(const void* d, void* img, hipStream_t s) = 0;
   virtual int apply_H(const void* dm, void* out, hipStream_t s) = 0;
   virtual int apply_H_batch(int nreq, const int* counts, const int* shots, const void* const* dm,

@@ -62,6 +62,7 @@ struct Step {
   T* hist;                   // g store: [local shot][slot][model]
   long long hstride;         // elements per local shot in hist
   T* data;                   // [shots of the job][nt][nr]
+  T* rec_bg;                 // M_BG records u^{n+1}(x_r) into [shots of the job][nt][nr] when non-null
   double* img;               // [shots of the job][model] FP64 per-shot images
   // background checkpoints (checkpoint snapshot modes); compact layout
   // [z][y][cpitch] per level

@@ -234,7 +234,8 @@ __device__ __forceinline__ int layer_depth(int i, int n, int nb) { return max(ma
 // One launch of NS (1 or 2) time steps of every shot of a wave.
 //   M_BG:   in0 = u^n, in1 = D^n            -> out0 = u^{n+NS}, out1 = D^{n+NS};
 //           g^n -> slot hs1, g^{n+1} -> slot hs2 (a negative slot is not written);
-//           checkpoint ck_store <- (u^n, D^n); BF16 maxima of the last level -> ck_max.
+//           checkpoint ck_store <- (u^n, D^n); BF16 maxima of the last level -> ck_max;
+//           with rec_bg set, records u^{n+1}(x_r), u^{n+2}(x_r) (nonlinear modelling).
 //   M_BORN: in0 = du^n, in1 = du^{n-1}      -> out0 = du^{n+1}, out1 = du^{n+2};
 //           reads g^n (hs1), g^{n+1} (hs2); records d[n], d[n+1].
 //   M_ADJ:  in0 = nu^{k+1}, in1 = nu^{k+2}  -> out0 = nu^k, out1 = nu^{k-1}  (n = k);
@@ -291,6 +292,8 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
   }
   // a null shot (no source: padding of a group) records and injects no data
   const bool live = p.srcx[shot] >= 0;
+  T* const recbg = BG ? p.rec_bg : nullptr;   // background traces (modelling), uniform
+  const bool rec = !BG || recbg != nullptr;    // whether receiver rows are looked up
 
   // field resources based at the strip's cell (sx0, 0), nzp rows long
   const long long kofs = (long long)SLACK + (long long)GZ * pitch + XL + sx0;
@@ -503,8 +506,8 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
           if (x == sx) lap[0] += ws;
           if (x + 1 == sx) lap[1] += ws;
         }
-        int rm[2];
-        const bool recrow = recs(z, rm);
+        int rm[2] = {-1, -1};
+        const bool recrow = rec && recs(z, rm);
         if (MODE == M_ADJ && recrow && live) {
           const T* drow = p.data + ((long long)shot * p.nt + (n - 1)) * p.nr;
           if (rm[0] >= 0) lap[0] += drow[rm[0]];
@@ -532,6 +535,11 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
               bst2(nv, rO0, vs + so, 0u);
               bst2(nd, rO1, vs + so, 0u);
               if (CK == CK_BF16 && ck_max >= 0) track(nv, nd);
+            }
+            if (recrow && outl && live) {
+              T* drow = recbg + ((long long)shot * p.nt + n) * p.nr;
+              if (rm[0] >= 0) drow[rm[0]] = nv.v[0];
+              if (rm[1] >= 0) drow[rm[1]] = nv.v[1];
             }
           } else {
             bst2(nv, rO0, vs + so, 0u);
@@ -571,8 +579,8 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
           if (x == sx) lap[0] += ws;
           if (x + 1 == sx) lap[1] += ws;
         }
-        int rm[2];
-        const bool recrow = recs(y, rm);
+        int rm[2] = {-1, -1};
+        const bool recrow = rec && recs(y, rm);
         if (MODE == M_ADJ && recrow && live) {
           const T* drow = p.data + ((long long)shot * p.nt + (n - 2)) * p.nr;
           if (rm[0] >= 0) lap[0] += drow[rm[0]];
@@ -594,6 +602,11 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
           bst2(nd, rO1, vs + so, 0u);
           gst(rH2, y - nb, g);
           if (CK == CK_BF16 && ck_max >= 0) track(nv, nd);
+          if (recrow && outl && live) {
+            T* drow = recbg + ((long long)shot * p.nt + n + 1) * p.nr;
+            if (rm[0] >= 0) drow[rm[0]] = nv.v[0];
+            if (rm[1] >= 0) drow[rm[1]] = nv.v[1];
+          }
         } else {
           bst2(nv, rO1, vs + so, 0u);
           if (MODE == M_BORN && recrow && outl && live) {

@@ -482,6 +482,12 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
           for (int i = 0; i < 4; ++i)
             if (rm[i] >= 0) drow[rm[i]] = TWO ? bnew.v[i] : anew.v[i];
         }
+        if (MODE == M_BG && p.rec_bg != nullptr && recrow && act && live) {   // nonlinear modelling
+          T* drow = p.rec_bg + ((long long)shot * p.nt + n) * p.nr;
+  #pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (rm[i] >= 0) drow[rm[i]] = anew.v[i];
+        }
 
         if (MODE == M_ADJ) {   // this half's contribution, added to the image one plane later
           V4<double> cw;

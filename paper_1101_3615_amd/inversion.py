@@ -93,3 +93,41 @@ def conjugate_gradient(problem, b, iters, precond=None):
         p = z + (rz_new / rz) * p
         rz = rz_new
     return x, norms
+
+
+def misfit(problem, d_obs):
+    """Residual data r = d - F[m] at the current background and J = 1/2 r.r (Sec. 1.1)."""
+    r = d_obs - problem.model()
+    return r, 0.5 * _dot(r, r)
+
+
+def gauss_newton(problem, c0, d_obs, outer, inner, precond_at=None):
+    """Gauss-Newton on J[m] = 1/2 ||d - F[m]||^2 over m = 1/c^2 (Sec. 1.1).
+
+    At c_k: r = d - F[m_k] (nonlinear modelling), the migrated residual b = F* r
+    (minus the gradient of J), the step dm from `inner` CG iterations on H dm = b
+    (preconditioned by precond_at(problem, b), a probed inverse fitted at c_k: Rn, or Kn
+    on the Krylov pairs of b), or
+    with inner = 0 the preconditioner applied to b (the fitted inverse in place of
+    H^-1, Sec. 2.2); m_{k+1} = m_k + dm, c_{k+1} = m_{k+1}^(-1/2).  Leaves the problem's background at the
+    last iterate; returns the velocity iterates and the misfits J(c_k)."""
+    c = c0.to(device=problem.device, dtype=problem.torch_dtype).clone()
+    cs, Js = [c], []
+    for _ in range(outer):
+        problem.set_background(c)
+        r, J = misfit(problem, d_obs)
+        Js.append(J)
+        b = problem.apply_Fadj(r)
+        if inner == 0:
+            dm = precond_at(problem, b)(b)
+        else:
+            dm, _ = conjugate_gradient(problem, b, inner,
+                                       precond=None if precond_at is None else precond_at(problem, b))
+        m = 1.0 / (c * c) + dm
+        if bool((m <= 0).any()):
+            raise ValueError("Gauss-Newton step leaves m = 1/c^2 non-positive")
+        c = 1.0 / torch.sqrt(m)
+        cs.append(c)
+    problem.set_background(c)
+    Js.append(misfit(problem, d_obs)[1])
+    return cs, Js

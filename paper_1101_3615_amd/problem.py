@@ -101,6 +101,14 @@ class Problem:
         L.check(self._lib.mp_apply_F(self._ctx, _ptr(dm), _ptr(d), _stream(stream)))
         return d
 
+    def model(self, out=None, stream=None):
+        """Nonlinear modelling at the current background: d[s][n][r] = u_s^{n+1}(x_r)."""
+        d = out if out is not None else torch.empty(self.data_shape, dtype=self.torch_dtype, device=self.device)
+        if tuple(d.shape) != self.data_shape or d.dtype != self.torch_dtype or not d.is_contiguous():
+            raise ValueError(f"out must be a contiguous {self.torch_dtype} tensor of shape {self.data_shape}")
+        L.check(self._lib.mp_model(self._ctx, _ptr(d), _stream(stream)))
+        return d
+
     def apply_Fadj(self, d, out=None, stream=None):
         if not isinstance(d, torch.Tensor):
             d = torch.as_tensor(np.asarray(d))

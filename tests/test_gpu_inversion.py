@@ -102,3 +102,62 @@ def test_descent_properties_full_size():
     phi_cg = 0.5 * float((x_cg * Hx).sum()) - float((b * x_cg).sum())
     print("functional: descent", phis[-1], "CG", phi_cg)
     assert phi_cg <= phis[-1] + 1e-9 * abs(phis[-1])
+
+
+def _gn_case(M):
+    """A smooth background and data modelled at it plus a weak reflectivity, on each side."""
+    w = _small()
+    c0 = F.medium(w).astype(np.float64)
+    m_true = 1.0 / c0 ** 2 + 0.5 * F.reflectivity(w, c0, seed=9).astype(np.float64)
+    c_true = 1.0 / np.sqrt(m_true)
+    O_true = Oracle(w, c_true)
+    d_ref = O_true.model_data(1.0 / O_true.c_pad ** 2)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c_true))
+    d_obs = P.model()
+    assert rel(d_obs.cpu().numpy(), d_ref) <= 1e-10
+    return w, c0, d_ref, P, d_obs
+
+
+def _compare_runs(c0, cs, Js, cs_ref, Js_ref):
+    assert len(cs) == len(cs_ref) and len(Js) == len(Js_ref)
+    for a, b in zip(cs[1:], cs_ref[1:]):   # the updates, not the velocities, at the tolerance
+        assert rel(a.cpu().numpy() - c0, b - c0) <= TOL
+    assert rel(Js, Js_ref) <= TOL
+
+
+def test_gauss_newton_matches_oracle():
+    """Two Gauss-Newton steps of two CG iterations each."""
+    M = _gpu()
+    from paper_1101_3615_amd import inversion as I
+    w, c0, d_ref, P, d_obs = _gn_case(M)
+    cs_ref, Js_ref = OI.gauss_newton(lambda c: Oracle(w, c), c0, d_ref, 2, 2)
+    cs, Js = I.gauss_newton(P, torch.from_numpy(c0), d_obs, 2, 2)
+    print("GN misfits", Js, Js_ref)
+    assert Js[2] < Js[0]
+    _compare_runs(c0, cs, Js, cs_ref, Js_ref)
+
+
+def test_gauss_newton_probed_steps_match_oracle():
+    """Two steps dm = P F* r with P a K1 probed inverse refitted at every iterate on the
+    pair (b, H b) of the migrated residual b (the paper's expansion with p = 4)."""
+    M = _gpu()
+    from paper_1101_3615_amd import inversion as I
+    from paper_1101_3615_amd.study import paper_bases
+    w, c0, d_ref, P, d_obs = _gn_case(M)
+    (B,) = paper_bases(2, [(0, 1, 1)])
+    basis = lambda v: S.apply_paper_basis(v, w.h, B.modes, B.mults, B.order, B.tl_scale)
+
+    def oracle_k1(Q, b):
+        coef, _, _ = S.fit_with(basis, [b], [Q.apply_H(b)])
+        return _oracle_prec(B, coef, w.h)
+
+    def gpu_k1(Q, b):
+        coef, _, _ = I.fit_krylov(Q, B, b, 1)
+        return I.preconditioner(Q, B, coef)
+
+    cs_ref, Js_ref = OI.gauss_newton(lambda c: Oracle(w, c), c0, d_ref, 2, 0, precond_at=oracle_k1)
+    cs, Js = I.gauss_newton(P, torch.from_numpy(c0), d_obs, 2, 0, precond_at=gpu_k1)
+    print("GN K1-step misfits", Js, Js_ref)
+    assert Js[2] < Js[0]
+    _compare_runs(c0, cs, Js, cs_ref, Js_ref)

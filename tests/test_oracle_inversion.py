@@ -111,3 +111,16 @@ def test_gauss_newton_lowers_the_misfit():
     assert Js[1] < 0.5 * Js[0] and Js[2] < Js[1], Js
     err = [np.linalg.norm(1.0 / c ** 2 - m_true) for c in cs]
     assert err[2] < err[1] < err[0]
+
+
+def test_gauss_newton_without_inner_iterations_applies_the_preconditioner():
+    """inner = 0: the step is the preconditioner applied to the migrated residual; with
+    three CG iterations as that preconditioner the iterates are those of inner = 3."""
+    w, c0, at = _tiny_wave()
+    P = at(1.0 / np.sqrt(1.0 / c0 ** 2 + _blob(w, c0, 0.03)))
+    d_obs = P.model_data(1.0 / P.c_pad ** 2)
+    cs3, Js3 = I.gauss_newton(at, c0, d_obs, 1, 3)
+    cs0, Js0 = I.gauss_newton(at, c0, d_obs, 1, 0,
+                              precond_at=lambda Q, b: (lambda v: I.conjugate_gradient(Q.apply_H, v, 3)[0]))
+    np.testing.assert_array_equal(cs0[1], cs3[1])
+    assert Js0 == Js3
