@@ -233,6 +233,62 @@ int mp_probe_fit(mp_ctx* ctx, const mp_basis* basis, int T, const void* const* y
 int mp_apply_Hinv(mp_ctx* ctx, const mp_basis* basis, const double* c, const void* img_dev,
                   void* out_dev, void* stream);
 
+/* ---- Curvelet-space trial functions (Sec. 1.5; the mask's construction, Sec. 2) ----
+ * 2D contexts with power-of-two model sizes up to 1024 per axis (MP_EUNSUPPORTED
+ * otherwise).  The frame is undecimated and built in the frequency domain of the
+ * periodic model grid: a lowpass wedge and nscales-1 directional bands; band j >= 1
+ * has A_j = nangles * 2^floor((j-1)/2) directions over a half turn, centred at
+ * theta = (l + 1/2) pi / A_j (the angle of the wavevector, x to z, z down).  The
+ * wedge windows are smooth, even and square-sum to one, so analysis followed by
+ * synthesis is the identity.  Coefficient arrays are [nwedges][nz][nx] in the
+ * context's precision (device); masks [nwedges][nz][nx] bytes (device, 0 or 1). */
+typedef struct mp_curvelet_desc {
+  int nscales;      /* J in [2, 8]: the lowpass and J-1 directional bands */
+  int nangles;      /* directions of band 1 over a half turn: even, in [4, 64] */
+  int mask_stride;  /* the mask is evaluated at nodes every mask_stride cells, [1, 64] */
+  int nfan;         /* half-opening angles alpha_i = (i + 1/2) pi / (2 nfan) of the ray pairs */
+  int max_steps;    /* Runge-Kutta steps (accepted or rejected) per ray before it counts as a miss */
+  double ray_rtol;  /* position error allowed per step, in cells, (0, 1] */
+} mp_curvelet_desc;
+typedef struct mp_curvelets mp_curvelets;
+
+/* Validate a descriptor (MP_EINVAL) and create a host-side handle. */
+int mp_curvelet_create(const mp_curvelet_desc* desc, mp_curvelets** out);
+void mp_curvelet_destroy(mp_curvelets* cv);
+
+/* Number of wedges; list (host, nullable) receives [nwedges][3] = (j, l, A_j),
+ * the lowpass first as (0, 0, 0), then band by band. */
+int mp_curvelet_wedges(const mp_curvelets* cv, int* nwedges, int* list);
+
+/* ||phi_w||_2 of every wedge's atom (host FP64 [nwedges]). */
+int mp_curvelet_norms(mp_ctx* ctx, const mp_curvelets* cv, double* norms, void* stream);
+
+/* Illumination mask (Sec. 1.5: the set S of visible curvelet centres; Sec. 2: ray
+ * tracing in smooth media).  c_dev: the velocity the rays see (model layout, field
+ * precision).  At nodes every mask_stride cells and for each wedge direction, a fan of
+ * ray pairs leaves along the upward normal turned by +alpha_i and -alpha_i; the centre
+ * is visible if for some alpha_i one ray reaches the sources' row inside their span and
+ * the other the receivers' row inside theirs (spans widened by half a cell).  Rays
+ * solve the kinematic ray equations with Dormand-Prince 5(4) steps in FP64 through a
+ * bilinear c and its centred-difference gradient; a ray that leaves the model's box
+ * first, or exhausts max_steps, misses.  mask_dev (written) takes, for each cell, the
+ * value of its node; the lowpass wedge is visible where a band-1 direction is.  Needs
+ * the sources on one row and the receivers on one row (MP_EUNSUPPORTED otherwise).
+ * Synchronises the stream. */
+int mp_illumination(mp_ctx* ctx, const mp_curvelets* cv, const void* c_dev, unsigned char* mask_dev,
+                    void* stream);
+
+/* out_dev = sum_w IFFT(U_w FFT(weights[w] mask_w coef_w)): the curvelet synthesis of
+ * the coefficients on the mask (mask_dev null: all ones; weights host FP64 [nwedges],
+ * null: all ones).  A randomized trial function of Sec. 1.5 is coef ~ N(0, 1) i.i.d.
+ * with weights sigma ||phi_w|| on the illumination mask. */
+int mp_curvelet_synthesis(mp_ctx* ctx, const mp_curvelets* cv, const void* coef_dev, const unsigned char* mask_dev,
+                          const double* weights, void* out_dev, void* stream);
+
+/* coef_dev[w] = IFFT(U_w FFT img_dev): the curvelet coefficients of an image at every
+ * grid position (the adjoint of the synthesis, and its inverse on the frame's range). */
+int mp_curvelet_analysis(mp_ctx* ctx, const mp_curvelets* cv, const void* img_dev, void* coef_dev, void* stream);
+
 /* Statistics of the last operator call; with timing enabled, waits for the
  * recorded events and restarts the timing accumulation. */
 int mp_last_stats(const mp_ctx* ctx, mp_stats* out);

@@ -280,37 +280,58 @@ def manifold(points, h):
     return float(zs[0]) * h, (p[:, 0].min() - 0.5) * h, (p[:, 0].max() + 0.5) * h
 
 
-def visibility(c, h, src, rec, J, A1, stride, nfan, rtol=1e-4, max_steps=4000, widen=0.0):
-    """vis[d, a, b] for each direction of direction_set and coarse node (a, b): some pair of the
-    fan has one ray reaching the source manifold and the other the receiver manifold.
-    ``widen`` (metres) grows (> 0) or shrinks (< 0) both intervals, for tie margins."""
+def ray_crossings(c, h, src, rec, J, A1, stride, nfan, rtol=1e-4, max_steps=4000, nodes=None):
+    """Crossings of every ray of the fans: for each direction d of direction_set, coarse node
+    (a, b) (all, or the (a, b) pairs listed in ``nodes``) and fan angle i, the ray turned by
+    +alpha_i (k = 0) and by -alpha_i (k = 1).  Returns a dict of arrays of shape
+    [ndir, nnodes, nfan, 2]: okS, xS (source row), okR, xR (receiver row), and the node
+    list.  All rays are traced together; each ray's arithmetic is its own."""
     med = Medium(c, h)
     nz, nx = med.c.shape
     zi, xi = mask_nodes(nz, stride), mask_nodes(nx, stride)
-    Z, X = np.meshgrid(zi * h, xi * h, indexing="ij")
-    zS, sl, sh = manifold(src, h)
-    zR, rl, rh = manifold(rec, h)
-    sl, sh, rl, rh = sl - widen, sh + widen, rl - widen, rh + widen
+    if nodes is None:
+        nodes = [(a, b) for a in range(zi.size) for b in range(xi.size)]
+    nodes = np.asarray(nodes, dtype=np.int64).reshape(-1, 2)
+    zS, _, _ = manifold(src, h)
+    zR, _, _ = manifold(rec, h)
     dirs = direction_set(J, A1)
-    vis = np.zeros((len(dirs), zi.size, xi.size), dtype=bool)
-    x0, z0 = X.ravel(), Z.ravel()
+    D, P = len(dirs), len(nodes)
+    dvec = np.zeros((D, nfan, 2, 2))
     for d, (A, l) in enumerate(dirs):
         plus, minus = ray_pairs(A, l, nfan)
-        hit = np.zeros(x0.size, dtype=bool)
-        for i in range(nfan):
-            hits = []
-            for dx, dz in (plus[i], minus[i]):
-                dxv, dzv = np.full(x0.size, dx), np.full(x0.size, dz)
-                okS, xS = trace_to_depth(med, x0, z0, dxv, dzv, zS, rtol, max_steps)
-                if zR == zS:
-                    okR, xR = okS, xS
-                else:
-                    okR, xR = trace_to_depth(med, x0, z0, dxv, dzv, zR, rtol, max_steps)
-                hits.append((okS & (xS >= sl) & (xS <= sh), okR & (xR >= rl) & (xR <= rh)))
-            (sp, rp), (sm, rm) = hits
-            hit |= (sp & rm) | (rp & sm)
-        vis[d] = hit.reshape(zi.size, xi.size)
-    return vis
+        dvec[d, :, 0], dvec[d, :, 1] = plus, minus
+    x0 = np.broadcast_to((xi[nodes[:, 1]] * h)[None, :, None, None], (D, P, nfan, 2)).ravel()
+    z0 = np.broadcast_to((zi[nodes[:, 0]] * h)[None, :, None, None], (D, P, nfan, 2)).ravel()
+    dx = np.broadcast_to(dvec[:, None, :, :, 0], (D, P, nfan, 2)).ravel()
+    dz = np.broadcast_to(dvec[:, None, :, :, 1], (D, P, nfan, 2)).ravel()
+    okS, xS = trace_to_depth(med, x0, z0, dx, dz, zS, rtol, max_steps)
+    if zR == zS:
+        okR, xR = okS, xS
+    else:
+        okR, xR = trace_to_depth(med, x0, z0, dx, dz, zR, rtol, max_steps)
+    shp = (D, P, nfan, 2)
+    return dict(okS=okS.reshape(shp), xS=xS.reshape(shp), okR=okR.reshape(shp), xR=xR.reshape(shp), nodes=nodes)
+
+
+def visibility_of(cross, src, rec, h, widen=0.0):
+    """vis[d, node] from ray crossings: some fan angle has one ray of the pair inside the
+    source span and the other inside the receiver span (spans from manifold(), grown by
+    ``widen`` metres, > 0, or shrunk, < 0, for tie margins)."""
+    _, sl, sh = manifold(src, h)
+    _, rl, rh = manifold(rec, h)
+    with np.errstate(invalid="ignore"):
+        s_in = cross["okS"] & (cross["xS"] >= sl - widen) & (cross["xS"] <= sh + widen)
+        r_in = cross["okR"] & (cross["xR"] >= rl - widen) & (cross["xR"] <= rh + widen)
+    pair = (s_in[..., 0] & r_in[..., 1]) | (r_in[..., 0] & s_in[..., 1])
+    return np.any(pair, axis=-1)
+
+
+def visibility(c, h, src, rec, J, A1, stride, nfan, rtol=1e-4, max_steps=4000, widen=0.0):
+    """vis[d, a, b] for each direction of direction_set and coarse node (a, b)."""
+    nz, nx = np.asarray(c).shape
+    cross = ray_crossings(c, h, src, rec, J, A1, stride, nfan, rtol, max_steps)
+    v = visibility_of(cross, src, rec, h, widen)
+    return v.reshape(v.shape[0], mask_nodes(nz, stride).size, mask_nodes(nx, stride).size)
 
 
 def expand_mask(vis, J, A1, nz, nx, stride):

@@ -32,7 +32,8 @@ EXPORTS = [
     "mp_create", "mp_destroy", "mp_set_background", "mp_footprint", "mp_apply_F", "mp_model",
     "mp_apply_Fadj", "mp_apply_H", "mp_apply_H_batch", "mp_release_cache", "mp_basis_create",
     "mp_basis_destroy", "mp_probe_fit", "mp_apply_Hinv", "mp_last_stats", "mp_strerror",
-    "mp_last_error",
+    "mp_last_error", "mp_curvelet_create", "mp_curvelet_destroy", "mp_curvelet_wedges", "mp_curvelet_norms",
+    "mp_illumination", "mp_curvelet_synthesis", "mp_curvelet_analysis",
 ]
 
 
@@ -65,6 +66,11 @@ class BasisDesc(ctypes.Structure):
                 ("nq", ctypes.c_int), ("qs", ctypes.POINTER(ctypes.c_int)), ("family", ctypes.c_int),
                 ("modes", ctypes.POINTER(ctypes.c_int)), ("mults", ctypes.POINTER(ctypes.c_int)),
                 ("order", ctypes.c_int), ("tl_scale", ctypes.c_double)]
+
+
+class CurveletDesc(ctypes.Structure):
+    _fields_ = [("nscales", ctypes.c_int), ("nangles", ctypes.c_int), ("mask_stride", ctypes.c_int),
+                ("nfan", ctypes.c_int), ("max_steps", ctypes.c_int), ("ray_rtol", ctypes.c_double)]
 
 
 class MatprobeError(RuntimeError):
@@ -114,13 +120,21 @@ def lib():
     L.mp_basis_destroy.restype = None
     L.mp_probe_fit.argtypes = [vp, vp, i, ctypes.POINTER(vp), ctypes.POINTER(vp), dp, dp, vp]
     L.mp_apply_Hinv.argtypes = [vp, vp, dp, vp, vp, vp]
+    L.mp_curvelet_create.argtypes = [ctypes.POINTER(CurveletDesc), ctypes.POINTER(vp)]
+    L.mp_curvelet_destroy.argtypes = [vp]
+    L.mp_curvelet_destroy.restype = None
+    L.mp_curvelet_wedges.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.mp_curvelet_norms.argtypes = [vp, vp, dp, vp]
+    L.mp_illumination.argtypes = [vp, vp, vp, vp, vp]
+    L.mp_curvelet_synthesis.argtypes = [vp, vp, vp, vp, dp, vp, vp]
+    L.mp_curvelet_analysis.argtypes = [vp, vp, vp, vp, vp]
     L.mp_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.mp_strerror.argtypes = [ip]
     L.mp_strerror.restype = ctypes.c_char_p
     L.mp_last_error.argtypes = []
     L.mp_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("mp_destroy", "mp_basis_destroy", "mp_strerror", "mp_last_error"):
+        if name not in ("mp_destroy", "mp_basis_destroy", "mp_curvelet_destroy", "mp_strerror", "mp_last_error"):
             getattr(L, name).restype = ctypes.c_int
     _check_single_runtime()
     _lib = L

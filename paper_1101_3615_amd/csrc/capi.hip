@@ -9,6 +9,7 @@
 #include <utility>
 
 #include "runtime.h"
+#include "curvelet.h"
 #include "symbol.h"
 #include "tables.h"
 
@@ -181,6 +182,7 @@ int mp_create(const mp_grid* g, const mp_acq* a, const mp_opts* o, mp_ctx** out)
 void mp_destroy(mp_ctx* ctx) {
   if (!ctx) return;
   symbol_release(ctx);
+  curvelet_release(ctx);
   delete ctx->eng;
   delete ctx;
 }
@@ -343,6 +345,70 @@ int mp_apply_Hinv(mp_ctx* ctx, const mp_basis* basis, const double* c, const voi
   for (int i = 0; i < basis->b.na() * basis->b.nq(); ++i)
     if (!std::isfinite(c[i])) return fail(MP_ENUMERIC, "non-finite coefficient");
   return finish(ctx, symbol_apply(ctx, basis->b, c, img, out, (hipStream_t)stream));
+}
+
+int mp_curvelet_create(const mp_curvelet_desc* d, mp_curvelets** out) {
+  if (!d || !out) return fail(MP_EINVAL, "null argument");
+  *out = nullptr;
+  if (d->nscales < 2 || d->nscales > 8) return fail(MP_EINVAL, "nscales must be in [2, 8]");
+  if (d->nangles < 4 || d->nangles > 64 || d->nangles % 2) return fail(MP_EINVAL, "nangles must be even, in [4, 64]");
+  if (d->mask_stride < 1 || d->mask_stride > 64) return fail(MP_EINVAL, "mask_stride must be in [1, 64]");
+  if (d->nfan < 1 || d->nfan > 256) return fail(MP_EINVAL, "nfan must be in [1, 256]");
+  if (d->max_steps < 1 || d->max_steps > 1000000) return fail(MP_EINVAL, "max_steps must be in [1, 1e6]");
+  if (!(d->ray_rtol > 0.0) || !(d->ray_rtol <= 1.0)) return fail(MP_EINVAL, "ray_rtol must be in (0, 1]");
+  mp_curvelets* c = new mp_curvelets();
+  c->cv = {d->nscales, d->nangles, d->mask_stride, d->nfan, d->max_steps, d->ray_rtol};
+  *out = c;
+  return MP_OK;
+}
+
+void mp_curvelet_destroy(mp_curvelets* cv) { delete cv; }
+
+int mp_curvelet_wedges(const mp_curvelets* cv, int* nwedges, int* list) {
+  if (!cv || !nwedges) return fail(MP_EINVAL, "null argument");
+  std::vector<int> w;
+  curvelet_wedges(cv->cv, w);
+  *nwedges = (int)w.size() / 3;
+  if (list) std::copy(w.begin(), w.end(), list);
+  return MP_OK;
+}
+
+int mp_curvelet_norms(mp_ctx* ctx, const mp_curvelets* cv, double* norms, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!cv || !norms) return fail(MP_EINVAL, "null argument");
+  std::vector<double> v;
+  rc = curvelet_norms(ctx, cv->cv, v, (hipStream_t)stream);
+  if (rc == MP_OK) std::copy(v.begin(), v.end(), norms);
+  return finish(ctx, rc);
+}
+
+int mp_illumination(mp_ctx* ctx, const mp_curvelets* cv, const void* c_dev, unsigned char* mask_dev, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!cv || !c_dev || !mask_dev) return fail(MP_EINVAL, "null argument");
+  return finish(ctx, curvelet_illumination(ctx, cv->cv, c_dev, mask_dev, (hipStream_t)stream));
+}
+
+int mp_curvelet_synthesis(mp_ctx* ctx, const mp_curvelets* cv, const void* coef_dev, const unsigned char* mask_dev,
+                          const double* weights, void* out_dev, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!cv || !coef_dev || !out_dev) return fail(MP_EINVAL, "null argument");
+  if (weights) {
+    std::vector<int> w;
+    curvelet_wedges(cv->cv, w);
+    for (size_t i = 0; i < w.size() / 3; ++i)
+      if (!std::isfinite(weights[i])) return fail(MP_ENUMERIC, "non-finite weight");
+  }
+  return finish(ctx, curvelet_synthesis(ctx, cv->cv, coef_dev, mask_dev, weights, out_dev, (hipStream_t)stream));
+}
+
+int mp_curvelet_analysis(mp_ctx* ctx, const mp_curvelets* cv, const void* img_dev, void* coef_dev, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!cv || !img_dev || !coef_dev) return fail(MP_EINVAL, "null argument");
+  return finish(ctx, curvelet_analysis(ctx, cv->cv, img_dev, coef_dev, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -104,6 +104,7 @@ struct mp_ctx {
   bool poisoned = false;
   bool has_bg = false;
   void* symbol_ws = nullptr;   // probing workspace (owned by symbol.hip)
+  void* curvelet_ws = nullptr; // curvelet workspace (owned by curvelet.hip)
 };
 
 struct mp_basis {

@@ -850,6 +850,15 @@ static int apply_t(mp_ctx* ctx, const Basis& b, const double* c, const void* img
   return MP_OK;
 }
 
+int model_fft(mp_ctx* ctx, void* data, bool f64, int inverse, hipStream_t s) {
+  int rc = check_grid(ctx->cfg);
+  if (rc) return rc;
+  SymbolWS* ws = ws_of(ctx);
+  if ((rc = ensure_tables(ctx, ws, 0, s))) return rc;
+  if (f64) return fft_nd<double>(ctx, ws, static_cast<Cx<double>*>(data), inverse, s);
+  return fft_nd<float>(ctx, ws, static_cast<Cx<float>*>(data), inverse, s);
+}
+
 int symbol_apply(mp_ctx* ctx, const Basis& b, const double* c, const void* img, void* out, hipStream_t s) {
   int rc = check_grid(ctx->cfg);
   if (rc) return rc;

@@ -93,3 +93,28 @@ def test_basis_descriptor_validation_without_device():
     assert make(mults=np.array([[0, 17]], np.int32))[1] == b"rational Chebyshev degree must be in [0, 16]"
     assert make(modes=np.array([[0, 1, 0, 0]], np.int32))[1] == b"2D Fourier modes need m_y = 0"
     assert make(modes=np.array([[0, 0, 0, 2]], np.int32))[1] == b"mode phase must be 0 (cos) or 1 (sin)"
+
+
+def test_curvelet_descriptor_validation_and_wedges():
+    """Host-only calls: the descriptor's checks and the wedge list (same order as the
+    oracle's frame)."""
+    import ctypes
+    import numpy as np
+    from oracle import curvelet as C
+    from paper_1101_3615_amd import _lib as L
+    lib = ctypes.CDLL(LIB)
+    lib.mp_curvelet_destroy.restype = None
+    h = ctypes.c_void_p()
+    bad = [L.CurveletDesc(1, 8, 4, 8, 100, 1e-4), L.CurveletDesc(3, 5, 4, 8, 100, 1e-4),
+           L.CurveletDesc(3, 8, 0, 8, 100, 1e-4), L.CurveletDesc(3, 8, 4, 0, 100, 1e-4),
+           L.CurveletDesc(3, 8, 4, 8, 0, 1e-4), L.CurveletDesc(3, 8, 4, 8, 100, 0.0)]
+    for d in bad:
+        assert lib.mp_curvelet_create(ctypes.byref(d), ctypes.byref(h)) == L.MP_EINVAL
+    d = L.CurveletDesc(4, 8, 4, 8, 100, 1e-4)
+    assert lib.mp_curvelet_create(ctypes.byref(d), ctypes.byref(h)) == L.MP_OK
+    n = ctypes.c_int()
+    assert lib.mp_curvelet_wedges(h, ctypes.byref(n), None) == L.MP_OK
+    lst = np.zeros(3 * n.value, dtype=np.int32)
+    assert lib.mp_curvelet_wedges(h, ctypes.byref(n), lst.ctypes.data_as(ctypes.POINTER(ctypes.c_int))) == L.MP_OK
+    assert [tuple(lst[3 * w:3 * w + 3]) for w in range(n.value)] == C.wedges(4, 8)
+    lib.mp_curvelet_destroy(h)
