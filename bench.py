@@ -228,6 +228,7 @@ def volume_run(nt):
             "gcell_steps_per_s": round(cs / wall / 1e9, 2), "sweeps": sweeps}
 
 
+CURVELETS = dict(nscales=4, nangles=8, mask_stride=4, nfan=16)   # frame and mask of the curvelet trials
 GEN_SIZES = [(0, 0, 0), (0, 1, 1), (0, 2, 2), (1, 0, 2), (1, 2, 2)]   # (Fourier m, angular a, TL degree r): p = 1, 4, 9, 21, 63
 
 
@@ -243,14 +244,62 @@ def generalization_run(ns=(1, 2, 4)):
     c = F.medium(w)
     P = M.Problem.from_spec(w)
     P.set_background(torch.from_numpy(c).to("cuda:0"))
-    trials = [torch.from_numpy(F.wavepackets(w, c, 100 + s, w.packets_per_trial)).to("cuda:0") for s in range(5)]
+    import numpy as np
+
+    from paper_1101_3615_amd.curvelets import Curvelets
+    wp = [torch.from_numpy(F.wavepackets(w, c, 100 + s, w.packets_per_trial)).to("cuda:0") for s in range(5)]
+    cv = Curvelets(P, **CURVELETS)
+    mask = cv.illumination(torch.from_numpy(c).to("cuda:0"))
+    cu = [cv.trial(torch.from_numpy(F.normal_field(cv.coef_shape, 600 + s, np.float64)), mask).clone()
+          for s in range(5)]
     bases = paper_bases(2, GEN_SIZES)
     out = []
-    for n in ns:
-        for p, mse, relres, deficient in generalization(P, bases, trials[:n], trials[4]):
-            out.append({"study": "generalization", "workload": w.name, "preconditioner": f"R{n}", "p": p,
-                        "relative_mse": round(mse, 6), "fit_relres": round(relres, 6), "rank_deficient": deficient})
+    for kind, trials in (("wavepackets", wp), ("curvelets", cu)):
+        for n in ns:
+            for p, mse, relres, deficient in generalization(P, bases, trials[:n], trials[4]):
+                out.append({"study": "generalization", "workload": w.name, "trials": kind, "preconditioner": f"R{n}",
+                            "p": p, "relative_mse": round(mse, 6), "fit_relres": round(relres, 6),
+                            "rank_deficient": deficient})
     return out
+
+
+def curvelet_run(reps=3):
+    """Curvelet trial synthesis and the ray-traced illumination mask on the 512x256 workload
+    (FP32): device time per call and the mask's visible fraction."""
+    import numpy as np
+    import torch
+
+    import fixtures as F
+    import paper_1101_3615_amd as M
+    from paper_1101_3615_amd.curvelets import Curvelets
+    w = F.c2()
+    c = torch.from_numpy(F.medium(w)).to("cuda:0")
+    P = M.Problem.from_spec(w)
+    cv = Curvelets(P, **CURVELETS)
+    z = torch.from_numpy(F.normal_field(cv.coef_shape, 700)).to("cuda:0")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t) * 1e3 / reps
+
+    mask, ms_mask = timed(lambda: cv.illumination(c))
+    _, ms_trial = timed(lambda: cv.trial(z, mask))
+    img = torch.from_numpy(F.normal_field(w.model_shape, 701)).to("cuda:0")
+    _, ms_an = timed(lambda: cv.analysis(img))
+    nz, nx = w.model_shape
+    s = CURVELETS["mask_stride"]
+    nodes = -(-nz // s) * -(-nx // s)
+    ndir = len({(A, l) for j, l, A in cv.wedges if j > 0})
+    rays = 2 * nodes * ndir * CURVELETS["nfan"]
+    return {"study": "curvelets", "workload": w.name, "wedges": cv.nw, "mask_nodes": nodes, "directions": ndir,
+            "rays": rays, "illumination_ms": round(ms_mask, 2), "rays_per_s": float(f"{rays / ms_mask * 1e3:.4g}"),
+            "visible_fraction": round(float(mask.float().mean()), 4), "trial_ms": round(ms_trial, 2),
+            "analysis_ms": round(ms_an, 2)}
 
 
 def gauss_newton_records(P, w, c, refl, basis, trial, outer=3, inner=5):
@@ -305,6 +354,7 @@ def inversion_run(gd_steps=200, cg_iters=20):
     import fixtures as F
     import paper_1101_3615_amd as M
     from paper_1101_3615_amd import inversion as I
+    from paper_1101_3615_amd.curvelets import Curvelets
     from paper_1101_3615_amd.study import paper_bases
     w = F.c1()
     c = F.medium(w)
@@ -326,8 +376,16 @@ def inversion_run(gd_steps=200, cg_iters=20):
                 "mse_vs_descent": round(I.relative_mse(a * b, x_gd), 6), "mse_vs_true": round(I.relative_mse(a * b, m), 6)})
     trials = [torch.from_numpy(F.wavepackets(w, c, 100 + s, w.packets_per_trial)).to("cuda:0") for s in range(4)]
     Htrials = [P.apply_H(y) for y in trials]
+    # randomized curvelet trials on the illuminated set, and the projection onto it that
+    # the paper applies before comparing with the true model
+    cv = Curvelets(P, **CURVELETS)
+    mask = cv.illumination(torch.from_numpy(c).to("cuda:0"))
+    ctrials = [cv.trial(torch.from_numpy(F.normal_field(cv.coef_shape, 500 + s, np.float64)), mask) for s in range(4)]
+    Hctrials = [P.apply_H(y) for y in ctrials]
+    m_vis = cv.project(m, mask).clone()
     kys, kxs = I.krylov_pairs(P, b, 4)
     fits = {"R1": (trials[:1], Htrials[:1]), "R4": (trials, Htrials),
+            "R1c": (ctrials[:1], Hctrials[:1]), "R4c": (ctrials, Hctrials),
             "K1": (kys[:1], kxs[:1]), "K2": (kys[:2], kxs[:2]), "K4": (kys, kxs)}
     bases = paper_bases(2, GEN_SIZES)
     precs = {}
@@ -340,7 +398,9 @@ def inversion_run(gd_steps=200, cg_iters=20):
             torch.cuda.synchronize()
             out.append({"study": "inversion", "workload": w.name, "preconditioner": name, "p": B.p,
                         "mse_vs_descent": round(I.relative_mse(img, x_gd), 6),
-                        "mse_vs_true": round(I.relative_mse(img, m), 6), "fit_relres": round(relres, 6),
+                        "mse_vs_true": round(I.relative_mse(img, m), 6),
+                        "mse_vs_true_visible": round(I.relative_mse(cv.project(img, mask), m_vis), 6),
+                        "fit_relres": round(relres, 6),
                         "rank_deficient": deficient, "apply_ms": round((time.perf_counter() - t) * 1e3, 3)})
             if B.p == 21:
                 precs[name] = I.preconditioner(P, B, coef)
@@ -379,6 +439,9 @@ def main():
                     help="only run the linearised inversion study (128x128 FP64 workload: 200 descent steps as "
                          "the reference image, Rn/Kn fitted inverses applied to the migrated image, CG with and "
                          "without a fitted preconditioner) and print one JSON line per result")
+    ap.add_argument("--curvelets", action="store_true",
+                    help="only time the curvelet trial synthesis and the ray-traced illumination mask on the "
+                         "512x256 workload and print one JSON line")
     ap.add_argument("--cpu-workers", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -411,6 +474,9 @@ def main():
     if args.generalization:
         for rec in generalization_run():
             print(json.dumps(rec), flush=True)
+        return
+    if args.curvelets:
+        print(json.dumps(curvelet_run()), flush=True)
         return
     if args.inversion:
         for rec in inversion_run():

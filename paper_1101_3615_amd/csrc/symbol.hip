@@ -832,21 +832,18 @@ static int apply_t(mp_ctx* ctx, const Basis& b, const double* c, const void* img
   const Grid3 g = grid3(cf);
   const int nq = b.nq();
   SY_HIP(hipMemcpyAsync(ws->qs.get(), mt.data(), sizeof(int) * mt.size(), hipMemcpyHostToDevice, s));
-  std::vector<double> coef((size_t)b.na() * nq);
-  for (size_t i = 0; i < coef.size(); ++i) coef[i] = c[i];
-  DevBuf coefs;
-  if ((rc = coefs.ensure(sizeof(double) * coef.size(), &ctx->budget, "coefficients"))) return rc;
-  SY_HIP(hipMemcpyAsync(coefs.get(), coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, s));
+  // p <= MAXP coefficients into the workspace's table (stream-ordered after earlier users)
+  SY_HIP(hipMemcpyAsync(ws->coef.get(), c, sizeof(double) * (size_t)b.na() * nq, hipMemcpyHostToDevice, s));
   for (int a = 0; a < b.na(); ++a) {
     hipLaunchKernelGGL(k_multiplier<R>, egrid(n), dim3(256), 0, s, Y, X, g, nq, ws->qs.as<int>(),
-                       coefs.as<double>() + (size_t)a * nq, b.family, b.ndim, b.order, b.tl_scale);
+                       ws->coef.as<double>() + (size_t)a * nq, b.family, b.ndim, b.order, b.tl_scale);
     SY_LAUNCH();
     if ((rc = fft_nd<R>(ctx, ws, Y, 1, s))) return rc;
     hipLaunchKernelGGL((k_accum_out<R, T>), egrid(n), dim3(256), 0, s, static_cast<T*>(out), Y, g,
                        ws->leg.as<double>(), ws->maxdeg, ws->degs.as<int>() + 5 * a, 1.0 / (double)n, a == 0 ? 1 : 0);
     SY_LAUNCH();
   }
-  SY_HIP(hipStreamSynchronize(s));   // keeps the coefficient buffer alive until used
+  SY_HIP(hipStreamSynchronize(s));   // the host tables copied above outlive the copies
   return MP_OK;
 }
 
