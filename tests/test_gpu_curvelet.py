@@ -130,3 +130,33 @@ def test_illumination_full_size_sampled_nodes():
             d = pos[(A, l)]
             assert lo[d, k] <= g <= hi[d, k], (a, b, wi)
     assert 0 < got.sum() < got.size
+
+
+def test_error_paths():
+    """Curvelets and modelling refuse what they cannot do, before any kernel runs."""
+    M, Curvelets = _gpu()
+    from test_gpu_wave import ragged
+    w = ragged("f32", nt=10)                       # 300 x 70: not powers of two
+    P = M.Problem.from_spec(w)
+    with pytest.raises(M.MatprobeError) as e:
+        P.model()
+    assert e.value.code == -4                      # no background
+    cv = Curvelets(P, nscales=3, nangles=4)
+    with pytest.raises(M.MatprobeError) as e:
+        cv.analysis(torch.zeros(w.model_shape))
+    assert e.value.code == -6                      # power-of-two sizes only
+    w2 = _wl("f32", 32, 64, [8, 40], [0, 2, 4])
+    w2 = w2.with_(src=np.array([[8, 0], [40, 3]], np.int32))   # sources on two rows
+    Q = M.Problem.from_spec(w2)
+    cq = Curvelets(Q, nscales=3, nangles=4)
+    with pytest.raises(M.MatprobeError) as e:
+        cq.illumination(torch.from_numpy(F.medium(w2)))
+    assert e.value.code == -6
+    z = torch.zeros(cq.coef_shape)
+    wts = np.ones(cq.nw)
+    wts[2] = np.nan
+    with pytest.raises(M.MatprobeError) as e:
+        cq.synthesis(z, None, wts)
+    assert e.value.code == -5
+    with pytest.raises(ValueError):
+        cq.synthesis(torch.zeros(3, 32, 64))
