@@ -233,6 +233,24 @@ int mp_probe_fit(mp_ctx* ctx, const mp_basis* basis, int T, const void* const* y
 int mp_apply_Hinv(mp_ctx* ctx, const mp_basis* basis, const double* c, const void* img_dev,
                   void* out_dev, void* stream);
 
+/* ---- Vector kernels of the solvers built on the operators (steepest descent and
+ * conjugate gradients on the normal equations, Sec. 1.1 and Sec. 2; Gauss-Newton,
+ * Sec. 1.1).  Vectors are n contiguous elements in the context's precision (device);
+ * n may be a model-grid or a data-space size; with n = 0 the pointers are not used. */
+
+/* *out (host) = sum_i a_i b_i with FP64 products and accumulation in a fixed order
+ * (results repeat bit for bit).  Synchronises the stream. */
+int mp_vec_dot(mp_ctx* ctx, long long n, const void* a_dev, const void* b_dev, double* out, void* stream);
+
+/* y = alpha x + beta y, computed in FP64 and rounded to the field precision (x and y may
+ * be the same buffer).  MP_ENUMERIC for a non-finite alpha or beta. */
+int mp_vec_axpby(mp_ctx* ctx, long long n, double alpha, const void* x_dev, double beta, void* y_dev, void* stream);
+
+/* The Gauss-Newton model update on the model grid: m = c^-2 + dm, c <- m^(-1/2) (c_dev
+ * in place, dm_dev a step in m = 1/c^2).  MP_ENUMERIC, with c untouched, if m is not
+ * positive and finite everywhere.  Synchronises the stream. */
+int mp_velocity_update(mp_ctx* ctx, void* c_dev, const void* dm_dev, void* stream);
+
 /* ---- Curvelet-space trial functions (Sec. 1.5; the mask's construction, Sec. 2) ----
  * 2D contexts with power-of-two model sizes up to 1024 per axis (MP_EUNSUPPORTED
  * otherwise).  The frame is undecimated and built in the frequency domain of the

@@ -10,7 +10,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmatprobe.so")
-SOURCES = ["capi.hip", "engine.hip", "wave2d.hip", "wave3d.hip", "prep.hip", "symbol.hip", "curvelet.hip"]
+SOURCES = ["capi.hip", "engine.hip", "wave2d.hip", "wave3d.hip", "prep.hip", "symbol.hip", "curvelet.hip", "vec.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

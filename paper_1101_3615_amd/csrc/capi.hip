@@ -11,6 +11,7 @@
 #include "runtime.h"
 #include "curvelet.h"
 #include "symbol.h"
+#include "vec.h"
 #include "tables.h"
 
 namespace mp {
@@ -183,6 +184,7 @@ void mp_destroy(mp_ctx* ctx) {
   if (!ctx) return;
   symbol_release(ctx);
   curvelet_release(ctx);
+  vec_release(ctx);
   delete ctx->eng;
   delete ctx;
 }
@@ -409,6 +411,35 @@ int mp_curvelet_analysis(mp_ctx* ctx, const mp_curvelets* cv, const void* img_de
   if (rc) return rc;
   if (!cv || !img_dev || !coef_dev) return fail(MP_EINVAL, "null argument");
   return finish(ctx, curvelet_analysis(ctx, cv->cv, img_dev, coef_dev, (hipStream_t)stream));
+}
+
+int mp_vec_dot(mp_ctx* ctx, long long n, const void* a_dev, const void* b_dev, double* out, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!out || n < 0) return fail(MP_EINVAL, "bad vec_dot arguments");
+  if (n == 0) {
+    *out = 0.0;
+    return MP_OK;
+  }
+  if (!a_dev || !b_dev) return fail(MP_EINVAL, "null buffer");
+  return finish(ctx, vec_dot(ctx, n, a_dev, b_dev, out, (hipStream_t)stream));
+}
+
+int mp_vec_axpby(mp_ctx* ctx, long long n, double alpha, const void* x_dev, double beta, void* y_dev, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (n < 0) return fail(MP_EINVAL, "bad vec_axpby arguments");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(MP_ENUMERIC, "non-finite scalar");
+  if (n == 0) return MP_OK;
+  if (!x_dev || !y_dev) return fail(MP_EINVAL, "null buffer");
+  return finish(ctx, vec_axpby(ctx, n, alpha, x_dev, beta, y_dev, (hipStream_t)stream));
+}
+
+int mp_velocity_update(mp_ctx* ctx, void* c_dev, const void* dm_dev, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!c_dev || !dm_dev) return fail(MP_EINVAL, "null buffer");
+  return finish(ctx, velocity_update(ctx, c_dev, dm_dev, (hipStream_t)stream));
 }
 
 }  // extern "C"

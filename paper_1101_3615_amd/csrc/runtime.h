@@ -105,6 +105,7 @@ struct mp_ctx {
   bool has_bg = false;
   void* symbol_ws = nullptr;   // probing workspace (owned by symbol.hip)
   void* curvelet_ws = nullptr; // curvelet workspace (owned by curvelet.hip)
+  void* vec_ws = nullptr;      // solver vector workspace (owned by vec.hip)
 };
 
 struct mp_basis {

@@ -7,24 +7,21 @@ motivation, Sec. 1).  Two fitted preconditioners (Sec. 2): Rn from n random tria
 functions (probe_fit on (y_t, H y_t)) and Kn from the Krylov subspace of the
 migrated image, the pairs (H^(j-1) b, H^j b), j = 1..n.
 
-Every operator application runs in the library's kernels (apply_H, apply_Hinv,
-probe_fit); the few vector updates per iteration (dot products, axpy) are torch
-operations on the problem's device.
+Every step runs in the library's kernels: the operators (apply_H, apply_Hinv, probe_fit,
+model, apply_Fadj) and the solvers' vector work (dot products with FP64 accumulation,
+y = alpha x + beta y, the velocity update of Gauss-Newton); torch only holds the vectors.
 """
 import torch
 
+from . import _lib as L
 from .problem import apply_Hinv, probe_fit
 
 
 def relative_mse(m, ref):
     """||m - ref||_2 / ||ref||_2 (the paper's relative MSE between models, Sec. 2: a ratio
-    of norms, not of squared norms)."""
+    of norms, not of squared norms).  A measurement of results, taken with torch."""
     m, ref = m.double(), ref.to(m.device).double()
     return float(torch.linalg.vector_norm(m - ref) / torch.linalg.vector_norm(ref))
-
-
-def _dot(a, b):
-    return float((a.double() * b.double()).sum())
 
 
 def krylov_pairs(problem, b, n):
@@ -52,53 +49,55 @@ def preconditioner(problem, basis, c):
 
 def steepest_descent(problem, b, steps):
     """x <- x + alpha r with r = b - H x and alpha = r.r / r.Hr, from x = 0.  Returns x
-    and the values of the functional 1/2 x.Hx - b.x = -1/2 x.(b + r), one per iterate
+    and the values of the functional 1/2 x.Hx - b.x = -1/2 (x.b + x.r), one per iterate
     (the first for x = 0); exact steps make them non-increasing."""
+    P = problem
     x = torch.zeros_like(b)
     r = b.clone()
     phis = [0.0]
     for _ in range(steps):
-        Hr = problem.apply_H(r)
-        rr, rHr = _dot(r, r), _dot(r, Hr)
+        Hr = P.apply_H(r)
+        rr, rHr = P.dot(r, r), P.dot(r, Hr)
         if rHr <= 0.0 or rr == 0.0:
             break
         alpha = rr / rHr
-        x += alpha * r
-        r -= alpha * Hr
-        phis.append(-0.5 * _dot(x, b + r))
+        P.axpby(alpha, r, 1.0, x)
+        P.axpby(-alpha, Hr, 1.0, r)
+        phis.append(-0.5 * (P.dot(x, b) + P.dot(x, r)))
     return x, phis
 
 
 def conjugate_gradient(problem, b, iters, precond=None):
     """(Preconditioned) conjugate gradients on H x = b from x = 0; returns x and the
     residual norms (one per iteration, the first for x = 0)."""
-    M = precond if precond is not None else (lambda v: v)
+    P = problem
     x = torch.zeros_like(b)
     r = b.clone()
-    z = M(r)
+    z = precond(r) if precond is not None else r.clone()
     p = z.clone()
-    rz = _dot(r, z)
-    norms = [_dot(r, r) ** 0.5]
+    rz = P.dot(r, z)
+    norms = [P.dot(r, r) ** 0.5]
     for _ in range(iters):
-        Hp = problem.apply_H(p)
-        pHp = _dot(p, Hp)
+        Hp = P.apply_H(p)
+        pHp = P.dot(p, Hp)
         if pHp == 0.0:
             break
         alpha = rz / pHp
-        x += alpha * p
-        r -= alpha * Hp
-        norms.append(_dot(r, r) ** 0.5)
-        z = M(r)
-        rz_new = _dot(r, z)
-        p = z + (rz_new / rz) * p
+        P.axpby(alpha, p, 1.0, x)
+        P.axpby(-alpha, Hp, 1.0, r)
+        norms.append(P.dot(r, r) ** 0.5)
+        z = precond(r) if precond is not None else r.clone()
+        rz_new = P.dot(r, z)
+        P.axpby(1.0, z, rz_new / rz, p)
         rz = rz_new
     return x, norms
 
 
 def misfit(problem, d_obs):
     """Residual data r = d - F[m] at the current background and J = 1/2 r.r (Sec. 1.1)."""
-    r = d_obs - problem.model()
-    return r, 0.5 * _dot(r, r)
+    r = problem.model()
+    problem.axpby(1.0, d_obs, -1.0, r)
+    return r, 0.5 * problem.dot(r, r)
 
 
 def gauss_newton(problem, c0, d_obs, outer, inner, precond_at=None):
@@ -107,11 +106,13 @@ def gauss_newton(problem, c0, d_obs, outer, inner, precond_at=None):
     At c_k: r = d - F[m_k] (nonlinear modelling), the migrated residual b = F* r
     (minus the gradient of J), the step dm from `inner` CG iterations on H dm = b
     (preconditioned by precond_at(problem, b), a probed inverse fitted at c_k: Rn, or Kn
-    on the Krylov pairs of b), or
-    with inner = 0 the preconditioner applied to b (the fitted inverse in place of
-    H^-1, Sec. 2.2); m_{k+1} = m_k + dm, c_{k+1} = m_{k+1}^(-1/2).  Leaves the problem's background at the
-    last iterate; returns the velocity iterates and the misfits J(c_k)."""
-    c = c0.to(device=problem.device, dtype=problem.torch_dtype).clone()
+    on the Krylov pairs of b), or with inner = 0 the preconditioner applied to b (the
+    fitted inverse in place of H^-1, Sec. 2.2); m_{k+1} = m_k + dm, c_{k+1} = m_{k+1}^(-1/2)
+    (in the library's kernel, which refuses a step that makes m non-positive).  Leaves the
+    problem's background at the last iterate; returns the velocity iterates and the
+    misfits J(c_k)."""
+    d_obs = problem._vec(d_obs, "d_obs")
+    c = c0.to(device=problem.device, dtype=problem.torch_dtype).contiguous().clone()
     cs, Js = [c], []
     for _ in range(outer):
         problem.set_background(c)
@@ -123,10 +124,13 @@ def gauss_newton(problem, c0, d_obs, outer, inner, precond_at=None):
         else:
             dm, _ = conjugate_gradient(problem, b, inner,
                                        precond=None if precond_at is None else precond_at(problem, b))
-        m = 1.0 / (c * c) + dm
-        if bool((m <= 0).any()):
-            raise ValueError("Gauss-Newton step leaves m = 1/c^2 non-positive")
-        c = 1.0 / torch.sqrt(m)
+        c = c.clone()
+        try:
+            problem.velocity_update(c, dm)
+        except L.MatprobeError as e:
+            if e.code == L.MP_ENUMERIC:
+                raise ValueError("Gauss-Newton step leaves m = 1/c^2 non-positive") from e
+            raise
         cs.append(c)
     problem.set_background(c)
     Js.append(misfit(problem, d_obs)[1])

@@ -151,6 +151,39 @@ class Problem:
         self._keep = dms                     # inputs must outlive the enqueued work
         return outs
 
+    # ---- vector kernels of the solvers (FP64 accumulation, fixed order) ----
+    def _vec(self, t, name):
+        if not (isinstance(t, torch.Tensor) and t.device == self.device and t.dtype == self.torch_dtype
+                and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {self.torch_dtype} tensor on {self.device}")
+        return t
+
+    def dot(self, a, b, stream=None):
+        """sum_i a_i b_i (FP64, fixed summation order); a and b of equal size."""
+        a, b = self._vec(a, "a"), self._vec(b, "b")
+        if a.numel() != b.numel():
+            raise ValueError("dot of vectors of different sizes")
+        out = ctypes.c_double()
+        L.check(self._lib.mp_vec_dot(self._ctx, a.numel(), _ptr(a), _ptr(b), ctypes.byref(out), _stream(stream)))
+        return out.value
+
+    def axpby(self, alpha, x, beta, y, stream=None):
+        """y = alpha x + beta y in place (FP64 arithmetic, rounded to the field precision)."""
+        x, y = self._vec(x, "x"), self._vec(y, "y")
+        if x.numel() != y.numel():
+            raise ValueError("axpby of vectors of different sizes")
+        L.check(self._lib.mp_vec_axpby(self._ctx, x.numel(), float(alpha), _ptr(x), float(beta), _ptr(y),
+                                       _stream(stream)))
+        return y
+
+    def velocity_update(self, c, dm, stream=None):
+        """c <- (c^-2 + dm)^(-1/2) in place on the model grid (a Gauss-Newton step in m = 1/c^2)."""
+        c, dm = self._vec(c, "c"), self._vec(dm, "dm")
+        if tuple(c.shape) != self.model_shape or tuple(dm.shape) != self.model_shape:
+            raise ValueError(f"c and dm must have the model shape {self.model_shape}")
+        L.check(self._lib.mp_velocity_update(self._ctx, _ptr(c), _ptr(dm), _stream(stream)))
+        return c
+
     def release_cache(self):
         L.check(self._lib.mp_release_cache(self._ctx))
 
