@@ -336,8 +336,9 @@ def gauss_newton_records(P, w, c, refl, basis, trial, outer=3, inner=5):
             out.append(dict(rec, error=str(e)))
             continue
         torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / outer
         err = [round(I.relative_mse(1.0 / (ck * ck) - m0, refl), 6) for ck in cs]
-        out.append(dict(rec, ms_per_outer=round((time.perf_counter() - t) * 1e3 / outer, 1),
+        out.append(dict(rec, ms_per_outer=round(ms, 1),
                         misfit=[float(f"{j:.6g}") for j in Js], model_error=err))
     P.set_background(c0)
     return out
@@ -396,12 +397,13 @@ def inversion_run(gd_steps=200, cg_iters=20):
             t = time.perf_counter()
             img = M.apply_Hinv(P, B, coef, b)
             torch.cuda.synchronize()
+            apply_ms = (time.perf_counter() - t) * 1e3
             out.append({"study": "inversion", "workload": w.name, "preconditioner": name, "p": B.p,
                         "mse_vs_descent": round(I.relative_mse(img, x_gd), 6),
                         "mse_vs_true": round(I.relative_mse(img, m), 6),
                         "mse_vs_true_visible": round(I.relative_mse(cv.project(img, mask), m_vis), 6),
                         "fit_relres": round(relres, 6),
-                        "rank_deficient": deficient, "apply_ms": round((time.perf_counter() - t) * 1e3, 3)})
+                        "rank_deficient": deficient, "apply_ms": round(apply_ms, 3)})
             if B.p == 21:
                 precs[name] = I.preconditioner(P, B, coef)
     out += gauss_newton_records(P, w, c, m, bases[3], trials[0])
