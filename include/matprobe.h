@@ -62,7 +62,7 @@ extern "C" {
 #define MP_EDEVICE (-3)      /* HIP error; the context is poisoned */
 #define MP_ESTATE (-4)       /* no background set */
 #define MP_ENUMERIC (-5)     /* non-finite input/output or rank-deficient fit */
-#define MP_EUNSUPPORTED (-6) /* valid request outside what this build implements */
+#define MP_EUNSUPPORTED (-6) /* valid request outside what the library implements */
 
 #define MP_F32 1
 #define MP_F64 2

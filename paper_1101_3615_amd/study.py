@@ -1,7 +1,7 @@
 """Generalization of the probed inverse (Sec. 2.2 of the paper, "Rn" preconditioners).
 
 The preconditioner Rn fits the inverse-Hessian symbol from n trial functions y_t
-and their images x_t = H y_t (Sec. 1.4), then is judged on a trial function y'
+and their images x_t = H y_t (Sec. 1.4), then is evaluated on a trial function y'
 drawn independently of them: the relative mean-squared error (defined in the
 paper's numerical section as a ratio of 2-norms, not of their squares) of
 reconstructing y' from H y' through the fitted series,
