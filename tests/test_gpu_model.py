@@ -93,3 +93,39 @@ def test_born_is_the_derivative_of_modelling_full_size():
     print("Taylor errors", errs)
     assert errs[1] < 1e-3
     assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+def test_model_full_size_sampled_shots():
+    """512 x 256 FP32 workload (64 shots, 3000 steps, the launch configuration of the
+    benchmark): the traces of a sampled shot against the oracle's background sweep of it."""
+    M = _gpu()
+    w = F.c2()
+    c = F.medium(w)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c))
+    d = P.model()
+    O = Oracle(w, c)
+    for s in (37,):
+        ref = O.background(s, keep_g=False)[1]
+        err = rel(d[s].double().cpu().numpy(), ref)
+        print(f"shot {s}: rel L2 {err:.3e}")
+        assert err <= TOL["f32"]
+
+
+def test_gauss_newton_lowers_the_misfit_full_size():
+    """On the 128 x 128 FP64 workload, from the smooth background towards it plus a weak
+    reflectivity: one Gauss-Newton step with three CG iterations lowers the misfit."""
+    M = _gpu()
+    from paper_1101_3615_amd import inversion as I
+    w = F.c1()
+    c0 = F.medium(w).astype(np.float64)
+    m_true = 1.0 / c0 ** 2 + 0.5 * F.reflectivity(w, c0, seed=3).astype(np.float64)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(1.0 / np.sqrt(m_true)))
+    d_obs = P.model().clone()
+    cs, Js = I.gauss_newton(P, torch.from_numpy(c0), d_obs, 1, 3)
+    print("misfits", Js)
+    assert Js[1] < 0.5 * Js[0]
+    err0 = np.linalg.norm(1.0 / c0 ** 2 - m_true)
+    err1 = np.linalg.norm(1.0 / cs[1].cpu().numpy() ** 2 - m_true)
+    assert err1 < err0
