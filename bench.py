@@ -529,6 +529,18 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = P.stats()
+    # apply_H alone, outside the timed region: background cold (plain: the call computes and
+    # keeps the g history) and resident (the next call reuses it); median of three each
+    cold, warm = [], []
+    for _ in range(3):
+        P.set_background(c_dev)
+        for lst, y, x in ((cold, y_dev[0], xs[0]), (warm, y_dev[-1], xs[-1])):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            P.apply_H(y, out=x)
+            torch.cuda.synchronize()
+            lst.append((time.perf_counter() - t1) * 1e3)
+    P.stats()
     P.release_cache()
     serving = serve_leg(args.serve_seconds) if (args.serve_seconds > 0 and not args.profile_steps) else None
     ms_per_step = 1e3 * wall / args.steps
@@ -578,6 +590,7 @@ def main():
         "serving": serving,
         "sweeps": sweeps,
         "profile_run": bool(args.profile_steps),
+        "apply_H_ms": {"plain": round(sorted(cold)[1], 2), "resident": round(sorted(warm)[1], 2)},
         "fit_relres": relres,
         "fit_rank_deficient": deficient,
     }
