@@ -263,6 +263,38 @@ def generalization_run(ns=(1, 2, 4)):
     return out
 
 
+def variable_media_run(gammas=(0.0, 0.1, 0.2, 0.3, 0.4), gd_steps=200, ntrials=5):
+    """R5 preconditioner applied to the migrated image against the descent image, in
+    backgrounds blended between a uniform medium (gamma = 0) and a smooth variable one
+    (gamma = 0.4), on the 128x128 FP64 workload, for each basis size."""
+    import numpy as np
+    import torch
+
+    import fixtures as F
+    import paper_1101_3615_amd as M
+    from paper_1101_3615_amd import inversion as I
+    from paper_1101_3615_amd.study import paper_bases
+    w = F.c1()
+    P = M.Problem.from_spec(w)
+    bases = paper_bases(2, GEN_SIZES)
+    out = []
+    for g in gammas:
+        c = F.blended_medium(w, g)
+        P.set_background(torch.from_numpy(c).to("cuda:0"))
+        m = torch.from_numpy(F.reflectivity(w, c, seed=5).astype(np.float64)).to("cuda:0")
+        b = P.apply_H(m).clone()
+        x_gd, _ = I.steepest_descent(P, b, gd_steps)
+        ys = [torch.from_numpy(F.wavepackets(w, c, 100 + s, w.packets_per_trial)).to("cuda:0") for s in range(ntrials)]
+        xs = [P.apply_H(y).clone() for y in ys]
+        for B in bases:
+            coef, relres, deficient = M.probe_fit(P, B, ys, xs, strict=False)
+            img = M.apply_Hinv(P, B, coef, b)
+            out.append({"study": "variable_media", "workload": w.name, "gamma": g, "preconditioner": f"R{ntrials}",
+                        "p": B.p, "mse_vs_descent": round(I.relative_mse(img, x_gd), 6),
+                        "fit_relres": round(relres, 6), "rank_deficient": deficient})
+    return out
+
+
 def curvelet_run(reps=3):
     """Curvelet trial synthesis and the ray-traced illumination mask on the 512x256 workload
     (FP32): device time per call and the mask's visible fraction."""
@@ -385,8 +417,17 @@ def inversion_run(gd_steps=200, cg_iters=20):
     Hctrials = [P.apply_H(y) for y in ctrials]
     m_vis = cv.project(m, mask).clone()
     kys, kxs = I.krylov_pairs(P, b, 4)
+    # the other trial functions of Sec. 2.4: white noise in model space, H applied to it,
+    # white data noise migrated; and the fit on the true model itself
+    white = [torch.from_numpy(F.normal_field(w.model_shape, 800 + s, np.float64)).to("cuda:0") for s in range(4)]
+    Hwhite = [P.apply_H(z).clone() for z in white]
+    HHwhite = [P.apply_H(y) for y in Hwhite]
+    mig = [P.apply_Fadj(torch.from_numpy(F.normal_field(P.data_shape, 900 + s, np.float64)).to("cuda:0")).clone()
+           for s in range(4)]
+    Hmig = [P.apply_H(y) for y in mig]
     fits = {"R1": (trials[:1], Htrials[:1]), "R4": (trials, Htrials),
             "R1c": (ctrials[:1], Hctrials[:1]), "R4c": (ctrials, Hctrials),
+            "R4w": (white, Hwhite), "R4Hw": (Hwhite, HHwhite), "R4d": (mig, Hmig), "Rtrue": ([m], [b]),
             "K1": (kys[:1], kxs[:1]), "K2": (kys[:2], kxs[:2]), "K4": (kys, kxs)}
     bases = paper_bases(2, GEN_SIZES)
     precs = {}
@@ -441,6 +482,9 @@ def main():
                     help="only run the linearised inversion study (128x128 FP64 workload: 200 descent steps as "
                          "the reference image, Rn/Kn fitted inverses applied to the migrated image, CG with and "
                          "without a fitted preconditioner) and print one JSON line per result")
+    ap.add_argument("--variable-media", action="store_true",
+                    help="only run the variable-media study (R5 on backgrounds blended from uniform to smooth "
+                         "variable, 128x128 FP64 workload) and print one JSON line per fit")
     ap.add_argument("--curvelets", action="store_true",
                     help="only time the curvelet trial synthesis and the ray-traced illumination mask on the "
                          "512x256 workload and print one JSON line")
@@ -479,6 +523,10 @@ def main():
         return
     if args.curvelets:
         print(json.dumps(curvelet_run()), flush=True)
+        return
+    if args.variable_media:
+        for rec in variable_media_run():
+            print(json.dumps(rec), flush=True)
         return
     if args.inversion:
         for rec in inversion_run():

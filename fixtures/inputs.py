@@ -171,3 +171,19 @@ def tiny(ndim=2, n=16, nb=8, nt=200, ns=2, nr=16, h=10.0, dt=1.0e-3,
                     ckpt_every=ckpt_every, medium=med,
                     legendre=[(0,) * ndim, (1,) + (0,) * (ndim - 1)],
                     trial_seeds=(seed + 1,), packets_per_trial=2)
+
+
+def blended_medium(w, gamma, r=0.05, seed=4, cmin=1500.0, cmax=3000.0, corr=60.0):
+    """Variable-media stand-in (2D, float32): M is a seeded smooth random velocity in
+    [cmin, cmax] (in place of the smoothed Marmousi model, which is not available), M_g is
+    M low-passed by the disk |k| <= r N of the FFT grid (N: the larger side), and
+    c = (1 - g/0.4) mean(M) + (g/0.4) M_g, so g = 0 is a uniform medium."""
+    base = w.with_(medium=dict(kind="smooth_random", cmin=cmin, cmax=cmax, corr=corr, seed=seed))
+    M = medium(base).astype(np.float64)
+    nz, nx = M.shape
+    kz = np.fft.fftfreq(nz) * nz
+    kx = np.fft.fftfreq(nx) * nx
+    disk = (kz[:, None] ** 2 + kx[None, :] ** 2) <= (r * max(nz, nx)) ** 2
+    Mg = np.fft.ifft2(np.fft.fft2(M) * disk).real
+    c = (1.0 - gamma / 0.4) * M.mean() + (gamma / 0.4) * Mg
+    return np.ascontiguousarray(c, dtype=np.float64).astype(np.float32)
