@@ -260,6 +260,17 @@ def generalization_run(ns=(1, 2, 4)):
                 out.append({"study": "generalization", "workload": w.name, "trials": kind, "preconditioner": f"R{n}",
                             "p": p, "relative_mse": round(mse, 6), "fit_relres": round(relres, 6),
                             "rank_deficient": deficient})
+    # Kn, fitted on the Krylov pairs of the migrated image of a reflectivity, tested on the
+    # same independent trial functions
+    from paper_1101_3615_amd import inversion as I
+    m = torch.from_numpy(F.reflectivity(w, c, seed=5).astype(np.float64)).to("cuda:0")
+    kys, kxs = I.krylov_pairs(P, P.apply_H(m).clone(), 7)
+    for kind, y_new in (("wavepackets", wp[4]), ("curvelets", cu[4])):
+        for n in (1, 4, 7):
+            for p, mse, relres, deficient in generalization(P, bases, kys[:n], y_new, xs_fit=kxs[:n]):
+                out.append({"study": "generalization", "workload": w.name, "trials": kind, "preconditioner": f"K{n}",
+                            "p": p, "relative_mse": round(mse, 6), "fit_relres": round(relres, 6),
+                            "rank_deficient": deficient})
     return out
 
 

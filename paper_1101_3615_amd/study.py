@@ -38,11 +38,12 @@ def paper_bases(ndim, sizes, order=-1, tl_scale=0.5):
     return out
 
 
-def generalization(problem, bases, ys_fit, y_new):
+def generalization(problem, bases, ys_fit, y_new, xs_fit=None):
     """[(p, relative MSE on y_new, relative residual of the fit, rank deficient), ...]
-    for the preconditioner fitted on ys_fit with each basis (torch tensors on the
-    problem's device)."""
-    xs = [problem.apply_H(y).clone() for y in ys_fit]
+    for the preconditioner fitted on the pairs (ys_fit, H ys_fit), or (ys_fit, xs_fit)
+    when given (Kn: the Krylov pairs of the migrated image), with each basis (torch
+    tensors on the problem's device)."""
+    xs = [problem.apply_H(y).clone() for y in ys_fit] if xs_fit is None else list(xs_fit)
     x_new = problem.apply_H(y_new).clone()
     ref = y_new.to(device=x_new.device).double()
     out = []
