@@ -118,3 +118,46 @@ def test_curvelet_descriptor_validation_and_wedges():
     assert lib.mp_curvelet_wedges(h, ctypes.byref(n), lst.ctypes.data_as(ctypes.POINTER(ctypes.c_int))) == L.MP_OK
     assert [tuple(lst[3 * w:3 * w + 3]) for w in range(n.value)] == C.wedges(4, 8)
     lib.mp_curvelet_destroy(h)
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/matprobe.h compiles as C99 and a C program links against the library and
+    calls its host-only entry points (no GPU needed): the boundary needs no C++ or torch."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        import pytest
+        pytest.skip("no C compiler")
+    names = declared()
+    src = tmp_path / "probe.c"
+    refs = "\n".join(f"  (void *)&{n}," for n in names)
+    src.write_text(f"""#include <stdio.h>
+#include <string.h>
+#include "matprobe.h"
+static void *const every_entry_point[] = {{
+{refs}
+}};
+int main(void) {{
+  mp_curvelet_desc d = {{4, 8, 4, 16, 100, 1e-4}};
+  mp_curvelets *cv = NULL;
+  int n = 0;
+  if (mp_curvelet_create(&d, &cv) != MP_OK) return 1;
+  if (mp_curvelet_wedges(cv, &n, NULL) != MP_OK) return 2;
+  mp_curvelet_destroy(cv);
+  if (mp_create(NULL, NULL, NULL, NULL) != MP_EINVAL) return 3;
+  printf("%d %s %u\\n", n, mp_strerror(MP_ESTATE), (unsigned)(sizeof every_entry_point / sizeof every_entry_point[0]));
+  return 0;
+}}
+""")
+    exe = tmp_path / "probe"
+    libdir = os.path.dirname(LIB)
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                        "-L", libdir, "-lmatprobe", "-Wl,-rpath," + libdir], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    n, rest = r.stdout.split(" ", 1)
+    assert int(n) == 1 + 8 + 8 + 16
+    assert rest.startswith("no background set")
+    assert int(rest.split()[-1]) == len(names)
