@@ -306,6 +306,50 @@ def variable_media_run(gammas=(0.0, 0.1, 0.2, 0.3, 0.4), gd_steps=200, ntrials=5
     return out
 
 
+def eps_rank_run(batch=64, eps=(1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6)):
+    """The 16384 x 16384 normal operator of the 128x128 FP64 workload assembled column by
+    column (apply_H_batch on unit vectors, `batch` columns per sweep): its asymmetry, its
+    smallest eigenvalue relative to the largest, and the eps-rank for a top eigenvalue of 1
+    (the table of Sec. 2.1).  Progress lines go to stderr."""
+    import numpy as np
+    import torch
+
+    import fixtures as F
+    import paper_1101_3615_amd as M
+    w = F.c1()
+    c = F.medium(w)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c).to("cuda:0"))
+    n = w.model_cells
+    H = np.empty((n, n))
+    shots = list(range(w.ns))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j0 in range(0, n, batch):
+        nb = min(batch, n - j0)
+        dms = []
+        for k in range(nb):
+            e = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+            e[j0 + k] = 1.0
+            dms.append(e.view(w.model_shape))
+        outs = P.apply_H_batch(dms, [shots] * nb)
+        H[:, j0:j0 + nb] = torch.stack([o.reshape(-1) for o in outs], 1).cpu().numpy()
+        if (j0 // batch) % 32 == 0:
+            print(f"eps-rank: {j0 + nb} of {n} columns, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    t_assemble = time.perf_counter() - t0
+    asym = float(np.linalg.norm(H - H.T) / np.linalg.norm(H))
+    Hs = torch.from_numpy(0.5 * (H + H.T)).to("cuda:0")
+    del H
+    t1 = time.perf_counter()
+    ev = torch.linalg.eigvalsh(Hs).cpu().numpy()[::-1]
+    t_eig = time.perf_counter() - t1
+    top = float(ev[0])
+    return {"study": "eps_rank", "workload": w.name, "n": n, "assemble_s": round(t_assemble, 1),
+            "eig_s": round(t_eig, 1), "asymmetry": float(f"{asym:.3g}"),
+            "min_eig_rel": float(f"{float(ev[-1]) / top:.3g}"),
+            "eps_rank": {f"{e:g}": int(np.sum(ev / top > e)) for e in eps}}
+
+
 def curvelet_run(reps=3):
     """Curvelet trial synthesis and the ray-traced illumination mask on the 512x256 workload
     (FP32): device time per call and the mask's visible fraction."""
@@ -496,6 +540,9 @@ def main():
     ap.add_argument("--variable-media", action="store_true",
                     help="only run the variable-media study (R5 on backgrounds blended from uniform to smooth "
                          "variable, 128x128 FP64 workload) and print one JSON line per fit")
+    ap.add_argument("--eps-rank", action="store_true",
+                    help="only assemble the 16384 x 16384 normal operator of the 128x128 FP64 workload and print "
+                         "its symmetry, definiteness and eps-rank profile")
     ap.add_argument("--curvelets", action="store_true",
                     help="only time the curvelet trial synthesis and the ray-traced illumination mask on the "
                          "512x256 workload and print one JSON line")
@@ -534,6 +581,9 @@ def main():
         return
     if args.curvelets:
         print(json.dumps(curvelet_run()), flush=True)
+        return
+    if args.eps_rank:
+        print(json.dumps(eps_rank_run()), flush=True)
         return
     if args.variable_media:
         for rec in variable_media_run():

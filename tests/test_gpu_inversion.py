@@ -161,3 +161,30 @@ def test_gauss_newton_probed_steps_match_oracle():
     print("GN K1-step misfits", Js, Js_ref)
     assert Js[2] < Js[0]
     _compare_runs(c0, cs, Js, cs_ref, Js_ref)
+
+
+def test_assembled_normal_operator_is_symmetric_psd():
+    """H assembled column by column (apply_H_batch on unit vectors, 32 x 32 FP64 grid) is
+    symmetric to rounding and positive semi-definite: F* is the exact transpose of F."""
+    M = _gpu()
+    w = F.tiny(n=32, nr=32, nt=150, dtype="f64", kind="smooth")
+    c = F.medium(w)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c))
+    n = w.model_cells
+    cols = []
+    for j0 in range(0, n, 128):
+        dms = []
+        for k in range(j0, min(n, j0 + 128)):
+            e = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+            e[k] = 1.0
+            dms.append(e.view(w.model_shape))
+        cols += [o.reshape(-1).cpu().numpy() for o in P.apply_H_batch(dms, [list(range(w.ns))] * len(dms))]
+    H = np.stack(cols, 1)
+    assert np.linalg.norm(H - H.T) <= 1e-13 * np.linalg.norm(H)
+    ev = np.linalg.eigvalsh(0.5 * (H + H.T))
+    assert ev[0] >= -1e-13 * ev[-1]
+    # a column equals apply_H of that unit vector
+    e = torch.zeros(n, dtype=torch.float64)
+    e[77] = 1.0
+    np.testing.assert_array_equal(P.apply_H(e.view(w.model_shape)).reshape(-1).cpu().numpy(), H[:, 77])
