@@ -412,13 +412,14 @@ def gauss_newton_records(P, w, c, refl, basis, trial, outer=3, inner=5):
         return I.preconditioner(problem, basis, coef)
 
     out = []
-    for name, pre, cg in (("none", None, inner), ("K1", k1, inner), ("K1", k1, 0), ("R1", r1, 0)):
+    for name, pre, cg, ls in (("none", None, inner, False), ("K1", k1, inner, False), ("K1", k1, 0, False),
+                              ("R1", r1, 0, False), ("K1", k1, 0, True), ("R1", r1, 0, True)):
         torch.cuda.synchronize()
         t = time.perf_counter()
         rec = {"study": "gauss_newton", "workload": w.name, "preconditioner": name, "p": basis.p, "outer": outer,
-               "inner_cg": cg}
+               "inner_cg": cg, "line_search": ls}
         try:
-            cs, Js = I.gauss_newton(P, c0, d_obs, outer, cg, precond_at=pre)
+            cs, Js = I.gauss_newton(P, c0, d_obs, outer, cg, precond_at=pre, line_search=ls)
         except ValueError as e:   # a step that leaves m = 1/c^2 non-positive
             out.append(dict(rec, error=str(e)))
             continue

@@ -84,7 +84,7 @@ def misfit(P, c, d_obs):
     return r, 0.5 * float(np.sum(r * r))
 
 
-def gauss_newton(problem_at, c0, d_obs, outer, inner, precond_at=None):
+def gauss_newton(problem_at, c0, d_obs, outer, inner, precond_at=None, line_search=False):
     """Gauss-Newton iterations on J[m] = 1/2 ||d - F[m]||^2 over m = 1/c^2 (Sec. 1.1).
 
     At c_k (problem_at(c_k) gives the operators linearised there): residual data
@@ -93,7 +93,8 @@ def gauss_newton(problem_at, c0, d_obs, outer, inner, precond_at=None):
     (preconditioned by precond_at(P, b) when given; b = F* r lets it fit Kn).  With
     inner = 0 the step is the preconditioner applied to the migrated residual,
     dm = P F* r: the fitted inverse in place of H^-1, as Sec. 2.2 describes for the
-    iterations after the first.
+    iterations after the first; with line_search the step is scaled to minimise the
+    quadratic model 1/2 dm.H dm - b.dm along it: alpha = dm.b / dm.H dm.
     m_{k+1} = m_k + dm on the model grid, c_{k+1} = m_{k+1}^(-1/2).  Returns the velocity
     iterates and the misfits J(c_k), the last one at the final velocity."""
     c = np.asarray(c0, dtype=np.float64)
@@ -105,6 +106,8 @@ def gauss_newton(problem_at, c0, d_obs, outer, inner, precond_at=None):
         b = P.apply_Fadj(r)
         if inner == 0:
             dm = precond_at(P, b)(b)
+            if line_search:
+                dm = dm * (float(np.sum(dm * b)) / float(np.sum(dm * P.apply_H(dm))))
         else:
             M = None if precond_at is None else precond_at(P, b)
             dm, _ = conjugate_gradient(P.apply_H, b, inner, precond=M)

@@ -100,14 +100,16 @@ def misfit(problem, d_obs):
     return r, 0.5 * problem.dot(r, r)
 
 
-def gauss_newton(problem, c0, d_obs, outer, inner, precond_at=None):
+def gauss_newton(problem, c0, d_obs, outer, inner, precond_at=None, line_search=False):
     """Gauss-Newton on J[m] = 1/2 ||d - F[m]||^2 over m = 1/c^2 (Sec. 1.1).
 
     At c_k: r = d - F[m_k] (nonlinear modelling), the migrated residual b = F* r
     (minus the gradient of J), the step dm from `inner` CG iterations on H dm = b
     (preconditioned by precond_at(problem, b), a probed inverse fitted at c_k: Rn, or Kn
     on the Krylov pairs of b), or with inner = 0 the preconditioner applied to b (the
-    fitted inverse in place of H^-1, Sec. 2.2); m_{k+1} = m_k + dm, c_{k+1} = m_{k+1}^(-1/2)
+    fitted inverse in place of H^-1, Sec. 2.2), scaled with line_search by
+    alpha = dm.b / dm.H dm (the minimum of the quadratic model along it);
+    m_{k+1} = m_k + dm, c_{k+1} = m_{k+1}^(-1/2)
     (in the library's kernel, which refuses a step that makes m non-positive).  Leaves the
     problem's background at the last iterate; returns the velocity iterates and the
     misfits J(c_k)."""
@@ -121,6 +123,9 @@ def gauss_newton(problem, c0, d_obs, outer, inner, precond_at=None):
         b = problem.apply_Fadj(r)
         if inner == 0:
             dm = precond_at(problem, b)(b)
+            if line_search:
+                alpha = problem.dot(dm, b) / problem.dot(dm, problem.apply_H(dm))
+                problem.axpby(0.0, dm, alpha, dm)
         else:
             dm, _ = conjugate_gradient(problem, b, inner,
                                        precond=None if precond_at is None else precond_at(problem, b))

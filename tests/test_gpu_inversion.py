@@ -140,7 +140,8 @@ def test_gauss_newton_matches_oracle():
 
 def test_gauss_newton_probed_steps_match_oracle():
     """Two steps dm = P F* r with P a K1 probed inverse refitted at every iterate on the
-    pair (b, H b) of the migrated residual b (the paper's expansion with p = 4)."""
+    pair (b, H b) of the migrated residual b (the paper's expansion with p = 4), without
+    and with the line search along dm."""
     M = _gpu()
     from paper_1101_3615_amd import inversion as I
     from paper_1101_3615_amd.study import paper_bases
@@ -156,11 +157,13 @@ def test_gauss_newton_probed_steps_match_oracle():
         coef, _, _ = I.fit_krylov(Q, B, b, 1)
         return I.preconditioner(Q, B, coef)
 
-    cs_ref, Js_ref = OI.gauss_newton(lambda c: Oracle(w, c), c0, d_ref, 2, 0, precond_at=oracle_k1)
-    cs, Js = I.gauss_newton(P, torch.from_numpy(c0), d_obs, 2, 0, precond_at=gpu_k1)
-    print("GN K1-step misfits", Js, Js_ref)
-    assert Js[2] < Js[0]
-    _compare_runs(c0, cs, Js, cs_ref, Js_ref)
+    for ls in (False, True):
+        cs_ref, Js_ref = OI.gauss_newton(lambda c: Oracle(w, c), c0, d_ref, 2, 0, precond_at=oracle_k1,
+                                         line_search=ls)
+        cs, Js = I.gauss_newton(P, torch.from_numpy(c0), d_obs, 2, 0, precond_at=gpu_k1, line_search=ls)
+        print("GN K1-step misfits (line search %s)" % ls, Js, Js_ref)
+        assert Js[2] < Js[0]
+        _compare_runs(c0, cs, Js, cs_ref, Js_ref)
 
 
 def test_assembled_normal_operator_is_symmetric_psd():

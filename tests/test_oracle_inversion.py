@@ -124,3 +124,18 @@ def test_gauss_newton_without_inner_iterations_applies_the_preconditioner():
                               precond_at=lambda Q, b: (lambda v: I.conjugate_gradient(Q.apply_H, v, 3)[0]))
     np.testing.assert_array_equal(cs0[1], cs3[1])
     assert Js0 == Js3
+
+
+def test_gauss_newton_line_search_step():
+    """inner = 0 with line_search: the step minimises the quadratic model along the
+    preconditioned direction; with the identity as preconditioner that is one exact
+    steepest-descent step on H dm = b."""
+    w, c0, at = _tiny_wave()
+    P = at(1.0 / np.sqrt(1.0 / c0 ** 2 + _blob(w, c0, 0.03)))
+    d_obs = P.model_data(1.0 / P.c_pad ** 2)
+    c0 = c0.astype(np.float64)
+    cs, _ = I.gauss_newton(at, c0, d_obs, 1, 0, precond_at=lambda Q, b: (lambda v: v), line_search=True)
+    Q = at(c0)
+    b = Q.apply_Fadj(I.misfit(Q, c0, d_obs)[0])
+    dm = I.steepest_descent(Q.apply_H, b, 1)
+    np.testing.assert_allclose(1.0 / cs[1] ** 2 - 1.0 / c0 ** 2, dm, rtol=1e-9, atol=1e-9 * np.abs(dm).max())
