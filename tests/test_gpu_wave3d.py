@@ -126,3 +126,43 @@ def test_3d_repeatable(snap, k):
         assert np.array_equal(P.apply_F(dm).cpu().numpy(), first)
     h = P.apply_H(dm).cpu().numpy()
     assert np.array_equal(P.apply_H(dm).cpu().numpy(), h)
+
+
+def test_c5_reduced_parity():
+    """The 256^3 workload's configuration (FP32 fields, BF16 checkpoints every 8 steps, nb 20,
+    its medium and surface acquisition) on a 48^3 model, 200 steps, two shots: apply_H
+    against the FP64 oracle within the BF16 bound (1e-2)."""
+    M = _gpu()
+    w5 = F.c5()
+    r = np.arange(2, 48, 4)
+    rx, ry = np.meshgrid(r, r)
+    w = w5.with_(nx=48, ny=48, nz=48, nt=200,
+                 src=np.array([[12, 12, 0], [36, 30, 0]], np.int32),
+                 rec=np.stack([rx.ravel(), ry.ravel(), np.zeros(rx.size, int)], 1).astype(np.int32))
+    c = F.medium(w)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c))
+    y = F.normal_field(w.model_shape, 57)
+    got = P.apply_H(torch.from_numpy(y)).cpu().numpy()
+    err = rel(got, Oracle(w, c).apply_H(y))
+    print(f"48^3 BF16 ckpt/8: apply_H rel L2 vs FP64 oracle = {err:.3e}")
+    assert err <= 1e-2
+
+
+def test_c5_full_size_dot_product():
+    """At the full 256^3 spatial size (296^3 propagation grid), two shots and 40 steps with
+    FP32 fields: <F m, d> = <m, F* d> to FP32 rounding."""
+    M = _gpu()
+    w = F.c5()
+    w = w.with_(nt=40, snap="full", ckpt_every=0, src=np.asarray(w.src)[:2])
+    c = F.medium(w)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c))
+    m = torch.from_numpy(F.normal_field(w.model_shape, 55))
+    d = torch.from_numpy(F.normal_field((w.ns, w.nt, w.nr), 56))
+    Fm = P.apply_F(m).double()
+    lhs = float((Fm * d.to(Fm.device).double()).sum())
+    Fd = P.apply_Fadj(d).double()
+    rhs = float((m.to(Fd.device).double() * Fd).sum())
+    print(f"256^3 dot product: {abs(lhs - rhs) / abs(lhs):.3e}")
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
