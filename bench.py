@@ -652,6 +652,18 @@ def main():
             lst.append((time.perf_counter() - t1) * 1e3)
     P.stats()
     P.release_cache()
+    # a plain device copy of 1 GiB on the same GPU: the practical bandwidth ceiling
+    src_buf = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst_buf = torch.empty_like(src_buf)
+    dst_buf.copy_(src_buf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst_buf.copy_(src_buf)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 4 * (1 << 28) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src_buf, dst_buf
     serving = serve_leg(args.serve_seconds) if (args.serve_seconds > 0 and not args.profile_steps) else None
     ms_per_step = 1e3 * wall / args.steps
     cell_steps = len(ys) * w.cell_steps
@@ -694,6 +706,7 @@ def main():
                    "apply_H_cell_steps_per_step": cell_steps},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": kind,
+                     "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                      "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 3),
                      "steps_per_launch": round(spl, 3)},
         "cpu_baseline": cpu,
