@@ -191,3 +191,48 @@ def test_assembled_normal_operator_is_symmetric_psd():
     e = torch.zeros(n, dtype=torch.float64)
     e[77] = 1.0
     np.testing.assert_array_equal(P.apply_H(e.view(w.model_shape)).reshape(-1).cpu().numpy(), H[:, 77])
+
+
+def test_solvers_and_gauss_newton_3d_match_oracle():
+    """The same solvers on a 16^3 FP64 cube (power-of-two model for the 3D multipliers):
+    preconditioned CG with a K1 fit of the paper's 3D expansion, and one Gauss-Newton step."""
+    M = _gpu()
+    from paper_1101_3615_amd import inversion as I
+    from paper_1101_3615_amd.study import paper_bases
+    from fixtures.configs import Workload
+    rx, ry = np.meshgrid(np.arange(1, 16, 3), np.arange(1, 16, 3))
+    w = Workload(name="cube16", ndim=3, nx=16, ny=16, nz=16, h=12.5, nb=4, dt=1.0e-3, nt=60, f_peak=20.0,
+                 src=np.array([[5, 6, 0], [11, 9, 0]], np.int32),
+                 rec=np.stack([rx.ravel(), ry.ravel(), np.zeros(rx.size, int)], 1).astype(np.int32),
+                 dtype="f64", snap="full", ckpt_every=0,
+                 medium=dict(kind="smooth_random", cmin=1800.0, cmax=2400.0, corr=50.0, seed=43))
+    c0 = F.medium(w).astype(np.float64)
+    O = Oracle(w, c0)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(c0))
+    m = F.normal_field(w.model_shape, 71, np.float64) * 1e-8
+    b_ref = O.apply_H(m)
+    b = P.apply_H(torch.from_numpy(m))
+    assert rel(b.cpu().numpy(), b_ref) <= 1e-10
+    (B,) = paper_bases(3, [(0, 1, 1)])
+    basis = lambda v: S.apply_paper_basis(v, w.h, B.modes, B.mults, B.order, B.tl_scale)
+    c_ref, _, _ = S.fit_with(basis, [b_ref], [O.apply_H(b_ref)])
+    ck, _, _ = I.fit_krylov(P, B, b, 1)
+    assert rel(ck, c_ref) <= TOL
+    prec_ref = lambda v: np.tensordot(c_ref, basis(v), axes=1)
+    xo, no = OI.conjugate_gradient(O.apply_H, b_ref, 3, precond=prec_ref)
+    xg, ng = I.conjugate_gradient(P, b, 3, precond=I.preconditioner(P, B, ck))
+    print("3D PCG", rel(xg.cpu().numpy(), xo), rel(ng, no))
+    assert rel(xg.cpu().numpy(), xo) <= TOL and rel(ng, no) <= TOL
+    # one Gauss-Newton step with two CG iterations
+    m_true = 1.0 / c0 ** 2 + 0.02 * F.normal_field(w.model_shape, 72, np.float64) / float(np.mean(c0)) ** 2
+    c_true = 1.0 / np.sqrt(m_true)
+    Ot = Oracle(w, c_true)
+    d_ref = Ot.model_data(1.0 / Ot.c_pad ** 2)
+    P.set_background(torch.from_numpy(c_true))
+    d_obs = P.model()
+    assert rel(d_obs.cpu().numpy(), d_ref) <= 1e-10
+    cs_ref, Js_ref = OI.gauss_newton(lambda c: Oracle(w, c), c0, d_ref, 1, 2)
+    cs, Js = I.gauss_newton(P, torch.from_numpy(c0), d_obs, 1, 2)
+    print("3D GN", Js, Js_ref)
+    _compare_runs(c0, cs, Js, cs_ref, Js_ref)
