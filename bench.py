@@ -481,9 +481,19 @@ def inversion_run(gd_steps=200, cg_iters=20):
     mig = [P.apply_Fadj(torch.from_numpy(F.normal_field(P.data_shape, 900 + s, np.float64)).to("cuda:0")).clone()
            for s in range(4)]
     Hmig = [P.apply_H(y) for y in mig]
+    # H-applied noise whose curvelet coefficients are set to their sign above a small
+    # threshold (a tenth of their RMS) and to zero below it, resynthesised with the atom norms
+    thr = []
+    for y in Hwhite:
+        coef = cv.analysis(y)
+        rms = (P.dot(coef, coef) / coef.numel()) ** 0.5
+        cv.sign_threshold(coef, 0.1 * rms)
+        thr.append(cv.synthesis(coef, None, cv.norms()).clone())
+    Hthr = [P.apply_H(y) for y in thr]
     fits = {"R1": (trials[:1], Htrials[:1]), "R4": (trials, Htrials),
             "R1c": (ctrials[:1], Hctrials[:1]), "R4c": (ctrials, Hctrials),
-            "R4w": (white, Hwhite), "R4Hw": (Hwhite, HHwhite), "R4d": (mig, Hmig), "Rtrue": ([m], [b]),
+            "R4w": (white, Hwhite), "R4Hw": (Hwhite, HHwhite), "R4d": (mig, Hmig), "R4t": (thr, Hthr),
+            "Rtrue": ([m], [b]),
             "K1": (kys[:1], kxs[:1]), "K2": (kys[:2], kxs[:2]), "K4": (kys, kxs)}
     bases = paper_bases(2, GEN_SIZES)
     precs = {}

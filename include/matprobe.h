@@ -303,6 +303,11 @@ int mp_illumination(mp_ctx* ctx, const mp_curvelets* cv, const void* c_dev, unsi
 int mp_curvelet_synthesis(mp_ctx* ctx, const mp_curvelets* cv, const void* coef_dev, const unsigned char* mask_dev,
                           const double* weights, void* out_dev, void* stream);
 
+/* In place on a coefficient array: c <- sign(c) where |c| >= threshold, 0 elsewhere (the
+ * magnitudes set to one or to zero, the signs kept: the thresholded trial functions of
+ * Sec. 2.4).  MP_EINVAL for a negative or non-finite threshold. */
+int mp_curvelet_sign_threshold(mp_ctx* ctx, const mp_curvelets* cv, void* coef_dev, double threshold, void* stream);
+
 /* coef_dev[w] = IFFT(U_w FFT img_dev): the curvelet coefficients of an image at every
  * grid position (the adjoint of the synthesis, and its inverse on the frame's range). */
 int mp_curvelet_analysis(mp_ctx* ctx, const mp_curvelets* cv, const void* img_dev, void* coef_dev, void* stream);

@@ -33,7 +33,8 @@ EXPORTS = [
     "mp_apply_Fadj", "mp_apply_H", "mp_apply_H_batch", "mp_release_cache", "mp_basis_create",
     "mp_basis_destroy", "mp_probe_fit", "mp_apply_Hinv", "mp_last_stats", "mp_strerror",
     "mp_last_error", "mp_curvelet_create", "mp_curvelet_destroy", "mp_curvelet_wedges", "mp_curvelet_norms",
-    "mp_illumination", "mp_curvelet_synthesis", "mp_curvelet_analysis", "mp_vec_dot", "mp_vec_axpby",
+    "mp_illumination", "mp_curvelet_synthesis", "mp_curvelet_analysis", "mp_curvelet_sign_threshold",
+    "mp_vec_dot", "mp_vec_axpby",
     "mp_velocity_update",
 ]
 
@@ -129,6 +130,7 @@ def lib():
     L.mp_illumination.argtypes = [vp, vp, vp, vp, vp]
     L.mp_curvelet_synthesis.argtypes = [vp, vp, vp, vp, dp, vp, vp]
     L.mp_curvelet_analysis.argtypes = [vp, vp, vp, vp, vp]
+    L.mp_curvelet_sign_threshold.argtypes = [vp, vp, vp, ctypes.c_double, vp]
     L.mp_vec_dot.argtypes = [vp, ctypes.c_longlong, vp, vp, dp, vp]
     L.mp_vec_axpby.argtypes = [vp, ctypes.c_longlong, ctypes.c_double, vp, ctypes.c_double, vp, vp]
     L.mp_velocity_update.argtypes = [vp, vp, vp, vp]

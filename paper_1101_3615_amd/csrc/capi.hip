@@ -413,6 +413,14 @@ int mp_curvelet_analysis(mp_ctx* ctx, const mp_curvelets* cv, const void* img_de
   return finish(ctx, curvelet_analysis(ctx, cv->cv, img_dev, coef_dev, (hipStream_t)stream));
 }
 
+int mp_curvelet_sign_threshold(mp_ctx* ctx, const mp_curvelets* cv, void* coef_dev, double threshold, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!cv || !coef_dev) return fail(MP_EINVAL, "null argument");
+  if (!(threshold >= 0.0) || !std::isfinite(threshold)) return fail(MP_EINVAL, "threshold must be finite and >= 0");
+  return finish(ctx, curvelet_sign_threshold(ctx, cv->cv, coef_dev, threshold, (hipStream_t)stream));
+}
+
 int mp_vec_dot(mp_ctx* ctx, long long n, const void* a_dev, const void* b_dev, double* out, void* stream) {
   int rc = guard(ctx);
   if (rc) return rc;

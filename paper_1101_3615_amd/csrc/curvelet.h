@@ -25,6 +25,7 @@ int curvelet_synthesis(mp_ctx* ctx, const Curvelets& cv, const void* coef, const
                        const double* weights, void* out, hipStream_t s);
 int curvelet_analysis(mp_ctx* ctx, const Curvelets& cv, const void* img, void* coef, hipStream_t s);
 int curvelet_illumination(mp_ctx* ctx, const Curvelets& cv, const void* c, unsigned char* mask, hipStream_t s);
+int curvelet_sign_threshold(mp_ctx* ctx, const Curvelets& cv, void* coef, double t, hipStream_t s);
 void curvelet_release(mp_ctx* ctx);
 
 }  // namespace mp

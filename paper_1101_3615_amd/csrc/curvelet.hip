@@ -204,6 +204,15 @@ __global__ void k_cv_to_complex(Cx2<T>* out, const T* in, long long n) {
     out[i] = {in[i], T(0)};
 }
 
+// coef <- sign(coef) where |coef| >= t, 0 elsewhere (magnitudes to one, signs kept)
+template <typename T>
+__global__ void k_cv_sign(T* coef, long long n, double t) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double v = (double)coef[i];
+    coef[i] = (T)(fabs(v) >= t ? (v > 0.0 ? 1.0 : -1.0) : 0.0);
+  }
+}
+
 // medium tables: c (FP64) and its centred-difference gradient, one-sided at the edges
 template <typename T>
 __global__ void k_cv_medium(double* c, double* gx, double* gz, const T* cin, int nx, int nz, double h) {
@@ -636,6 +645,18 @@ int curvelet_illumination(mp_ctx* ctx, const Curvelets& cv, const void* c, unsig
   if (rc) return rc;
   if (ctx->cfg.dtype == MP_F32) return illum_t<float>(ctx, cv, c, mask, s);
   return illum_t<double>(ctx, cv, c, mask, s);
+}
+
+int curvelet_sign_threshold(mp_ctx* ctx, const Curvelets& cv, void* coef, double t, hipStream_t s) {
+  int rc = check_cv(ctx, cv);
+  if (rc) return rc;
+  const long long n = (long long)cv_wedges(cv.nscales, cv.nangles).size() / 3 * ctx->cfg.nx * ctx->cfg.nz;
+  if (ctx->cfg.dtype == MP_F32)
+    hipLaunchKernelGGL(k_cv_sign<float>, cgrid(n), dim3(256), 0, s, static_cast<float*>(coef), n, t);
+  else
+    hipLaunchKernelGGL(k_cv_sign<double>, cgrid(n), dim3(256), 0, s, static_cast<double*>(coef), n, t);
+  CV_LAUNCH();
+  return MP_OK;
 }
 
 void curvelet_release(mp_ctx* ctx) {

@@ -90,6 +90,15 @@ class Curvelets:
         L.check(self._lib.mp_curvelet_analysis(self.problem._ctx, self._h, _ptr(img), _ptr(o), _stream(stream)))
         return o
 
+    def sign_threshold(self, coef, threshold, stream=None):
+        """In place: coefficients of magnitude >= threshold become their sign, the rest 0."""
+        coef = self._coef(coef) if not (isinstance(coef, torch.Tensor) and coef.is_cuda) else coef
+        if tuple(coef.shape) != self.coef_shape or coef.dtype != self.problem.torch_dtype or not coef.is_contiguous():
+            raise ValueError(f"coefficients must be a contiguous {self.problem.torch_dtype} array {self.coef_shape}")
+        L.check(self._lib.mp_curvelet_sign_threshold(self.problem._ctx, self._h, _ptr(coef), float(threshold),
+                                                     _stream(stream)))
+        return coef
+
     def trial(self, z, mask, sigma=1.0, stream=None):
         """Randomized curvelet trial function: coefficients sigma ||phi_w|| z on the mask."""
         return self.synthesis(z, mask, sigma * self.norms(stream), stream=stream)

@@ -160,3 +160,20 @@ def test_error_paths():
     assert e.value.code == -5
     with pytest.raises(ValueError):
         cq.synthesis(torch.zeros(3, 32, 64))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sign_threshold(dtype):
+    M, Curvelets = _gpu()
+    w = _wl(dtype, 32, 64, [16, 48], list(range(0, 64, 4)))
+    P = M.Problem.from_spec(w)
+    cv = Curvelets(P, nscales=3, nangles=4)
+    npdt = np.float64 if dtype == "f64" else np.float32
+    z = F.normal_field(cv.coef_shape, 91, npdt)
+    t = torch.from_numpy(z).cuda()
+    cv.sign_threshold(t, 0.5)
+    zz = z.astype(np.float64)
+    ref = np.where(np.abs(zz) >= 0.5, np.sign(zz), 0.0)
+    assert np.array_equal(t.cpu().numpy().astype(np.float64), ref)
+    with pytest.raises(M.MatprobeError):
+        cv.sign_threshold(t, -1.0)
