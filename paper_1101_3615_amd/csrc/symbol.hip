@@ -482,45 +482,59 @@ __global__ __launch_bounds__(256) void k_qupdate(double* A, long long lda, long 
 }
 
 // One-sided Jacobi SVD of the p x p matrix in X (row-major, ld MAXP): on exit
-// the columns of X are U Sigma, V (ld MAXP) the right singular vectors.
+// the columns of X are U Sigma, V (ld MAXP) the right singular vectors.  Parallel
+// (round-robin) ordering: each sweep is P - 1 rounds (P = p rounded up to even) of
+// P/2 disjoint column pairs, one group of 8 threads per pair; a pair with the padding
+// index p (odd p) is skipped.  One barrier per round.
 __device__ void jacobi_svd(double* X, double* V, int p) {
   __shared__ int rot;
   for (int t = threadIdx.x; t < p * p; t += blockDim.x) V[t / p * MAXP + t % p] = (t / p == t % p) ? 1.0 : 0.0;
   __syncthreads();
+  const int P = (p + 1) & ~1;
+  const int grp = threadIdx.x >> 3, gl = threadIdx.x & 7;   // 32 groups of 8 (blockDim 256)
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (threadIdx.x == 0) rot = 0;
     __syncthreads();
-    for (int i = 0; i < p - 1; ++i) {
-      for (int j = i + 1; j < p; ++j) {
-        __shared__ double al, be, ga;
-        if (threadIdx.x == 0) {
-          double a = 0, b = 0, g = 0;
-          for (int k = 0; k < p; ++k) {
-            a += X[k * MAXP + i] * X[k * MAXP + i];
-            b += X[k * MAXP + j] * X[k * MAXP + j];
-            g += X[k * MAXP + i] * X[k * MAXP + j];
-          }
-          al = a; be = b; ga = g;
+    for (int r = 0; r < P - 1; ++r) {
+      for (int k = grp; k < P / 2; k += (int)(blockDim.x >> 3)) {
+        // circle method: element 0 fixed, 1 .. P-1 rotate by r
+        const int ka = k, kb = P - 1 - k;
+        const int ea = (ka == 0) ? 0 : 1 + (ka - 1 + r) % (P - 1);
+        const int eb = (kb == 0) ? 0 : 1 + (kb - 1 + r) % (P - 1);
+        const int i = min(ea, eb), j = max(ea, eb);
+        if (j >= p) continue;                                  // the padding column (group-uniform)
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int q = gl; q < p; q += 8) {
+          const double xi = X[q * MAXP + i], xj = X[q * MAXP + j];
+          a += xi * xi;
+          b += xj * xj;
+          g += xi * xj;
         }
-        __syncthreads();
-        if (fabs(ga) > 1e-15 * sqrt(al * be) && ga != 0.0) {
-          const double zeta = (be - al) / (2.0 * ga);
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+          a += __shfl_xor(a, o);
+          b += __shfl_xor(b, o);
+          g += __shfl_xor(g, o);
+        }
+        if (fabs(g) > 1e-15 * sqrt(a * b) && g != 0.0) {
+          const double zeta = (b - a) / (2.0 * g);
           const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-          for (int k = threadIdx.x; k < p; k += blockDim.x) {
-            const double xi = X[k * MAXP + i], xj = X[k * MAXP + j];
-            X[k * MAXP + i] = cs * xi - sn * xj;
-            X[k * MAXP + j] = sn * xi + cs * xj;
-            const double vi = V[k * MAXP + i], vj = V[k * MAXP + j];
-            V[k * MAXP + i] = cs * vi - sn * vj;
-            V[k * MAXP + j] = sn * vi + cs * vj;
+          for (int q = gl; q < p; q += 8) {
+            const double xi = X[q * MAXP + i], xj = X[q * MAXP + j];
+            X[q * MAXP + i] = cs * xi - sn * xj;
+            X[q * MAXP + j] = sn * xi + cs * xj;
+            const double vi = V[q * MAXP + i], vj = V[q * MAXP + j];
+            V[q * MAXP + i] = cs * vi - sn * vj;
+            V[q * MAXP + j] = sn * vi + cs * vj;
           }
-          if (threadIdx.x == 0) rot = 1;
+          if (gl == 0) rot = 1;
         }
-        __syncthreads();
       }
+      __syncthreads();
     }
     if (!rot) break;
+    __syncthreads();
   }
 }
 
