@@ -243,7 +243,8 @@ int mp_apply_Hinv(mp_ctx* ctx, const mp_basis* basis, const double* c, const voi
 int mp_vec_dot(mp_ctx* ctx, long long n, const void* a_dev, const void* b_dev, double* out, void* stream);
 
 /* y = alpha x + beta y, computed in FP64 and rounded to the field precision (x and y may
- * be the same buffer).  MP_ENUMERIC for a non-finite alpha or beta. */
+ * be the same buffer).  With beta = 0, y is overwritten and not read, so it may hold
+ * anything (NaN included).  MP_ENUMERIC for a non-finite alpha or beta. */
 int mp_vec_axpby(mp_ctx* ctx, long long n, double alpha, const void* x_dev, double beta, void* y_dev, void* stream);
 
 /* The Gauss-Newton model update on the model grid: m = c^-2 + dm, c <- m^(-1/2) (c_dev

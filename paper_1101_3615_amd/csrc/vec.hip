@@ -54,10 +54,12 @@ __global__ __launch_bounds__(VB) void k_dot_final(const double* partial, double*
   if (threadIdx.x == 0) out[0] = s[0];
 }
 
+// beta == 0 overwrites y without reading it (what y held, NaN included, does not matter)
 template <typename T>
 __global__ void k_axpby(long long n, double alpha, const T* x, double beta, T* y) {
+  const bool read_y = beta != 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    y[i] = (T)(alpha * (double)x[i] + beta * (double)y[i]);
+    y[i] = (T)(read_y ? alpha * (double)x[i] + beta * (double)y[i] : alpha * (double)x[i]);
 }
 
 // count of cells where c^-2 + dm <= 0 or is not finite

@@ -168,7 +168,8 @@ class Problem:
         return out.value
 
     def axpby(self, alpha, x, beta, y, stream=None):
-        """y = alpha x + beta y in place (FP64 arithmetic, rounded to the field precision)."""
+        """y = alpha x + beta y in place (FP64 arithmetic, rounded to the field precision);
+        beta = 0 overwrites y without reading it."""
         x, y = self._vec(x, "x"), self._vec(y, "y")
         if x.numel() != y.numel():
             raise ValueError("axpby of vectors of different sizes")

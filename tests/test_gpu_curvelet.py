@@ -67,6 +67,30 @@ def test_frame_matches_oracle(dtype, shape):
     assert rel(y, C.trial(zt, U, mask, 1.5)) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("shape,dtype", [((1024, 1024), "f32"), ((4, 1024), "f64"), ((1024, 8), "f64")])
+def test_frame_extreme_sizes(shape, dtype):
+    """The largest grid the frame accepts and the thinnest ones: analysis against the
+    oracle, and on the GPU alone the tight frame (synthesis of the analysis is the
+    identity) and Parseval (the coefficients carry the image's energy)."""
+    M, Curvelets = _gpu()
+    nz, nx = shape
+    w = _wl(dtype, nz, nx, [nx // 4, 3 * nx // 4], list(range(0, nx, 4)))
+    P = M.Problem.from_spec(w)
+    J, A1 = 5, 8
+    cv = Curvelets(P, nscales=J, nangles=A1)
+    U = C.windows(nz, nx, J, A1)
+    assert cv.coef_shape == U.shape
+    np.testing.assert_allclose(cv.norms(), C.atom_norms(U), rtol=1e-13)
+    f = F.normal_field(shape, 34, np.float64)
+    ft = f.astype(np.float32).astype(np.float64) if dtype == "f32" else f
+    coef = cv.analysis(torch.from_numpy(f))
+    got = coef.cpu().numpy()
+    assert rel(got, C.analysis(ft, U)) <= TOL[dtype]
+    assert rel(cv.synthesis(coef).cpu().numpy(), ft) <= TOL[dtype]
+    energy = float(np.sum(got.astype(np.float64) ** 2))
+    assert abs(energy - float(np.sum(ft ** 2))) <= 2 * TOL[dtype] * float(np.sum(ft ** 2))
+
+
 def _bracketed(got, c, h, src, rec, J, A1, stride, nfan, nz, nx, rtol=1e-4):
     cross = C.ray_crossings(c, h, src, rec, J, A1, stride, nfan, rtol)
     nn = (C.mask_nodes(nz, stride).size, C.mask_nodes(nx, stride).size)

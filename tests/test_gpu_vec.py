@@ -47,6 +47,10 @@ def test_axpby(dtype):
     terms = 0.75 * np.abs(x.astype(np.float64)) + 1.25 * np.abs(y.astype(np.float64))
     rnd = 0.0 if dtype == "f64" else 6e-8
     assert np.all(np.abs(got - ref) <= 4e-16 * terms + rnd * np.abs(ref))
+    # beta = 0 overwrites y without reading it
+    tz = torch.full_like(tx, float("nan"))
+    P.axpby(-0.5, tx, 0.0, tz)
+    assert torch.equal(tz, (-0.5 * tx.double()).to(tx.dtype))
     with pytest.raises(M.MatprobeError) as e:
         P.axpby(float("nan"), tx, 1.0, ty)
     assert e.value.code == -5
