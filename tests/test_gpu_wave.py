@@ -233,3 +233,18 @@ def test_batch_requests_with_ragged_shot_counts():
     # the same shots in another order give the same image to rounding
     swapped = P.apply_H_batch([torch.from_numpy(dms[1])], [lists[1][::-1]])[0].cpu().numpy()
     assert rel(swapped, mixed[1]) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_zero_inputs_give_exact_zeros(dtype):
+    """The operators are linear: a zero perturbation or zero data gives exactly zero
+    (no bias from the background, the sponge or stale buffers), also right after a
+    nonzero call on the same context."""
+    w = ragged(dtype, nt=60)
+    M, P, c = _setup(w)
+    dm = torch.from_numpy(F.normal_field(w.model_shape, 95))
+    P.apply_H(dm)                                   # leaves nonzero fields and images behind
+    zm = torch.zeros(w.model_shape, dtype=dm.dtype)
+    assert not torch.any(P.apply_H(zm).cpu())
+    assert not torch.any(P.apply_F(zm).cpu())
+    assert not torch.any(P.apply_Fadj(torch.zeros((w.ns, w.nt, w.nr))).cpu())

@@ -166,3 +166,17 @@ def test_c5_full_size_dot_product():
     rhs = float((m.to(Fd.device).double() * Fd).sum())
     print(f"256^3 dot product: {abs(lhs - rhs) / abs(lhs):.3e}")
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+@pytest.mark.parametrize("snap,k", [("full", 0), ("ckpt_bf16", 4)])
+def test_3d_zero_inputs_give_exact_zeros(snap, k):
+    """Linear operators: zero in, exactly zero out, after a nonzero call on the same context."""
+    M = _gpu()
+    w = cube("f32", nt=40, snap=snap, k=k)
+    P = M.Problem.from_spec(w)
+    P.set_background(torch.from_numpy(F.medium(w)))
+    P.apply_H(torch.from_numpy(F.normal_field(w.model_shape, 53)))
+    zm = torch.zeros(w.model_shape)
+    assert not torch.any(P.apply_H(zm).cpu())
+    assert not torch.any(P.apply_F(zm).cpu())
+    assert not torch.any(P.apply_Fadj(torch.zeros((w.ns, w.nt, w.nr))).cpu())
