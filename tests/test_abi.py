@@ -3,6 +3,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "matprobe.h")
 LIB = os.path.join(ROOT, "paper_1101_3615_amd", "libmatprobe.so")
@@ -39,6 +41,15 @@ def test_python_binding_imports_without_device():
     assert callable(M.probe_fit) and callable(M.apply_Hinv)
     from paper_1101_3615_amd._lib import EXPORTS
     assert set(EXPORTS) <= set(declared())
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No CPU fallback: without the built library the binding raises before any compute."""
+    from paper_1101_3615_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libmatprobe.so"))
+    with pytest.raises(RuntimeError, match="is missing"):
+        _lib.lib()
 
 
 def test_create_rejects_grids_past_the_32_bit_offset_limit():
