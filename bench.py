@@ -202,17 +202,31 @@ def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_m
 
 
 def volume_run(nt):
-    """apply_H on the 256^3 workload with nt time steps (inputs resident on the device): wall
-    time, cell-steps per second and per-sweep device time per launch from the HIP events."""
+    """apply_H on the 256^3 workload with nt time steps (see apply_H_run)."""
+    import fixtures as F
+    return apply_H_run(F.c5().with_(nt=nt), volume=True)
+
+
+def checkpointed_run(nt):
+    """apply_H on the 1024 x 512 workload (128 shots, BF16 checkpoints every 4 steps) with
+    nt time steps (see apply_H_run)."""
+    import fixtures as F
+    return apply_H_run(F.c3().with_(nt=nt))
+
+
+def apply_H_run(w, volume=False):
+    """One apply_H on workload w (inputs resident on the device): wall time, cell-steps per
+    second and per-sweep device time per launch from the HIP events."""
     import torch
 
     import fixtures as F
     import paper_1101_3615_amd as M
-    w = F.c5().with_(nt=nt)
+    nt = w.nt
     c = F.medium(w)
     P = M.Problem.from_spec(w, timing=True)
     P.set_background(torch.from_numpy(c).to("cuda:0"))
-    y = torch.from_numpy(F.wavepackets(w, c, 15, 64)).to("cuda:0")
+    y = F.wavepackets(w, c, 15, 64) if volume else F.trials(w, c)[0]
+    y = torch.from_numpy(y).to("cuda:0")
     torch.cuda.synchronize()
     P.stats()
     t0 = time.perf_counter()
@@ -540,6 +554,9 @@ def main():
     ap.add_argument("--volume-steps", type=int, default=0,
                     help="only run apply_H on the 256^3 workload (32 shots, BF16 checkpoints) with this "
                          "many time steps and print its sweep times (3D measurement and profiling)")
+    ap.add_argument("--checkpointed-steps", type=int, default=0,
+                    help="only run apply_H on the 1024x512 workload (128 shots, BF16 checkpoints every 4 steps) "
+                         "with this many time steps and print its sweep times")
     ap.add_argument("--generalization", action="store_true",
                     help="only run the generalization study of the probed inverse (128x128 FP64 workload, "
                          "R1/R2/R4 fitted on 1/2/4 trial functions, tested on an independent one, bases of the "
@@ -582,6 +599,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}))
+        return
+    if args.checkpointed_steps:
+        print(json.dumps(checkpointed_run(args.checkpointed_steps)))
         return
     if args.volume_steps:
         print(json.dumps(volume_run(args.volume_steps)))
