@@ -250,3 +250,162 @@ def test_fused_H_equals_adjoint_of_born_data(small):
     a = F.normal_field(P.w.model_shape, 13).astype(np.float64)
     np.testing.assert_allclose(P.apply_Fadj(P.apply_F(a)), P.apply_H(a), rtol=1e-12,
                                atol=1e-12 * np.max(np.abs(P.apply_H(a))))
+
+
+# ------------------------------------------------------- absorbing layer --
+#
+# The layer is defined (a reading: the paper names a PML of width .15N) as a
+# damping term eta u_t with eta = eta_max (d / nb)^2 at distance d cells into
+# the layer, eta_max = 3 c_max ln(1/R) / (2 nb h), c_max the background's
+# maximum.  Two pins tie the oracle's time stepping to that definition through
+# what the damped wave equation u_tt + eta u_t = c^2 Lap u fixes: an exact
+# discrete energy balance and the WKB attenuation of a plane-wave pulse.
+
+def _stated_eta(P, R):
+    """eta on the propagation grid from the definition above (not from the oracle)."""
+    nb, h = P.nb, P.h
+    eta_max = 3.0 * float(np.max(P.c_model)) * np.log(1.0 / R) / (2.0 * nb * h)
+    eta = np.zeros(P.c_pad.shape)
+    for ax, n in enumerate(P.w.model_shape):
+        i = np.arange(n + 2 * nb)
+        d = np.where(i < nb, nb - i, np.where(i >= n + nb, i - (n + nb - 1), 0))
+        eta = eta + (eta_max * (d / nb) ** 2).reshape([-1 if k == ax else 1 for k in range(P.nd)])
+    return eta
+
+
+def _plant_eta_scale(P, scale):
+    """Plant a mistake in the oracle object: its damping profile times ``scale``."""
+    eta = P.eta * scale
+    P.a = 1.0 / (1.0 + eta * P.dt / 2.0)
+    P.b = (1.0 - eta * P.dt / 2.0) * P.a
+
+
+def _energy_balance_error(P, R, nt=120):
+    """max over steps of |E(n+1/2) - E(n-1/2) + dt/2 sum eta (u+ - u-)^2 / kappa| / E0.
+
+    For u+ = a (2u + kappa L u) - b u- with a = 1/(1 + eta dt/2),
+    b = (1 - eta dt/2) a, multiplying the scheme by (u+ - u-)/kappa and summing
+    (L symmetric) gives E(n+1/2) - E(n-1/2) = -(dt/2) sum eta (u+ - u-)^2 / kappa
+    with E(n+1/2) = sum (u+ - u)^2 / kappa - sum u+ L u, exactly.
+    """
+    rng = np.random.default_rng(17)
+    u0 = rng.standard_normal(P.c_pad.shape)
+    snaps = {-1: u0, 0: u0 + 0.05 * rng.standard_normal(P.c_pad.shape)}
+    P.nt = nt
+    P.background(0, keep_g=False, snapshots=snaps, source=False)
+    eta = _stated_eta(P, R)
+    e = [_energy(P, snaps[n + 1], snaps[n]) for n in range(-1, nt)]     # E(n + 1/2)
+    worst = 0.0
+    for n in range(0, nt):
+        drop = 0.5 * P.dt * np.sum(eta * (snaps[n + 1] - snaps[n - 1]) ** 2 / P.kappa)
+        worst = max(worst, abs(e[n + 1] - e[n] + drop))
+    return worst / abs(e[0])
+
+
+@pytest.mark.parametrize("nb,R", [(8, 1e-3), (12, 1e-2)])
+def test_sponge_exact_discrete_energy_balance(nb, R):
+    """Energy lost per step = (dt/2) sum eta (u+ - u-)^2 / kappa with the stated eta.
+
+    A smooth random medium makes c_max (which sets eta_max) differ from the
+    local c in kappa; a wrong eta_max, profile exponent, distance origin or
+    damping form (a, b) breaks the identity far above rounding.
+    """
+    w = F.tiny(n=20, nb=nb, nt=120, ns=1, nr=2, kind="smooth_random").with_(sponge_R=R)
+    P = Problem(w, F.medium(w))
+    assert _energy_balance_error(P, R) < 1e-11
+    _plant_eta_scale(P, 1.5)
+    assert _energy_balance_error(P, R) > 1e-4
+
+
+def _plane_wave_round_trip(nb, R, eta_scale=1.0, kh=1.0, courant=0.2, nx=240, nz=100,
+                           c=2000.0, h=10.0):
+    """Ratio of the reflected to the incident L2 norm of a downgoing plane pulse.
+
+    The pulse (carrier kh, Gaussian envelope of 8 cells) starts 30 cells below
+    the top of the model, is recorded 50 cells deep, crosses the bottom layer,
+    reflects from the zero exterior and comes back.  The model is wide enough
+    that nothing from the side layers reaches the recording column in time, so
+    the column sees the 1D problem.
+    """
+    dt = courant * h / c
+    z0, zr = 30, 50
+    dist = (nz - zr) + nb + 1                      # recording depth to the first exterior cell
+    nt = int(((2 * dist + 40) * h / c) / dt)
+    w = Workload(name="sponge", ndim=2, nx=nx, nz=nz, h=h, nb=nb, dt=dt, nt=nt, f_peak=10.0,
+                 src=np.array([[nx // 2, 0]], np.int32), rec=np.array([[nx // 2, zr]], np.int32),
+                 medium=dict(kind="constant", c=c), sponge_R=R)
+    P = Problem(w, F.medium(w))
+    if eta_scale != 1.0:
+        _plant_eta_scale(P, eta_scale)
+    zz = np.arange(nz + 2 * nb) - nb - float(z0)
+
+    def pulse(shift):
+        s = zz - shift
+        return np.repeat((np.exp(-0.5 * (s / 8.0) ** 2) * np.cos(kh * s))[:, None],
+                         P.c_pad.shape[1], axis=1)
+
+    snaps = {-1: pulse(-c * dt / h), 0: pulse(0.0)}      # moving down at speed c
+    _, tr = P.background(0, keep_g=False, snapshots=snaps, source=False)
+    t = (np.arange(nt) + 1) * dt
+    split = ((zr - z0) + dist) * h / c                 # between the two passes
+    tr = tr[:, 0]
+    return np.linalg.norm(tr[t >= split]) / np.linalg.norm(tr[t < split])
+
+
+def _local_decay(eta, kh, courant, c, h):
+    """Im k h of the damped scheme's plane wave at the pulse's frequency, for each eta.
+
+    Discrete dispersion relation of u+ = a(2u + kappa L u) - b u- for
+    u = exp(i(k x - w t)): -(4/dt^2) sin^2(w dt/2) - i eta sin(w dt)/dt = c^2 sigma(k),
+    sigma(k) = h^-2 (w0 + 2 sum_j w_j cos(j k h)), solved for complex k by Newton.
+    """
+    dt = courant * h / c
+    jj = np.arange(1, 5)
+
+    def sig(k):
+        return (FD8[0] + 2 * np.sum(FD8[1:] * np.cos(jj * k * h))) / h ** 2
+
+    def dsig(k):
+        return -2 * np.sum(FD8[1:] * jj * h * np.sin(jj * k * h)) / h ** 2
+
+    k0 = kh / h
+    om = 2.0 / dt * np.arcsin(np.sqrt(-c * c * sig(k0) * dt * dt / 4.0))
+    out = []
+    for e in np.atleast_1d(eta):
+        rhs = -(4.0 / dt ** 2) * np.sin(om * dt / 2) ** 2 - 1j * e * np.sin(om * dt) / dt
+        k = complex(k0)
+        for _ in range(60):
+            k = k - (c * c * sig(k) - rhs) / (c * c * dsig(k))
+        out.append(k.imag * h)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("nb", [20, 40])
+def test_sponge_wkb_round_trip_attenuation(nb):
+    """Round trip through the layer attenuates as exp(-2 sum_d Im k_d h) (WKB).
+
+    Im k_d is the local decay of the damped scheme at each layer cell
+    d = 1..nb; for eta << omega it is eta_d / (2c), so the exponent is close to
+    sum_d eta_d h / c.  The zero exterior acts as the reflecting wall somewhere
+    in the first exterior cell, whose share is not fixed by WKB: the measured
+    exponent (relative to the same run with R = 1, i.e. no damping, which
+    measures the wall's own reflection) must lie between the sum over the
+    layer's cells and that sum plus one exterior cell's round trip.  Measured:
+    the wall sits 0.40 of a cell out for both widths.  A damping 1.5 times too
+    strong, or a linear or cubic profile, falls far outside.
+    """
+    R, c, h, kh, courant = 1e-3, 2000.0, 10.0, 1.0, 0.2
+    eta_max = 3.0 * c * np.log(1.0 / R) / (2.0 * nb * h)
+    d = np.arange(1, nb + 2)
+    decay = _local_decay(eta_max * (d / nb) ** 2, kh, courant, c, h)
+    lo = 2.0 * np.sum(decay[:nb])
+    hi = lo + 2.0 * decay[nb]
+    wall = _plane_wave_round_trip(nb, 1.0)
+    assert abs(wall - 1.0) < 1e-3                      # undamped: the wall reflects all
+    got = -np.log(_plane_wave_round_trip(nb, R) / wall)
+    assert lo <= got <= hi, (lo, got, hi)
+    # the simple WKB estimate sum eta h / c is within 5 % of the measured exponent
+    simple = np.sum(eta_max * (d[:nb] / nb) ** 2) * h / c
+    assert abs(got / simple - 1.0) < 0.05
+    planted = -np.log(_plane_wave_round_trip(nb, R, eta_scale=1.5) / wall)
+    assert planted > hi + 0.5
