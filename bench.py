@@ -288,82 +288,6 @@ def generalization_run(ns=(1, 2, 4)):
     return out
 
 
-def variable_media_run(gammas=(0.0, 0.1, 0.2, 0.3, 0.4), gd_steps=200, ntrials=5):
-    """R5 preconditioner applied to the migrated image against the descent image, in
-    backgrounds blended between a uniform medium (gamma = 0) and a smooth variable one
-    (gamma = 0.4), on the 128x128 FP64 workload, for each basis size."""
-    import numpy as np
-    import torch
-
-    import fixtures as F
-    import paper_1101_3615_amd as M
-    from paper_1101_3615_amd import inversion as I
-    from paper_1101_3615_amd.study import paper_bases
-    w = F.c1()
-    P = M.Problem.from_spec(w)
-    bases = paper_bases(2, GEN_SIZES)
-    out = []
-    for g in gammas:
-        c = F.blended_medium(w, g)
-        P.set_background(torch.from_numpy(c).to("cuda:0"))
-        m = torch.from_numpy(F.reflectivity(w, c, seed=5).astype(np.float64)).to("cuda:0")
-        b = P.apply_H(m).clone()
-        x_gd, _ = I.steepest_descent(P, b, gd_steps)
-        ys = [torch.from_numpy(F.wavepackets(w, c, 100 + s, w.packets_per_trial)).to("cuda:0") for s in range(ntrials)]
-        xs = [P.apply_H(y).clone() for y in ys]
-        for B in bases:
-            coef, relres, deficient = M.probe_fit(P, B, ys, xs, strict=False)
-            img = M.apply_Hinv(P, B, coef, b)
-            out.append({"study": "variable_media", "workload": w.name, "gamma": g, "preconditioner": f"R{ntrials}",
-                        "p": B.p, "mse_vs_descent": round(I.relative_mse(img, x_gd), 6),
-                        "fit_relres": round(relres, 6), "rank_deficient": deficient})
-    return out
-
-
-def eps_rank_run(batch=64, eps=(1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6)):
-    """The 16384 x 16384 normal operator of the 128x128 FP64 workload assembled column by
-    column (apply_H_batch on unit vectors, `batch` columns per sweep): its asymmetry, its
-    smallest eigenvalue relative to the largest, and the eps-rank for a top eigenvalue of 1
-    (the table of Sec. 2.1).  Progress lines go to stderr."""
-    import numpy as np
-    import torch
-
-    import fixtures as F
-    import paper_1101_3615_amd as M
-    w = F.c1()
-    c = F.medium(w)
-    P = M.Problem.from_spec(w)
-    P.set_background(torch.from_numpy(c).to("cuda:0"))
-    n = w.model_cells
-    H = np.empty((n, n))
-    shots = list(range(w.ns))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for j0 in range(0, n, batch):
-        nb = min(batch, n - j0)
-        dms = []
-        for k in range(nb):
-            e = torch.zeros(n, dtype=torch.float64, device="cuda:0")
-            e[j0 + k] = 1.0
-            dms.append(e.view(w.model_shape))
-        outs = P.apply_H_batch(dms, [shots] * nb)
-        H[:, j0:j0 + nb] = torch.stack([o.reshape(-1) for o in outs], 1).cpu().numpy()
-        if (j0 // batch) % 32 == 0:
-            print(f"eps-rank: {j0 + nb} of {n} columns, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    t_assemble = time.perf_counter() - t0
-    asym = float(np.linalg.norm(H - H.T) / np.linalg.norm(H))
-    Hs = torch.from_numpy(0.5 * (H + H.T)).to("cuda:0")
-    del H
-    t1 = time.perf_counter()
-    ev = torch.linalg.eigvalsh(Hs).cpu().numpy()[::-1]
-    t_eig = time.perf_counter() - t1
-    top = float(ev[0])
-    return {"study": "eps_rank", "workload": w.name, "n": n, "assemble_s": round(t_assemble, 1),
-            "eig_s": round(t_eig, 1), "asymmetry": float(f"{asym:.3g}"),
-            "min_eig_rel": float(f"{float(ev[-1]) / top:.3g}"),
-            "eps_rank": {f"{e:g}": int(np.sum(ev / top > e)) for e in eps}}
-
-
 def curvelet_run(reps=3):
     """Curvelet trial synthesis and the ray-traced illumination mask on the 512x256 workload
     (FP32): device time per call and the mask's visible fraction."""
@@ -439,7 +363,7 @@ def gauss_newton_records(P, w, c, refl, basis, trial, outer=3, inner=5):
             continue
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t) * 1e3 / outer
-        err = [round(I.relative_mse(1.0 / (ck * ck) - m0, refl), 6) for ck in cs]
+        err = [round(I.relative_mse(P, 1.0 / (ck * ck) - m0, refl), 6) for ck in cs]
         out.append(dict(rec, ms_per_outer=round(ms, 1),
                         misfit=[float(f"{j:.6g}") for j in Js], model_error=err))
     P.set_background(c0)
@@ -472,11 +396,11 @@ def inversion_run(gd_steps=200, cg_iters=20):
     ms_gd = (time.perf_counter() - t) * 1e3 / gd_steps
     r = b - P.apply_H(x_gd)
     out = [{"study": "inversion", "workload": w.name, "image": f"descent{gd_steps}", "ms_per_step": round(ms_gd, 3),
-            "relres": round(float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)), 6),
-            "mse_vs_true": round(I.relative_mse(x_gd, m), 6)}]
+            "relres": round((P.dot(r, r) / P.dot(b, b)) ** 0.5, 6),
+            "mse_vs_true": round(I.relative_mse(P, x_gd, m), 6)}]
     a = float((b * x_gd).sum() / (b * b).sum())
     out.append({"study": "inversion", "workload": w.name, "image": "migrated (best scalar multiple)",
-                "mse_vs_descent": round(I.relative_mse(a * b, x_gd), 6), "mse_vs_true": round(I.relative_mse(a * b, m), 6)})
+                "mse_vs_descent": round(I.relative_mse(P, a * b, x_gd), 6), "mse_vs_true": round(I.relative_mse(P, a * b, m), 6)})
     trials = [torch.from_numpy(F.wavepackets(w, c, 100 + s, w.packets_per_trial)).to("cuda:0") for s in range(4)]
     Htrials = [P.apply_H(y) for y in trials]
     # randomized curvelet trials on the illuminated set, and the projection onto it that
@@ -520,9 +444,9 @@ def inversion_run(gd_steps=200, cg_iters=20):
             torch.cuda.synchronize()
             apply_ms = (time.perf_counter() - t) * 1e3
             out.append({"study": "inversion", "workload": w.name, "preconditioner": name, "p": B.p,
-                        "mse_vs_descent": round(I.relative_mse(img, x_gd), 6),
-                        "mse_vs_true": round(I.relative_mse(img, m), 6),
-                        "mse_vs_true_visible": round(I.relative_mse(cv.project(img, mask), m_vis), 6),
+                        "mse_vs_descent": round(I.relative_mse(P, img, x_gd), 6),
+                        "mse_vs_true": round(I.relative_mse(P, img, m), 6),
+                        "mse_vs_true_visible": round(I.relative_mse(P, cv.project(img, mask), m_vis), 6),
                         "fit_relres": round(relres, 6),
                         "rank_deficient": deficient, "apply_ms": round(apply_ms, 3)})
             if B.p == 21:
@@ -536,7 +460,7 @@ def inversion_run(gd_steps=200, cg_iters=20):
         out.append({"study": "inversion", "workload": w.name, "solver": "CG", "preconditioner": name, "p": 21,
                     "iters": len(norms) - 1, "ms_per_iter": round((time.perf_counter() - t) * 1e3 / cg_iters, 3),
                     "relres": [round(v / norms[0], 6) for v in norms],
-                    "mse_vs_descent": round(I.relative_mse(x, x_gd), 6), "mse_vs_true": round(I.relative_mse(x, m), 6)})
+                    "mse_vs_descent": round(I.relative_mse(P, x, x_gd), 6), "mse_vs_true": round(I.relative_mse(P, x, m), 6)})
     return out
 
 
@@ -565,12 +489,6 @@ def main():
                     help="only run the linearised inversion study (128x128 FP64 workload: 200 descent steps as "
                          "the reference image, Rn/Kn fitted inverses applied to the migrated image, CG with and "
                          "without a fitted preconditioner) and print one JSON line per result")
-    ap.add_argument("--variable-media", action="store_true",
-                    help="only run the variable-media study (R5 on backgrounds blended from uniform to smooth "
-                         "variable, 128x128 FP64 workload) and print one JSON line per fit")
-    ap.add_argument("--eps-rank", action="store_true",
-                    help="only assemble the 16384 x 16384 normal operator of the 128x128 FP64 workload and print "
-                         "its symmetry, definiteness and eps-rank profile")
     ap.add_argument("--curvelets", action="store_true",
                     help="only time the curvelet trial synthesis and the ray-traced illumination mask on the "
                          "512x256 workload and print one JSON line")
@@ -612,13 +530,6 @@ def main():
         return
     if args.curvelets:
         print(json.dumps(curvelet_run()), flush=True)
-        return
-    if args.eps_rank:
-        print(json.dumps(eps_rank_run()), flush=True)
-        return
-    if args.variable_media:
-        for rec in variable_media_run():
-            print(json.dumps(rec), flush=True)
         return
     if args.inversion:
         for rec in inversion_run():

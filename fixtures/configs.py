@@ -188,7 +188,7 @@ def c5():
         dtype="f32", snap="ckpt_bf16", ckpt_every=8,
         medium=dict(kind="smooth_random", cmin=1500.0, cmax=4500.0,
                     corr=400.0, seed=14),
-        legendre=leg, trial_seeds=(15, 16, 17, 18), packets_per_trial=512)
+        legendre=leg, trial_seeds=(15, 16, 17, 18), packets_per_trial=4096)
 
 
 ALL = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}

@@ -86,27 +86,75 @@ def wavepackets(w, c, seed, npk, window=4.0):
         ph = st.uniform(npk, 0.0, 2 * np.pi)
         normals = np.stack([cth, sth * np.sin(ph), sth * np.cos(ph)], axis=1)
     sgn = st.signs(npk)
-    y = np.zeros(shape)
-    for j in range(npk):
-        idx = tuple(min(int(round(cen[j, d] / h)), shape[d] - 1) for d in range(nd))
-        kj = 4 * np.pi * w.f_peak / float(c[idx])
+    if nd == 3:
+        y = _packets3d(shape, h, cen, normals, sgn, w.f_peak, c, window)
+    else:
+        y = np.zeros(shape)
+        for j in range(npk):
+            idx = tuple(min(int(round(cen[j, d] / h)), shape[d] - 1) for d in range(nd))
+            kj = 4 * np.pi * w.f_peak / float(c[idx])
+            sperp = np.pi / kj
+            spar = 2 * np.pi / kj
+            r = window * spar
+            sl, grids = [], []
+            for d in range(nd):
+                a = max(int(np.floor((cen[j, d] - r) / h)), 0)
+                b = min(int(np.ceil((cen[j, d] + r) / h)) + 1, shape[d])
+                sl.append(slice(a, b))
+                grids.append(np.arange(a, b) * h - cen[j, d])
+            mesh = np.meshgrid(*grids, indexing="ij")
+            rho_perp = sum(mesh[d] * normals[j, d] for d in range(nd))
+            r2 = sum(m_ ** 2 for m_ in mesh)
+            rho_par2 = np.maximum(r2 - rho_perp ** 2, 0.0)
+            env = np.exp(-rho_par2 / (2 * spar ** 2) - rho_perp ** 2 / (2 * sperp ** 2))
+            y[tuple(sl)] += sgn[j] * env * np.cos(kj * rho_perp)
+    y /= np.max(np.abs(y))
+    return y.astype(np.float32)
+
+
+def _packets3d(shape, h, cen, normals, sgn, f_peak, c, window):
+    """The 3D packet sum of ``wavepackets`` in factored form.
+
+    With rho_perp = sum_d n_d g_d (g_d the offsets along each axis) and
+    beta = 1/(2 sigma_perp^2) - 1/(2 sigma_par^2), each packet is
+    Re prod_d [exp(-g_d^2/(2 sigma_par^2) - beta n_d^2 g_d^2 + i k n_d g_d)]
+    times exp(-2 beta n_d n_e g_d g_e) for the three axis pairs: the same
+    function, built from 1D and 2D factors so the box costs a few products.  The
+    box products run in torch (multi-threaded, exact IEEE products; every
+    transcendental is taken in numpy on the 1D and 2D factors).
+    """
+    import torch
+    y = torch.zeros(shape, dtype=torch.float64)
+    for j in range(cen.shape[0]):
+        idx = tuple(min(int(round(cen[j, d] / h)), shape[d] - 1) for d in range(3))
+        kj = 4 * np.pi * f_peak / float(c[idx])
         sperp = np.pi / kj
         spar = 2 * np.pi / kj
         r = window * spar
-        sl, grids = [], []
-        for d in range(nd):
+        sl, g = [], []
+        for d in range(3):
             a = max(int(np.floor((cen[j, d] - r) / h)), 0)
             b = min(int(np.ceil((cen[j, d] + r) / h)) + 1, shape[d])
             sl.append(slice(a, b))
-            grids.append(np.arange(a, b) * h - cen[j, d])
-        mesh = np.meshgrid(*grids, indexing="ij")
-        rho_perp = sum(mesh[d] * normals[j, d] for d in range(nd))
-        r2 = sum(m_ ** 2 for m_ in mesh)
-        rho_par2 = np.maximum(r2 - rho_perp ** 2, 0.0)
-        env = np.exp(-rho_par2 / (2 * spar ** 2) - rho_perp ** 2 / (2 * sperp ** 2))
-        y[tuple(sl)] += sgn[j] * env * np.cos(kj * rho_perp)
-    y /= np.max(np.abs(y))
-    return y.astype(np.float32)
+            g.append(np.arange(a, b) * h - cen[j, d])
+        n = normals[j]
+        beta = 1.0 / (2 * sperp ** 2) - 1.0 / (2 * spar ** 2)
+        one = [np.exp(-g[d] ** 2 / (2 * spar ** 2) - beta * (n[d] * g[d]) ** 2) for d in range(3)]
+        ph = [kj * n[d] * g[d] for d in range(3)]
+        zy = np.exp(-2 * beta * n[0] * n[1] * np.outer(g[0], g[1]))
+        zx = np.exp(-2 * beta * n[0] * n[2] * np.outer(g[0], g[2]))
+        yx = np.exp(-2 * beta * n[1] * n[2] * np.outer(g[1], g[2]))
+        # (z, y) and (y, x) complex factors, real and imaginary parts
+        a2 = np.outer(one[0], one[1]) * zy
+        ar = a2 * np.cos(np.add.outer(ph[0], ph[1]))
+        ai = a2 * np.sin(np.add.outer(ph[0], ph[1]))
+        b2 = one[2][None, :] * yx
+        br = b2 * np.cos(ph[2])[None, :]
+        bi = b2 * np.sin(ph[2])[None, :]
+        t = lambda v: torch.from_numpy(np.ascontiguousarray(v))
+        box = (t(ar)[:, :, None] * t(br)[None, :, :] - t(ai)[:, :, None] * t(bi)[None, :, :]) * t(zx)[:, None, :]
+        y[tuple(sl)] += float(sgn[j]) * box
+    return y.numpy()
 
 
 def trials(w, c=None):
@@ -173,17 +221,18 @@ def tiny(ndim=2, n=16, nb=8, nt=200, ns=2, nr=16, h=10.0, dt=1.0e-3,
                     trial_seeds=(seed + 1,), packets_per_trial=2)
 
 
-def blended_medium(w, gamma, r=0.05, seed=4, cmin=1500.0, cmax=3000.0, corr=60.0):
-    """Variable-media stand-in (2D, float32): M is a seeded smooth random velocity in
-    [cmin, cmax] (in place of the smoothed Marmousi model, which is not available), M_g is
-    M low-passed by the disk |k| <= r N of the FFT grid (N: the larger side), and
-    c = (1 - g/0.4) mean(M) + (g/0.4) M_g, so g = 0 is a uniform medium."""
-    base = w.with_(medium=dict(kind="smooth_random", cmin=cmin, cmax=cmax, corr=corr, seed=seed))
-    M = medium(base).astype(np.float64)
-    nz, nx = M.shape
-    kz = np.fft.fftfreq(nz) * nz
-    kx = np.fft.fftfreq(nx) * nx
-    disk = (kz[:, None] ** 2 + kx[None, :] ** 2) <= (r * max(nz, nx)) ** 2
-    Mg = np.fft.ifft2(np.fft.fft2(M) * disk).real
-    c = (1.0 - gamma / 0.4) * M.mean() + (gamma / 0.4) * Mg
-    return np.ascontiguousarray(c, dtype=np.float64).astype(np.float32)
+def bandlimited_data(shape, seed, dt, f_peak):
+    """Seeded data traces [..., nt, nr] with a Ricker amplitude spectrum, float32.
+
+    White N(0,1) samples filtered along time by |R(f)| = f^2 / f_peak^2
+    exp(1 - f^2 / f_peak^2) (peak 1 at f_peak), then scaled to unit RMS: data of
+    the band that the sources put into the medium, for applying F* to traces
+    other than Born data of a known model.
+    """
+    x = normal_field(shape, seed, np.float64)
+    nt = shape[-2]
+    f = np.fft.rfftfreq(nt, dt)
+    amp = (f / f_peak) ** 2 * np.exp(1.0 - (f / f_peak) ** 2)
+    y = np.fft.irfft(np.fft.rfft(x, axis=-2) * amp[:, None], n=nt, axis=-2)
+    y /= np.sqrt(np.mean(y * y))
+    return y.astype(np.float32)

@@ -962,14 +962,7 @@ static int fit_t(mp_ctx* ctx, const Basis& b, int T_, const void* const* y, cons
   SY_HIP(hipMemcpyAsync(rp.data(), ws->part.get(), sizeof(double) * 256, hipMemcpyDeviceToHost, s));
   SY_HIP(hipStreamSynchronize(s));
   bool deficient = false;
-  if (h.status) {
-    hipLaunchKernelGGL(k_minnorm, dim3(1), dim3(256), 0, s, W, ws->G0.as<double>(), p, 1e-13);
-    SY_LAUNCH();
-    SY_HIP(hipMemcpyAsync(&h, W, sizeof(Small), hipMemcpyDeviceToHost, s));
-    SY_HIP(hipStreamSynchronize(s));
-    deficient = true;
-    if (relres) *relres = std::nan("");
-  } else {
+  if (!h.status) {
     double smax = 0.0, smin = 1e300;
     for (int i = 0; i < p; ++i) {
       smax = std::max(smax, h.sig[i]);
@@ -979,6 +972,28 @@ static int fit_t(mp_ctx* ctx, const Basis& b, int T_, const void* const* y, cons
     double rr = 0.0;
     for (int i = 0; i < 256; ++i) rr += rp[i];
     if (relres) *relres = (h.bb > 0.0) ? std::sqrt(rr / h.bb) : 0.0;
+  }
+  if (h.status || deficient) {
+    // rank deficient (a Cholesky pivot failed, or the singular-value test): the
+    // minimum-norm solution of the column-equilibrated normal equations, from the
+    // first Gram matrix; the residual from the same Gram, ||b||^2 - 2 c.r + c.G c
+    hipLaunchKernelGGL(k_minnorm, dim3(1), dim3(256), 0, s, W, ws->G0.as<double>(), p, 1e-13);
+    SY_LAUNCH();
+    std::vector<double> G((size_t)(p + 1) * (p + 1));
+    SY_HIP(hipMemcpyAsync(&h, W, sizeof(Small), hipMemcpyDeviceToHost, s));
+    SY_HIP(hipMemcpyAsync(G.data(), ws->G0.get(), sizeof(double) * G.size(), hipMemcpyDeviceToHost, s));
+    SY_HIP(hipStreamSynchronize(s));
+    deficient = true;
+    if (relres) {
+      const int ld = p + 1;
+      double rr = G[(size_t)p * ld + p];
+      for (int i = 0; i < p; ++i) {
+        rr -= 2.0 * h.c[i] * G[(size_t)i * ld + p];
+        for (int j = 0; j < p; ++j) rr += h.c[i] * G[(size_t)i * ld + j] * h.c[j];
+      }
+      const double bb = G[(size_t)p * ld + p];
+      *relres = (bb > 0.0) ? std::sqrt(std::max(rr, 0.0) / bb) : 0.0;
+    }
   }
   for (int i = 0; i < p; ++i) c[i] = h.c[i];
   if (deficient) {

@@ -17,11 +17,15 @@ from . import _lib as L
 from .problem import apply_Hinv, probe_fit
 
 
-def relative_mse(m, ref):
+def relative_mse(problem, m, ref):
     """||m - ref||_2 / ||ref||_2 (the paper's relative MSE between models, Sec. 2: a ratio
-    of norms, not of squared norms).  A measurement of results, taken with torch."""
-    m, ref = m.double(), ref.to(m.device).double()
-    return float(torch.linalg.vector_norm(m - ref) / torch.linalg.vector_norm(ref))
+    of norms, not of squared norms), with the library's vector kernels (FP64 dot in a
+    fixed order).  m and ref are cast to the problem's precision and device."""
+    P = problem
+    ref = ref.to(device=P.device, dtype=P.torch_dtype).contiguous()
+    diff = m.to(device=P.device, dtype=P.torch_dtype).contiguous().clone()
+    P.axpby(-1.0, ref, 1.0, diff)
+    return (P.dot(diff, diff) / P.dot(ref, ref)) ** 0.5
 
 
 def krylov_pairs(problem, b, n):

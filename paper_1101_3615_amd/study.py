@@ -45,11 +45,10 @@ def generalization(problem, bases, ys_fit, y_new, xs_fit=None):
     tensors on the problem's device)."""
     xs = [problem.apply_H(y).clone() for y in ys_fit] if xs_fit is None else list(xs_fit)
     x_new = problem.apply_H(y_new).clone()
-    ref = y_new.to(device=x_new.device).double()
     out = []
     for B in bases:
         c, relres, deficient = probe_fit(problem, B, ys_fit, xs, strict=False)
-        rec = apply_Hinv(problem, B, c, x_new).double()
-        mse = relative_mse(rec, ref)
+        rec = apply_Hinv(problem, B, c, x_new)
+        mse = relative_mse(problem, rec, y_new)
         out.append((B.p, mse, float(relres), bool(deficient)))
     return out

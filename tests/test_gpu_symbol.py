@@ -90,15 +90,29 @@ def test_probe_fit_matches_oracle_least_squares(dtype):
 
 
 def test_probe_fit_rank_deficient():
+    """A duplicated column: the fit flags the system (code -5) and, with strict=False,
+    returns the minimum-norm least-squares coefficients (numpy's lstsq on the stacked
+    columns; the duplicate columns share the equilibration scale, so the minimum in the
+    equilibrated variables is the plain minimum norm) and their residual."""
     M = _gpu()
     w = F.tiny(n=8, nr=8, dtype="f64").with_(nx=32, nz=32)
     P = _problem(M, w)
-    B = M.Basis([(0, 0), (0, 0)], (0,), 2)        # the same column twice
-    x = F.normal_field((32, 32), 80)
-    y = F.normal_field((32, 32), 81)
-    with pytest.raises(M.MatprobeError) as e:
-        M.probe_fit(P, B, [torch.from_numpy(y)], [torch.from_numpy(x)])
-    assert e.value.code == -5
+    x = F.normal_field((32, 32), 80).astype(np.float64)
+    y = F.normal_field((32, 32), 81).astype(np.float64)
+    for legs in ([(0, 0), (0, 0)], [(0, 0), (1, 0), (0, 0)]):
+        B = M.Basis(legs, (0,), 2)
+        with pytest.raises(M.MatprobeError) as e:
+            M.probe_fit(P, B, [torch.from_numpy(y)], [torch.from_numpy(x)])
+        assert e.value.code == -5
+        c, relres, deficient = M.probe_fit(P, B, [torch.from_numpy(y)], [torch.from_numpy(x)], strict=False)
+        assert deficient
+        zt = (np.arange(32) * 2 + 1) / 32.0 - 1.0          # cell centres of the depth axis
+        cols = [x * (zt[:, None] if a == 1 else 1.0) for a, _ in legs]
+        A = np.stack([col.ravel() for col in cols], axis=1)
+        cref = np.linalg.lstsq(A, y.ravel(), rcond=1e-10)[0]
+        assert rel(np.asarray(c), cref) <= 1e-10
+        rref = np.linalg.norm(A @ cref - y.ravel()) / np.linalg.norm(y)
+        assert abs(relres - rref) <= 1e-8
 
 
 def test_non_power_of_two_rejected():
