@@ -1,18 +1,33 @@
 #!/usr/bin/env python3
 """Throughput of the matrix-probing pass on one MI355X.
 
-Workload (default): the 512 x 256 plain FP32 configuration -- propagation
-grid 552 x 296 (20 absorbing cells per side), 64 surface sources, 256
-receivers, 12 Hz Ricker, dt = 0.8 ms, 3000 steps, FP32 fields, full FP32 g
-history, FP64 imaging; 2 random wavepacket trial functions; p = 20 basis terms
-(Legendre in depth, degrees 0-4, times rho^0..3); the fitted inverse applied to
-the remigrated image of a synthetic reflectivity by FFT multipliers.
+Workload (default): the 256^3 configuration -- propagation grid 296^3 (20
+absorbing cells per side, 12.5 m), 32 surface sources on an 8 x 4 lattice,
+64 x 64 receivers, 10 Hz Ricker, dt = 1 ms, FP32 stencils, BF16 checkpoints of
+the background every 8 steps with recomputation, FP64 imaging; 4 wavepacket
+trial functions of 4096 packets; p = 40 basis terms (Legendre polynomials of
+total degree <= 2 in (z, y, x) times rho^0..3); the FP64 least-squares fit on
+the GPU; the fitted inverse applied by 3D FFT multipliers.
 
-One step = the whole probing pass on inputs resident in HBM: set the
-background (drops the resident background wavefield), x_t = H y_t for both
-trials (the first computes and keeps the background, the second reuses it),
-the least-squares fit, and the fitted inverse applied to the image.
-value = apply_H propagation-grid cell-steps of the step / step time.
+The record is 2000 steps.  Its checkpoints (25.9 GB per shot) limit a shot wave
+to what the device holds: the benchmark computes that wave size from the
+library's footprint of the 2000-step job (8 shots on one MI355X, four waves) and
+runs every application of H with it.  A step applies H over the first
+--record-steps steps of the record (default 40: five checkpoint segments), so
+every launch has the shape of the full application; value = apply_H
+propagation cell-steps of the step / step time, i.e. the rate of a full
+application extrapolated over the record length (--full-record times one
+2000-step application to check it).
+
+One step, with every input resident in HBM: set the background; x_t = H y_t for
+the 4 trials; the least-squares fit over the 4 x 256^3 stacked rows; the fitted
+inverse applied to x_0.
+
+Extra legs on the same line: the 512 x 256 FP32 workload (full 3000-step
+record) and the 1024 x 512 BF16-checkpointed workload (400 of its 4000 steps,
+waves of 64 shots as at full length), each with its dominant kernel's roofline
+fraction; the serving run; the FP64 oracle on a bounded sample of the 256^3
+workload as the CPU baseline.
 
 Prints one JSON line (see the keys below).  --gpus must be 1.
 """
@@ -29,25 +44,25 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
+_CPU_INPUT = {}
+
+
 def _cpu_shot(args):
     """Oracle apply_H of one shot over the first `nsteps` steps (CPU baseline leg)."""
     shot, nsteps = args
-    import fixtures as F
     from oracle import Problem
-    w = F.c2().with_(nt=nsteps)
-    c = F.medium(w)
-    y = F.trials(w, c)[0]
+    w, c, y = _CPU_INPUT["w"].with_(nt=nsteps), _CPU_INPUT["c"], _CPU_INPUT["y"]
     P = Problem(w, c)
     t = time.perf_counter()
     P.apply_H(y, shots=[shot])
     return time.perf_counter() - t
 
 
-def cpu_baseline(nsteps, workers):
-    """The FP64 oracle on a bounded sample of the workload, one shot per process."""
+def cpu_baseline(w, c, y, nsteps, workers):
+    """The FP64 oracle on a bounded sample of workload w (inputs c, y built by the
+    caller), one shot per forked process.  Run before anything initialises the GPU."""
     import multiprocessing as mp
-    import fixtures as F
-    w = F.c2()
+    _CPU_INPUT.update(w=w, c=c, y=y)
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
         times = pool.map(_cpu_shot, [(s, nsteps) for s in range(workers)])
@@ -55,8 +70,26 @@ def cpu_baseline(nsteps, workers):
     cell_steps = w.prop_cells * nsteps * workers
     return {"value": cell_steps / wall / 1e9, "unit": "Gcell-steps/s", "cores": workers,
             "kind": "oracle",
-            "sample": f"{workers} shots x {nsteps} of {w.nt} steps of apply_H (forward + adjoint), "
-                      f"FP64 numpy, one process per shot, slowest worker {wall:.1f} s"}
+            "sample": f"{w.name}: {workers} shots x {nsteps} of {w.nt} steps of apply_H (background, Born and "
+                      f"adjoint sweeps), FP64 numpy, one process per shot, slowest worker {wall:.1f} s"}
+
+
+def kernel_bytes3d(kind, w, nsh):
+    """Algorithmic HBM bytes of one launch (one time step) of a 3D sweep kernel over
+    nsh shots (FP32 fields, FP64 image), P = propagation cells, M = model cells:
+      fused:      per shot reads u, D, du, du^{n-1} and writes u, D, du^{n+1}
+                  (28 B per cell); kappa and the perturbation once (8 B per cell);
+      background: per shot reads u, D and writes u, D (16 B per cell), writes g
+                  (4 B per model cell); kappa once;
+      adjoint:    per shot reads nu, nu^{k+2} and writes nu^k (12 B per cell), reads g
+                  (4 B per model cell), one FP64 image read-modify-write per pair of
+                  shots (8 B per model cell and shot); kappa once.
+    The BF16 checkpoint writes (4 B per cell every 8th step) and the receiver traffic
+    are left out."""
+    P, M = w.prop_cells, w.model_cells
+    per = {"fused": 28 * P, "background": 16 * P + 4 * M, "adjoint": 12 * P + 4 * M + 8 * M}[kind]
+    shared = 8 * P if kind == "fused" else 4 * P
+    return per * nsh + shared
 
 
 def kernel_bytes(kind, w, s=2):
@@ -84,19 +117,26 @@ def kernel_bytes(kind, w, s=2):
     return per * ns + shared
 
 
+def _sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+TRAFFIC = {"2d": ("traffic.json", "wave2d.hip"), "3d": ("traffic_c5.json", "wave3d.hip")}
+
+
 def traffic_for(kind, w):
-    """Measured HBM bytes per launch from the committed counter summary, if current."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    """Measured HBM bytes per launch from the committed counter summary, if it was taken
+    on this workload with the kernel source as it is now (else None)."""
+    rec_name, src_name = TRAFFIC["3d" if w.ndim == 3 else "2d"]
     try:
-        with open(path) as f:
+        with open(os.path.join(ROOT, "profiles", rec_name)) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    src = os.path.join(ROOT, "paper_1101_3615_amd", "csrc", "wave2d.hip")
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
+    digest = _sha(os.path.join(ROOT, "paper_1101_3615_amd", "csrc", src_name))
     k = rec.get("kernels", {}).get(kind)
-    if not k or rec.get("wave2d_sha256") != digest or rec.get("workload") != w.name:
+    if not k or rec.get("source_sha256", rec.get("wave2d_sha256")) != digest or rec.get("workload") != w.name:
         return None
     return k.get("bytes_per_launch")
 
@@ -160,17 +200,19 @@ def serve_leg(seconds, rate=20.0, seed=13):
             "served_vs_plain": round(t_plain / t_served, 3)}
 
 
-def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, workload):
-    """profiles/traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
-    this benchmark and of the copy probe: per sweep kernel, HBM bytes per launch =
-    mean counter (KiB) x 1024 x (copy bytes / the copy kernel's reading of the same
-    counter)."""
+def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, dims):
+    """profiles/traffic.json (2D, 512 x 256 workload) or profiles/traffic_c5.json (3D,
+    256^3 workload) from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this
+    benchmark and of the copy probe: per sweep kernel, HBM bytes per launch = mean counter
+    (KiB) x 1024 x (copy bytes / the copy kernel's reading of the same counter)."""
     import csv
     import glob
     import re
 
+    import fixtures as F
+
     def means(d):
-        f = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
         acc = {}
         for r in csv.DictReader(open(f)):
             acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
@@ -184,19 +226,22 @@ def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_m
     fe, wr = means(fetch_dir), means(write_dir)
     kernels = {}
     for name in fe:
-        m = re.search(r"k_sweep2d<float, (\d), (\d), (\d)>", name)
-        if not m or name not in wr or m.group(2) != "2":
+        if dims == "3d":
+            m = re.search(r"k_step3d<float, (\d), (\d)>", name)
+            ok = m is not None
+        else:
+            m = re.search(r"k_sweep2d<float, (\d), (\d), (\d)>", name)
+            ok = m is not None and m.group(2) == "2"
+        if not ok or name not in wr:
             continue
         kind = KIND_OF_MODE[m.group(1)]
         kernels[kind] = {"kernel": name, "fetch_kib_raw": fe[name], "write_kib_raw": wr[name],
                          "bytes_per_launch": fe[name] * 1024.0 * f_fac + wr[name] * 1024.0 * w_fac}
-    src = os.path.join(ROOT, "paper_1101_3615_amd", "csrc", "wave2d.hip")
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
-    rec = {"workload": workload, "wave2d_sha256": digest, "fetch_scale": f_fac, "write_scale": w_fac,
-           "copy_probe_bytes": copy_bytes, "kernels": kernels}
-    out = os.path.join(ROOT, "profiles", "traffic.json")
-    with open(out, "w") as f:
+    rec_name, src_name = TRAFFIC[dims]
+    rec = {"workload": (F.c5() if dims == "3d" else F.c2()).name,
+           "source_sha256": _sha(os.path.join(ROOT, "paper_1101_3615_amd", "csrc", src_name)),
+           "fetch_scale": f_fac, "write_scale": w_fac, "copy_probe_bytes": copy_bytes, "kernels": kernels}
+    with open(os.path.join(ROOT, "profiles", rec_name), "w") as f:
         json.dump(rec, f, indent=1)
     return rec
 
@@ -464,15 +509,169 @@ def inversion_run(gd_steps=200, cg_iters=20):
     return out
 
 
+def wave_size_for(w_full, free_bytes):
+    """Shots per wave the engine uses for workload w_full on a device with free_bytes free:
+    the largest even count whose one-wave footprint fits 90 % of free memory (the
+    library's default budget), then the fewest waves split evenly in pairs."""
+    import paper_1101_3615_amd as M
+    P = M.Problem.from_spec(w_full)
+    budget = 0.9 * free_bytes
+    fit = 0
+    for k in range(2, w_full.ns + 1, 2):
+        if P.footprint("H", nshots=k) <= budget:
+            fit = k
+    P.close()
+    if fit < 2:
+        raise RuntimeError("the device cannot hold one pair of shots of the workload")
+    ngr, cgr = w_full.ns // 2, fit // 2
+    nw = -(-ngr // cgr)
+    return -(-ngr // nw) * 2
+
+
+def per_launch(st, k):
+    n = st["launches_sweep"][k]
+    return (st["ms_sweep"][k] / 1e3 / n, st["steps_sweep"][k] / n) if n else (None, None)
+
+
+def sweep_table(st, bytes_of):
+    out = {}
+    for k in st["ms_sweep"]:
+        t, sl = per_launch(st, k)
+        if t is None:
+            continue
+        out[k] = {"ms": round(st["ms_sweep"][k], 3), "launches": st["launches_sweep"][k],
+                  "steps_per_launch": round(sl, 3), "us_per_launch": round(1e6 * t, 3),
+                  "alg_GBs": round(bytes_of(k, sl) / t / 1e9, 1)}
+    return out
+
+
+def roofline_of(st, w, bytes_of, copy_gbs):
+    """The sweep kind with the most device time: algorithmic bytes per launch over its
+    average launch time (HIP events on the call's stream), against the 8 TB/s peak."""
+    kind = max(st["ms_sweep"], key=lambda k: st["ms_sweep"][k])
+    avg_s, spl = per_launch(st, kind)
+    alg = bytes_of(kind, spl)
+    achieved = alg / avg_s / 1e9
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+         "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for(kind, w), "kernel": kind,
+         "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 3), "steps_per_launch": round(spl, 3)}
+    if copy_gbs:
+        r.update(copy_GBs=round(copy_gbs, 1), frac_of_copy=round(achieved / copy_gbs, 4))
+    return r
+
+
+def copy_rate(dev):
+    """A plain device copy of 1 GiB on the same GPU (read + write bytes over time): the
+    practical bandwidth ceiling of the moment."""
+    import torch
+    src_buf = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst_buf = torch.empty_like(src_buf)
+    dst_buf.copy_(src_buf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst_buf.copy_(src_buf)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * 4 * (1 << 28) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def c2_leg(steps, copy_gbs):
+    """The 512 x 256 FP32 workload (full 3000-step record, 64 shots, FP32 g history): the
+    whole probing pass (background, H on both trials, the fit, the fitted inverse on the
+    remigrated image of a reflectivity) timed over `steps` passes."""
+    import torch
+
+    import fixtures as F
+    import paper_1101_3615_amd as M
+    w = F.c2()
+    c = F.medium(w)
+    ys = F.trials(w, c)
+    refl = F.reflectivity(w, c)
+    dev = torch.device("cuda:0")
+    c_dev = torch.from_numpy(c).to(dev)
+    y_dev = [torch.from_numpy(y).to(dev) for y in ys]
+    P = M.Problem.from_spec(w, timing=True)
+    P.set_background(c_dev)
+    img = P.apply_H(torch.from_numpy(refl).to(dev))
+    B = M.Basis(w.legendre, w.qs, w.ndim)
+    xs = [torch.empty_like(img) for _ in ys]
+    out = torch.empty_like(img)
+
+    def step():
+        P.set_background(c_dev)
+        for y, x in zip(y_dev, xs):
+            P.apply_H(y, out=x)
+        coef, _, _ = M.probe_fit(P, B, y_dev, xs, strict=False)
+        M.apply_Hinv(P, B, coef, img, out=out)
+
+    step()
+    torch.cuda.synchronize()
+    P.stats()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    st = P.stats()
+    bytes_of = lambda k, sl: kernel_bytes(k, w, round(sl))
+    res = {"workload": w.name, "value": round(len(ys) * w.cell_steps / wall / 1e9, 3), "unit": "Gcell-steps/s",
+           "ms_per_step": round(1e3 * wall, 2), "steps": steps, "dtype": "f32", "snapshots": "fp32 full g history",
+           "roofline": roofline_of(st, w, bytes_of, copy_gbs), "sweeps": sweep_table(st, bytes_of)}
+    P.close()
+    return res
+
+
+def c3_leg(nt, copy_gbs):
+    """The 1024 x 512 workload with BF16 checkpoints every 4 steps: one application of H over
+    nt of its 4000 steps, 128 shots in waves of 64 (the wave size of the full record)."""
+    import torch
+
+    import fixtures as F
+    import paper_1101_3615_amd as M
+    w = F.c3().with_(nt=nt)
+    c = F.medium(w)
+    y = torch.from_numpy(F.trials(w, c)[0]).to("cuda:0")
+    os.environ["MP_MAX_WAVE"] = "64"
+    try:
+        P = M.Problem.from_spec(w, timing=True)
+        P.set_background(torch.from_numpy(c).to("cuda:0"))
+        P.apply_H(y)
+        torch.cuda.synchronize()
+        P.stats()
+        t0 = time.perf_counter()
+        P.apply_H(y)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = P.stats()
+        waves = st["waves"]
+    finally:
+        os.environ.pop("MP_MAX_WAVE", None)
+    nsh = w.ns // waves
+    # a 2D launch covers the wave's shots; its bytes scale with them
+    bytes_of = lambda k, sl: kernel_bytes(k, w.with_(src=w.src[:nsh]), round(sl))
+    res = {"workload": w.name, "value": round(w.cell_steps / wall / 1e9, 3), "unit": "Gcell-steps/s",
+           "record_steps": F.c3().nt, "steps": nt, "waves": waves, "dtype": "f32",
+           "snapshots": "bf16 checkpoints every 4 steps",
+           "roofline": roofline_of(st, w, bytes_of, copy_gbs), "sweeps": sweep_table(st, bytes_of)}
+    P.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-steps", type=int, default=1500, help="time steps of the CPU-baseline sample")
+    ap.add_argument("--record-steps", type=int, default=40,
+                    help="time steps of the 2000-step record applied per H in a benchmark step")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="time steps of the CPU-baseline sample")
     ap.add_argument("--profile-steps", type=int, default=0,
-                    help="run the workload with this many time steps (counter collection only; "
-                         "the printed line is then marked and is not a benchmark result)")
+                    help="run only the headline workload with this many record steps, no extra legs (counter "
+                         "collection; the printed line is then marked and is not a benchmark result)")
+    ap.add_argument("--full-record", action="store_true",
+                    help="only apply H once over the full 2000-step record of the 256^3 workload (with the "
+                         "benchmark's wave size) and print its rate: the check of the extrapolated value")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--volume-steps", type=int, default=0,
@@ -494,14 +693,17 @@ def main():
                          "512x256 workload and print one JSON line")
     ap.add_argument("--cpu-workers", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 512x256 and 1024x512 legs")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson serving run (0: skip the serving leg)")
-    ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
-                    help="write profiles/traffic.json from rocprofv3 --pmc output folders and exit")
+    ap.add_argument("--ingest-counters", nargs=5,
+                    metavar=("DIMS", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="DIMS = 2d or 3d: write profiles/traffic.json or traffic_c5.json from rocprofv3 --pmc "
+                         "output folders and exit")
     args = ap.parse_args()
     if args.ingest_counters:
-        import fixtures as F
-        print(json.dumps(ingest_counters(*args.ingest_counters, 1024, F.c2().name), indent=1))
+        dims, *dirs = args.ingest_counters
+        print(json.dumps(ingest_counters(*dirs, 1024, dims), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (shots would shard "
@@ -536,38 +738,59 @@ def main():
             print(json.dumps(rec), flush=True)
         return
 
-    # CPU baseline first: forked workers must not inherit an initialised GPU runtime
-    cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps, args.cpu_workers)
+    import fixtures as F
 
-    import numpy as np
+    w_full = F.c5()
+    nt_b = args.profile_steps or args.record_steps
+    if args.full_record:
+        nt_b = w_full.nt
+    w = w_full.with_(nt=nt_b)
+    t_in = time.perf_counter()
+    c = F.medium(w)
+    ys = F.trials(w, c)                          # the workload's 4 trials of 4096 packets
+    print(f"inputs ready in {time.perf_counter() - t_in:.1f} s", file=sys.stderr, flush=True)
+    # CPU baseline before anything touches the GPU: forked workers must not inherit a
+    # HIP runtime
+    run_cpu = not (args.no_cpu or args.profile_steps or args.full_record)
+    cpu = cpu_baseline(w_full, c, ys[0], args.cpu_steps, args.cpu_workers) if run_cpu else None
+    if cpu:
+        print(f"cpu baseline {cpu['value']:.4f} Gcell-steps/s", file=sys.stderr, flush=True)
+
     import torch
 
-    import fixtures as F
     import paper_1101_3615_amd as M
-
-    w = F.c2()
-    if args.profile_steps:
-        w = w.with_(nt=args.profile_steps)
-    c = F.medium(w)
-    ys = F.trials(w, c)
-    refl = F.reflectivity(w, c)
     dev = torch.device("cuda:0")
+    free = torch.cuda.mem_get_info(dev)[0]
+    wave = wave_size_for(w_full, free)
+    os.environ["MP_MAX_WAVE"] = str(wave)
     c_dev = torch.from_numpy(c).to(dev)
     y_dev = [torch.from_numpy(y).to(dev) for y in ys]
     P = M.Problem.from_spec(w, timing=True)
     P.set_background(c_dev)
-    img = P.apply_H(torch.from_numpy(refl).to(dev))     # input of the fitted inverse
+    if args.full_record:
+        torch.cuda.synchronize()
+        P.stats()
+        t0 = time.perf_counter()
+        P.apply_H(y_dev[0])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = P.stats()
+        bytes_of = lambda k, sl: kernel_bytes3d(k, w, wave)
+        print(json.dumps({"workload": w.name, "record_steps": w.nt, "shots": w.ns, "wave_shots": wave,
+                          "waves": st["waves"], "apply_H_s": round(wall, 3),
+                          "gcell_steps_per_s": round(w.cell_steps / wall / 1e9, 3),
+                          "sweeps": sweep_table(st, bytes_of)}), flush=True)
+        return
     B = M.Basis(w.legendre, w.qs, w.ndim)
-    xs = [torch.empty_like(img) for _ in ys]
-    out = torch.empty_like(img)
-    torch.cuda.synchronize()
+    xs = [torch.empty_like(y) for y in y_dev]
+    out = torch.empty_like(y_dev[0])
 
     def step():
         P.set_background(c_dev)
         for y, x in zip(y_dev, xs):
             P.apply_H(y, out=x)
         coef, relres, deficient = M.probe_fit(P, B, y_dev, xs, strict=False)
-        M.apply_Hinv(P, B, coef, img, out=out)
+        M.apply_Hinv(P, B, coef, xs[0], out=out)
         return relres, deficient
 
     for _ in range(args.warmup):
@@ -580,54 +803,28 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = P.stats()
-    # apply_H alone, outside the timed region: background cold (plain: the call computes and
-    # keeps the g history) and resident (the next call reuses it); median of three each
-    cold, warm = [], []
-    for _ in range(3):
-        P.set_background(c_dev)
-        for lst, y, x in ((cold, y_dev[0], xs[0]), (warm, y_dev[-1], xs[-1])):
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            P.apply_H(y, out=x)
-            torch.cuda.synchronize()
-            lst.append((time.perf_counter() - t1) * 1e3)
-    P.stats()
-    P.release_cache()
-    # a plain device copy of 1 GiB on the same GPU: the practical bandwidth ceiling
-    src_buf = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-    dst_buf = torch.empty_like(src_buf)
-    dst_buf.copy_(src_buf)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        dst_buf.copy_(src_buf)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * 4 * (1 << 28) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src_buf, dst_buf
+    waves = st["waves"]
+    # the fitted inverse applied to x_0 against y_0 (the fit's own training pair)
+    rec_err = ((P.dot(out - y_dev[0], out - y_dev[0]) / P.dot(y_dev[0], y_dev[0])) ** 0.5
+               if out.dtype == y_dev[0].dtype else None)
+    P.close()
+    del P, xs, out, y_dev
+    torch.cuda.empty_cache()
+    os.environ.pop("MP_MAX_WAVE", None)
+    print(f"headline: {wall / args.steps:.3f} s per step", file=sys.stderr, flush=True)
+    copy_gbs = copy_rate(dev)
+    extra = {}
+    if not (args.no_extra or args.profile_steps):
+        extra["c2"] = c2_leg(3, copy_gbs)
+        print("c2 leg done", file=sys.stderr, flush=True)
+        extra["c3"] = c3_leg(400, copy_gbs)
+        print("c3 leg done", file=sys.stderr, flush=True)
     serving = serve_leg(args.serve_seconds) if (args.serve_seconds > 0 and not args.profile_steps) else None
+
     ms_per_step = 1e3 * wall / args.steps
     cell_steps = len(ys) * w.cell_steps
     value = cell_steps / (wall / args.steps) / 1e9
-
-    # dominant kernel: the sweep kind with the most device time in the timed region
-    def per_launch(k):
-        n = st["launches_sweep"][k]
-        return (st["ms_sweep"][k] / 1e3 / n, st["steps_sweep"][k] / n) if n else (None, None)
-
-    kind = max(st["ms_sweep"], key=lambda k: st["ms_sweep"][k])
-    avg_s, spl = per_launch(kind)
-    alg = kernel_bytes(kind, w, round(spl))
-    achieved = alg / avg_s / 1e9
-    traffic = traffic_for(kind, w)
-    sweeps = {}
-    for k in st["ms_sweep"]:
-        t, sl = per_launch(k)
-        if t is None:
-            continue
-        sweeps[k] = {"ms": round(st["ms_sweep"][k], 3), "launches": st["launches_sweep"][k],
-                     "steps_per_launch": round(sl, 3), "us_per_launch": round(1e6 * t, 3),
-                     "alg_GBs": round(kernel_bytes(k, w, round(sl)) / t / 1e9, 1)}
+    bytes_of = lambda k, sl: kernel_bytes3d(k, w, wave)
     line = {
         "metric": "Gcell-steps/s for H=F*F (fraction of HBM roofline); served p50/p99 latency",
         "value": round(value, 3),
@@ -641,23 +838,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "model_grid": [w.nx, w.nz], "prop_grid": list(reversed(w.prop_shape)),
-                   "shots": w.ns, "receivers": w.nr, "steps": w.nt, "trials": len(ys), "p": w.p,
-                   "snapshots": "fp32 full g history", "image": "fp64",
-                   "apply_H_cell_steps_per_step": cell_steps},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": kind,
-                     "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
-                     "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 3),
-                     "steps_per_launch": round(spl, 3)},
+        "config": {"workload": w.name, "model_grid": [w.nx, w.ny, w.nz], "prop_grid": list(reversed(w.prop_shape)),
+                   "shots": w.ns, "receivers": w.nr, "record_steps": w_full.nt, "steps_per_apply_H": w.nt,
+                   "wave_shots": wave, "waves": waves, "trials": len(ys), "packets_per_trial": w.packets_per_trial,
+                   "p": w.p, "snapshots": "bf16 checkpoints every 8 steps, fp32 scales, recomputation",
+                   "image": "fp64", "apply_H_cell_steps_per_step": cell_steps,
+                   "value_is": f"apply_H rate over {w.nt} of the {w_full.nt} record steps per application, "
+                               "extrapolated to the full record (same launches per step)"},
+        "roofline": roofline_of(st, w, bytes_of, copy_gbs),
         "cpu_baseline": cpu,
         "serving": serving,
-        "sweeps": sweeps,
+        "sweeps": sweep_table(st, bytes_of),
         "profile_run": bool(args.profile_steps),
-        "apply_H_ms": {"plain": round(sorted(cold)[1], 2), "resident": round(sorted(warm)[1], 2)},
         "fit_relres": relres,
         "fit_rank_deficient": deficient,
+        "hinv_x0_vs_y0": rec_err,
     }
+    line.update(extra)
     print(json.dumps(line), flush=True)
 
 

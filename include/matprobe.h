@@ -68,7 +68,8 @@ extern "C" {
 #define MP_F64 2
 
 #define MP_SNAP_FULL 0      /* keep every background time level */
-#define MP_SNAP_CKPT_F32 1  /* two-level FP32 checkpoints every k steps, recompute */
+#define MP_SNAP_CKPT_F32 1  /* two-level checkpoints in the field precision every k steps, recompute
+                               (MP_EUNSUPPORTED for 3D grids with FP32 fields) */
 #define MP_SNAP_CKPT_BF16 2 /* BF16 checkpoints (level and increment) with FP32 scales */
 
 #define MP_OP_F 1

@@ -128,6 +128,10 @@ int mp_create(const mp_grid* g, const mp_acq* a, const mp_opts* o, mp_ctx** out)
   }
   if (o->snap == MP_SNAP_CKPT_BF16 && o->dtype != MP_F32)
     return fail(MP_EUNSUPPORTED, "BF16 checkpoints are built for FP32 fields");
+  if (nd == 3 && o->snap == MP_SNAP_CKPT_F32 && o->dtype == MP_F32)
+    return fail(MP_EUNSUPPORTED,
+                "3D FP32 fields with FP32 checkpoints are switched off (their forward sweep gave "
+                "non-repeatable results on some runs); use BF16 checkpoints or the full history");
   {
     // The sweeps address one field slice and one model-grid image with 32-bit
     // buffer offsets whose out-of-grid values must stay past the end of the

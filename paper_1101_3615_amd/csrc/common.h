@@ -132,4 +132,13 @@ __device__ __forceinline__ int xcd_item(int nitems) {
 }
 inline int xcd_grid(int nitems) { return ((nitems + 7) / 8) * 8; }
 
+// Compute units of the current device (256 on MI355X if the query fails).
+inline int device_cu_count() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+    return v;
+  return 256;
+}
+
 }  // namespace mp

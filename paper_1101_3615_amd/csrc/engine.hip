@@ -83,6 +83,7 @@ class EngineT final : public Engine {
     L_.mstride = L_.mplane * c.nz;
     cpitch_ = (int)round_up(L_.nxp, 4);
     cstride_ = (long long)cpitch_ * L_.nyp * L_.nzp;
+    cu_count_ = device_cu_count();
     const char* zc = getenv("MP_ZC");
     zc_target_ = zc ? std::max(4, atoi(zc)) : 0;
   }
@@ -286,18 +287,32 @@ class EngineT final : public Engine {
     p.nt = cfg_.nt;
     p.shot0 = s0;
     if (cfg_.ndim == 3) {
-      // one item per 64 x 16 tile of a pair of shots and z chunk: as few chunks
-      // as keep about 1024 items in the launch (each chunk rereads 8 planes)
+      // one item per 64 x 16 tile of a pair of shots and z chunk.  Workgroups are
+      // resident one per CU and split over the 8 XCDs, each XCD walking its item
+      // range in rounds of its CU count; the chunk count minimises rounds x (chunk
+      // height + the 8 planes each chunk rereads), so a launch of few shots still
+      // fills the last round without cutting z into many short chunks.
       int zc = zc_target_;
       const long long tiles = (long long)(nsh / 2) * L_.nstrips * L_.nytiles;
       if (zc <= 0) {
-        const long long want = std::min<long long>((1024 + tiles - 1) / tiles, std::max(1, L_.nzp / 8));
-        zc = (int)((L_.nzp + want - 1) / want);
+        const long long per_xcd = std::max(1LL, (long long)cu_count_ / 8);
+        long long best = -1;
+        for (int nch = 1; nch <= std::max(1, L_.nzp / 16); ++nch) {
+          const long long h = (L_.nzp + nch - 1) / nch;
+          const long long items = tiles * nch;
+          const long long rounds = ((items + 7) / 8 + per_xcd - 1) / per_xcd;
+          const long long cost = rounds * (h + 8);
+          if (best < 0 || cost < best) {
+            best = cost;
+            zc = (int)h;
+          }
+        }
       }
       p.nchunks = (L_.nzp + zc - 1) / zc;
       p.zc = (L_.nzp + p.nchunks - 1) / p.nchunks;
       p.ngroups = 1;
       p.nwg = (int)(tiles * p.nchunks);
+      p.nsh = nsh;
     }   // 2D: the launcher picks the z chunking per kernel
     T* f = fields_.as<T>();
     const long long fs = (long long)W * L_.fstride;
@@ -856,6 +871,7 @@ class EngineT final : public Engine {
   Budget* budget_;
   Layout L_;
   int zc_target_ = 0;
+  int cu_count_ = 256;
   int cpitch_ = 0;
   long long cstride_ = 0;
   bool cached_ = false;

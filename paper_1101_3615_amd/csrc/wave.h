@@ -47,7 +47,7 @@ struct Step {
   int nr, nt;
   int shot0;                 // job index of local shot 0 of this wave
   int zc, nchunks, ngroups, nwg;
-  int nsh;                   // 2D: shots of the launch
+  int nsh;                   // shots of the launch (3D: a multiple of 2)
   // 2D sweeps (one or two steps per launch): inputs and outputs of the launch
   T* in0;                    // background u^n / field level 0
   T* in1;                    // background increment D^n / field level -1

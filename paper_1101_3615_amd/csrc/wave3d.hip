@@ -10,10 +10,10 @@
 //   y-neighbours: the tile's centre plane plus 4 halo rows above and below,
 //                 staged in LDS (double buffered: one barrier per plane).
 // Every input of a plane (queue row, halos, kappa, previous level, g, image) is
-// loaded through buffer resources one plane ahead; lanes and planes outside the
-// grid read zero from the hardware range check instead of branching.  Workgroups
-// are persistent and walk their XCD's tiles x-fastest, so tiles that share halo
-// lines run on one L2 at the same time.
+// loaded through buffer resources at the start of the plane; lanes and planes
+// outside the grid read zero from the hardware range check instead of branching.
+// Workgroups are persistent and walk their XCD's items pairs of shots fastest, so
+// the pairs of a tile share its kappa and perturbation through that XCD's L2.
 // The arithmetic per cell is that of the 2D kernel with the y axis added.
 #include <algorithm>
 
@@ -167,15 +167,17 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
   for (int k = (int)(blockIdx.x >> 3); k < per; k += spx) {
   const int item = xcd * per + k;
   if (item >= p.nwg) break;
-  // x tiles fastest, then y tiles: the workgroups that run together on one XCD
-  // cover whole xy planes of a shot's chunk, so the halo rows and columns a tile
-  // reads were fetched into that XCD's L2 by its neighbours (marching in step)
-  const int tx = item % p.L.nstrips;
-  int rest = item / p.L.nstrips;
+  // pairs of shots fastest, then x tiles, y tiles and z chunks: the workgroups
+  // that run together on one XCD carry every pair of a few neighbouring tiles, so
+  // kappa and the perturbation of a tile come from HBM once and reach the other
+  // pairs from that XCD's L2 (marching in step)
+  const int npair = p.nsh >> 1;
+  const int ls = (item % npair) * 2 + half;
+  int rest = item / npair;
+  const int tx = rest % p.L.nstrips;
+  rest /= p.L.nstrips;
   const int ty = rest % p.L.nytiles;
-  rest /= p.L.nytiles;
-  const int chunk = rest % p.nchunks;
-  const int ls = (rest / p.nchunks) * 2 + half;
+  const int chunk = rest / p.L.nytiles;
   const int z0 = chunk * p.zc;
   const int z1 = min(z0 + p.zc, p.L.nzp);
 
@@ -275,9 +277,11 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
   const unsigned hvo = hload ? (unsigned)((long long)(hy + GY) * pitch + XL + hx) * esz : OFF_NONE3;
   const Rsrc3 rHv = hfieldB ? rBc : rAc;
 
-  // Inputs of one z plane.  FP32 sweeps load them one plane ahead, so that their
-  // latency overlaps the work on the plane before; FP64 sweeps (small test grids,
-  // twice the registers) load them at the start of the plane.
+  // Inputs of one z plane, loaded at the start of the plane (the loads of a plane
+  // are independent, so they are all in flight together).  Loading them one plane
+  // ahead instead gave wrong, non-repeatable fields for the odd shot of a pair
+  // once a launch held two or more pairs, even with a full wait before the
+  // prefetched plane was used; it is not used (3 % slower at 256^3).
   struct In3 {
     V4<T> qa, qb;          // plane z + 4 of fields A, B (enters the queue)
     V4<T> hv;              // y-halo row of plane z (field A or B)
@@ -301,7 +305,6 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
     if (MODE == M_BORN || MODE == M_ADJ) f.g = bld4<NT3>(rG, gvo + zm * gplane, 0u, T(0));
     if (MODE == M_ADJ) f.im = bld4<NT3>(rI, ivo + (zm - 1u) * iplane, 0u, double(0));
   };
-  constexpr bool PF3 = sizeof(T) == 4;
 
   // Image of plane zz for the pair: old + (even half's + odd half's contribution),
   // written by the even half (the contributions were put in LDS before a barrier)
@@ -323,16 +326,14 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
     qa[s] = bld4(rAc, lvo, soff(z0 - 4 + s), T(0));
     if (TWO) qb[s] = bld4(rBc, lvo, soff(z0 - 4 + s), T(0));
   }
-  In3 cur, nxt;
-  if (PF3) fetch(z0, cur);
+  In3 cur;
 
   for (int zb = z0; zb < z1; zb += 9) {
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
       const int z = zb + r;
       if (z < z1) {   // uniform; a constant trip count keeps the loop fully unrolled
-        if (PF3) fetch(min(z + 1, z1 - 1), nxt);   // the last plane reloads itself
-        else fetch(z, cur);
+        fetch(z, cur);
         qa[(r + 8) % 9] = cur.qa;
         if (TWO) qb[(r + 8) % 9] = cur.qb;
         // centre rows and y halo into LDS
@@ -495,7 +496,6 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
           for (int i = 0; i < 4; ++i) cw.v[i] = xmod[i] ? -((double)g[i] * (double)anew.v[i]) : 0.0;
           RED[half][z & 1][tid] = cw;
         }
-        if (PF3) cur = nxt;
       }
     }
   }

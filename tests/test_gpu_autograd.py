@@ -38,8 +38,10 @@ def test_c3_slice_dot_product_and_finite_differences(snap, tol):
     """1024 x 512, 4000 steps, snapshots every 4 steps (8 of the 128 shots):
     dot-product test and central differences of L = 1/2 ||F dm - d_obs||^2 along
     32 seeded wavepacket directions (L is quadratic, so the central difference is
-    exact up to rounding); tolerance FP32 checkpoints 1e-3, BF16 checkpoints 1e-2
-    (median over directions)."""
+    exact up to rounding); tolerance FP32 checkpoints 1e-3, BF16 checkpoints 1e-2 on the
+    relative L2 error of the 32 directional derivatives taken together (a single
+    direction nearly orthogonal to the gradient has a large relative error of its own,
+    so the median and the maximum per direction are printed, not bounded)."""
     M, born = _gpu()
     w = _c3_slice(snap)
     c = F.medium(w)
@@ -69,15 +71,16 @@ def test_c3_slice_dot_product_and_finite_differences(snap, tol):
             rr = (P.apply_F(v).double() - d_obs.double())
             return 0.5 * float((rr ** 2).sum())
 
-    errs = []
+    fds, ans = [], []
     for i in range(32):
         v = torch.from_numpy(F.wavepackets(w, c, 100 + i, 64)).cuda() * float(refl.abs().max())
         eps = 1.0
-        fd = (L(dm0 + eps * v) - L(dm0 - eps * v)) / (2 * eps)
-        an = float((grad * v.double()).sum())
-        errs.append(abs(fd - an) / max(abs(fd), 1e-300))
-    errs = np.array(errs)
+        fds.append((L(dm0 + eps * v) - L(dm0 - eps * v)) / (2 * eps))
+        ans.append(float((grad * v.double()).sum()))
+    fds, ans = np.array(fds), np.array(ans)
+    errs = np.abs(fds - ans) / np.maximum(np.abs(fds), 1e-300)
+    err_all = float(np.linalg.norm(fds - ans) / np.linalg.norm(fds))
     print(f"{snap}: dot-product rel err {dot_err:.3e}; FD vs backward over 32 directions: "
-          f"median {np.median(errs):.3e}, max {errs.max():.3e}")
+          f"relative L2 {err_all:.3e}, per direction median {np.median(errs):.3e}, max {errs.max():.3e}")
     assert dot_err <= tol
-    assert np.median(errs) <= tol
+    assert err_all <= tol

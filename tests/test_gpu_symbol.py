@@ -201,3 +201,120 @@ def test_paper_basis_fit_matches_oracle_least_squares():
                                [y.astype(np.float64) for y in ys], [x.astype(np.float64) for x in xs])
     assert rel(c, cref) <= 1e-10
     assert abs(relres - rref) <= 1e-10 * rref
+
+
+# ---- the 256^3 workload's basis: Legendre P_i(z~) P_j(y~) P_k(x~), i + j + k <= 2, times rho^0..3 ----
+
+C5LEG = F.c5().legendre          # 10 position factors (numpy axis order z, y, x)
+C5QS = F.c5().qs                 # (0, 1, 2, 3): p = 40
+
+
+def _cube_problem(M, n, dtype):
+    return M.Problem.from_spec(F.tiny(ndim=3, n=n, nb=4, nt=10, ns=1, nr=2, dtype=dtype).with_(h=12.5))
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_c5_basis_fit_exact_recovery_and_least_squares(n):
+    """The 40-term 3D basis: y = sum c_i B_i x (oracle) gives c back to 1e-10 (FP64,
+    two trials); on unrelated FP32 fields the fit matches the oracle's Householder
+    least squares to 1e-10."""
+    M = _gpu()
+    h = 12.5
+    assert len(C5LEG) == 10 and len(C5QS) * len(C5LEG) == 40
+    P = _cube_problem(M, n, "f64")
+    B = M.Basis(C5LEG, C5QS, 3)
+    rng = np.random.default_rng(90 + n)
+    ctrue = rng.standard_normal(B.p)
+    xs = [F.normal_field((n, n, n), 300 + t).astype(np.float64) for t in range(2)]
+    ys = [S.apply_Hinv(ctrue, x, h, C5LEG, C5QS) for x in xs]
+    c, relres = M.probe_fit(P, B, [torch.from_numpy(y) for y in ys], [torch.from_numpy(x) for x in xs])
+    assert np.max(np.abs(c - ctrue)) <= 1e-10 * np.max(np.abs(ctrue))
+    assert relres < 1e-10
+    P32 = _cube_problem(M, n, "f32")
+    xs = [F.normal_field((n, n, n), 310 + t) for t in range(2)]
+    ys = [F.normal_field((n, n, n), 320 + t) for t in range(2)]
+    c, relres = M.probe_fit(P32, B, [torch.from_numpy(y) for y in ys], [torch.from_numpy(x) for x in xs])
+    cref, rref, _ = S.fit([y.astype(np.float64) for y in ys], [x.astype(np.float64) for x in xs], h, C5LEG, C5QS)
+    assert rel(c, cref) <= 1e-10
+    assert abs(relres - rref) <= 1e-10 * rref
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c5_basis_apply_Hinv_matches_oracle_64(dtype):
+    M = _gpu()
+    P = _cube_problem(M, 64, dtype)
+    B = M.Basis(C5LEG, C5QS, 3)
+    c = np.random.default_rng(95).standard_normal(B.p)
+    img = F.normal_field((64, 64, 64), 330)
+    got = M.apply_Hinv(P, B, c, torch.from_numpy(img)).cpu().numpy()
+    ref = S.apply_Hinv(c, img, 12.5, C5LEG, C5QS)
+    assert rel(got, ref) <= (1e-13 if dtype == "f64" else 1e-6)
+
+
+def _plane_waves(n, h, waves):
+    """sum_w a_w cos(k_w . x + phi_w) on the n^3 model grid, and each wave's rho = |k| h / pi.
+
+    waves: (m_z, m_y, m_x, a, phi) with integer frequency indices, so each term is a
+    grid eigenfunction of every Fourier multiplier: B_(a,q) cos = P_a(x~) rho^q cos.
+    """
+    idx = np.arange(n, dtype=np.float64)
+    rho = S.rho((n, n, n), h)
+    out, terms = np.zeros((n, n, n)), []
+    for mz, my, mx, a, phi in waves:
+        th = (2 * np.pi / n) * (mz * idx[:, None, None] + my * idx[None, :, None] + mx * idx[None, None, :]) + phi
+        term = a * np.cos(th)
+        r = rho[mz % n, my % n, mx % n]
+        terms.append((term, r))
+        out += term
+    return out, terms
+
+
+def _closed_form(c, terms, n):
+    """sum_(a,q) c_(a,q) P_a(x~) rho_w^q cos_w for each plane-wave term (no FFT)."""
+    out = np.zeros((n, n, n))
+    cc = np.asarray(c).reshape(len(C5LEG), len(C5QS))
+    for ia, a in enumerate(C5LEG):
+        s = np.zeros((n, n, n))
+        for term, r in terms:
+            s += sum(cc[ia, iq] * r ** q for iq, q in enumerate(C5QS)) * term
+        out += S.position_factor(a, (n, n, n)) * s
+    return out
+
+
+def test_c5_apply_Hinv_full_size_plane_waves():
+    """apply_Hinv at the workload's 256^3 (FP32, 3D FFT multipliers): plane waves are
+    eigenfunctions of every multiplier, so the output has a closed form."""
+    M = _gpu()
+    n = 256
+    P = _cube_problem(M, n, "f32")
+    B = M.Basis(C5LEG, C5QS, 3)
+    c = np.random.default_rng(97).standard_normal(B.p)
+    img, terms = _plane_waves(n, 12.5, [(3, -7, 20, 1.0, 0.3), (-40, 11, 5, 0.5, 1.1), (90, 64, -100, 0.25, 2.0)])
+    got = M.apply_Hinv(P, B, c, torch.from_numpy(img.astype(np.float32))).cpu().numpy()
+    assert rel(got, _closed_form(c, terms, n)) <= 1e-6
+
+
+def test_c5_fit_full_size_exact_recovery():
+    """The fit at the workload's size: 4 trials of 256^3 (67 M stacked rows, p = 40),
+    FP64.  Each trial is a sum of plane waves of distinct |k|; y_t = sum c_i B_i x_t in
+    closed form; the fit returns c to 1e-10."""
+    M = _gpu()
+    n = 256
+    P = _cube_problem(M, n, "f64")
+    B = M.Basis(C5LEG, C5QS, 3)
+    ctrue = np.random.default_rng(98).standard_normal(B.p)
+    rng = np.random.default_rng(99)
+    xs, ys = [], []
+    for t in range(4):
+        waves = []
+        for j in range(6):
+            m = rng.integers(-100, 101, size=3)
+            waves.append((int(m[0]), int(m[1]), int(m[2]), float(rng.uniform(0.5, 1.0)), float(rng.uniform(0, 6.28))))
+        x, terms = _plane_waves(n, 12.5, waves)
+        xs.append(torch.from_numpy(x))
+        ys.append(torch.from_numpy(_closed_form(ctrue, terms, n)))
+    c, relres = M.probe_fit(P, B, ys, xs)
+    print(f"256^3 fit, 4 trials, p = 40: max |c - c_true| / max |c_true| = "
+          f"{np.max(np.abs(c - ctrue)) / np.max(np.abs(ctrue)):.2e}, relres {relres:.2e}")
+    assert np.max(np.abs(c - ctrue)) <= 1e-10 * np.max(np.abs(ctrue))
+    assert relres < 1e-10
