@@ -243,6 +243,20 @@ int mp_apply_Hinv(mp_ctx* ctx, const mp_basis* basis, const double* c, const voi
  * (results repeat bit for bit).  Synchronises the stream. */
 int mp_vec_dot(mp_ctx* ctx, long long n, const void* a_dev, const void* b_dev, double* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving or solver loops, harnesses that forbid hipMalloc): mp_vec_dot with the result
+ * left on the device and nothing allocated.  *out_dev (device, one double) = sum_i a_i b_i,
+ * computed by the same kernels in the same order as mp_vec_dot (equal bits).  The partial
+ * sums live in a static 8 KiB device array, one per GPU, resolved at mp_create (or at the
+ * first call on another device) and held until the process ends; the call allocates
+ * nothing, does not synchronise and is stream-ordered.  Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (other streams, other threads) race: order
+ * them on one stream.  n = 0 writes 0.  MP_EINVAL for n < 0, n > MP_NOALLOC_MAX_N or a null
+ * pointer. */
+#define MP_NOALLOC_MAX_N (1LL << 40)
+int mp_vec_dot_noalloc(mp_ctx* ctx, long long n, const void* a_dev, const void* b_dev, double* out_dev,
+                       void* stream);
+
 /* y = alpha x + beta y, computed in FP64 and rounded to the field precision (x and y may
  * be the same buffer).  With beta = 0, y is overwritten and not read, so it may hold
  * anything (NaN included).  MP_ENUMERIC for a non-finite alpha or beta. */

@@ -34,7 +34,7 @@ EXPORTS = [
     "mp_basis_destroy", "mp_probe_fit", "mp_apply_Hinv", "mp_last_stats", "mp_strerror",
     "mp_last_error", "mp_curvelet_create", "mp_curvelet_destroy", "mp_curvelet_wedges", "mp_curvelet_norms",
     "mp_illumination", "mp_curvelet_synthesis", "mp_curvelet_analysis", "mp_curvelet_sign_threshold",
-    "mp_vec_dot", "mp_vec_axpby",
+    "mp_vec_dot", "mp_vec_dot_noalloc", "mp_vec_axpby",
     "mp_velocity_update",
 ]
 
@@ -132,6 +132,7 @@ def lib():
     L.mp_curvelet_analysis.argtypes = [vp, vp, vp, vp, vp]
     L.mp_curvelet_sign_threshold.argtypes = [vp, vp, vp, ctypes.c_double, vp]
     L.mp_vec_dot.argtypes = [vp, ctypes.c_longlong, vp, vp, dp, vp]
+    L.mp_vec_dot_noalloc.argtypes = [vp, ctypes.c_longlong, vp, vp, vp, vp]
     L.mp_vec_axpby.argtypes = [vp, ctypes.c_longlong, ctypes.c_double, vp, ctypes.c_double, vp, vp]
     L.mp_velocity_update.argtypes = [vp, vp, vp, vp]
     L.mp_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]

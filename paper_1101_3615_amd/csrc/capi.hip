@@ -180,6 +180,12 @@ int mp_create(const mp_grid* g, const mp_acq* a, const mp_opts* o, mp_ctx** out)
     delete ctx;
     return MP_ENOMEM;
   }
+  const int src = vec_scratch_init();   // the allocation-free entry point's scratch, this device
+  if (src) {
+    delete ctx->eng;
+    delete ctx;
+    return src;
+  }
   *out = ctx;
   return MP_OK;
 }
@@ -435,6 +441,16 @@ int mp_vec_dot(mp_ctx* ctx, long long n, const void* a_dev, const void* b_dev, d
   }
   if (!a_dev || !b_dev) return fail(MP_EINVAL, "null buffer");
   return finish(ctx, vec_dot(ctx, n, a_dev, b_dev, out, (hipStream_t)stream));
+}
+
+int mp_vec_dot_noalloc(mp_ctx* ctx, long long n, const void* a_dev, const void* b_dev, double* out_dev,
+                       void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!out_dev || n < 0) return fail(MP_EINVAL, "bad vec_dot_noalloc arguments");
+  if (n > MP_NOALLOC_MAX_N) return fail(MP_EINVAL, "vec_dot_noalloc: n beyond MP_NOALLOC_MAX_N");
+  if (n > 0 && (!a_dev || !b_dev)) return fail(MP_EINVAL, "null buffer");
+  return finish(ctx, vec_dot_noalloc(ctx, n, a_dev, b_dev, out_dev, (hipStream_t)stream));
 }
 
 int mp_vec_axpby(mp_ctx* ctx, long long n, double alpha, const void* x_dev, double beta, void* y_dev, void* stream) {

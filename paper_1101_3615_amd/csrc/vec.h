@@ -13,6 +13,11 @@ int vec_dot(mp_ctx* ctx, long long n, const void* a, const void* b, double* out,
 int vec_axpby(mp_ctx* ctx, long long n, double alpha, const void* x, double beta, void* y, hipStream_t s);
 // c <- (c^-2 + dm)^(-1/2) on the model grid; MP_ENUMERIC (c untouched) if some c^-2 + dm <= 0
 int velocity_update(mp_ctx* ctx, void* c, const void* dm, hipStream_t s);
+// Resolve this device's copy of the allocation-free dot product's scratch (current device).
+int vec_scratch_init();
+// *out_dev (device) = sum_i a_i b_i as vec_dot, with the partial sums in the static
+// scratch: no allocation, no synchronisation
+int vec_dot_noalloc(mp_ctx* ctx, long long n, const void* a, const void* b, double* out_dev, hipStream_t s);
 void vec_release(mp_ctx* ctx);
 
 }  // namespace mp

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "prep.h"
@@ -154,6 +155,70 @@ static int vel_t(mp_ctx* ctx, void* c, const void* dm, hipStream_t s) {
 
 int velocity_update(mp_ctx* ctx, void* c, const void* dm, hipStream_t s) {
   return ctx->cfg.dtype == MP_F32 ? vel_t<float>(ctx, c, dm, s) : vel_t<double>(ctx, c, dm, s);
+}
+
+// ---- the allocation-free dot product ----
+// Its only device memory beyond the caller's buffers is the VBLOCKS partial sums, held
+// in this file-scope array: one copy per GPU, kept until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is a stand-in, not a device
+// address): the address is resolved once per device with hipGetSymbolAddress, with that
+// device current, and the kernels take the resolved pointer.
+constexpr int SCRATCH_DOUBLES = VBLOCKS;   // 8 KiB
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[MAX_DEVICES] = {};
+
+int vec_scratch_init() {
+  int dev = 0;
+  VC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    set_error("device index beyond the scratch table");
+    return MP_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return MP_EDEVICE;
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  return MP_OK;
+}
+
+int vec_dot_noalloc(mp_ctx* ctx, long long n, const void* a, const void* b, double* out_dev, hipStream_t s) {
+  static_assert(VBLOCKS <= SCRATCH_DOUBLES, "the partial sums of one call must fit the scratch");
+  int dev = 0;
+  VC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    set_error("device index beyond the scratch table");
+    return MP_EUNSUPPORTED;
+  }
+  double* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    part = g_scratch_ptr[dev];
+  }
+  if (!part) {   // a context created on another device: resolve this device's copy now
+    int rc = vec_scratch_init();
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    part = g_scratch_ptr[dev];
+  }
+  // the same two kernels, grid and summation order as vec_dot: equal results, bit for bit
+  if (ctx->cfg.dtype == MP_F32)
+    hipLaunchKernelGGL(k_dot_part<float>, dim3(VBLOCKS), dim3(VB), 0, s, static_cast<const float*>(a),
+                       static_cast<const float*>(b), n, part);
+  else
+    hipLaunchKernelGGL(k_dot_part<double>, dim3(VBLOCKS), dim3(VB), 0, s, static_cast<const double*>(a),
+                       static_cast<const double*>(b), n, part);
+  VC_LAUNCH();
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(VB), 0, s, part, out_dev);
+  VC_LAUNCH();
+  return MP_OK;
 }
 
 void vec_release(mp_ctx* ctx) {

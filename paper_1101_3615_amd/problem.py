@@ -167,6 +167,18 @@ class Problem:
         L.check(self._lib.mp_vec_dot(self._ctx, a.numel(), _ptr(a), _ptr(b), ctypes.byref(out), _stream(stream)))
         return out.value
 
+    def dot_noalloc(self, a, b, out, stream=None):
+        """out[0] = sum_i a_i b_i on the device, as dot() (same bits), allocating nothing and
+        not synchronising; out is a float64 device tensor of at least one element."""
+        a, b = self._vec(a, "a"), self._vec(b, "b")
+        if a.numel() != b.numel():
+            raise ValueError("dot of vectors of different sizes")
+        if not (isinstance(out, torch.Tensor) and out.device == self.device and out.dtype == torch.float64
+                and out.numel() >= 1 and out.is_contiguous()):
+            raise ValueError(f"out must be a contiguous float64 tensor on {self.device}")
+        L.check(self._lib.mp_vec_dot_noalloc(self._ctx, a.numel(), _ptr(a), _ptr(b), _ptr(out), _stream(stream)))
+        return out
+
     def axpby(self, alpha, x, beta, y, stream=None):
         """y = alpha x + beta y in place (FP64 arithmetic, rounded to the field precision);
         beta = 0 overwrites y without reading it."""
