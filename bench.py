@@ -146,11 +146,13 @@ KIND_OF_MODE = {"0": "fused", "1": "born", "2": "background", "3": "adjoint"}
 
 def serve_leg(seconds, rate=20.0, seed=13):
     """Serving workload: seeded Poisson arrivals (rate req/s) of apply_H requests
-    on the grids {256x128, 512x256, 1024x512} (steps 48/96/192) with 16/32/64
-    shots, FP32 fields and BF16 checkpoints every 4 steps.  Reports latency
-    percentiles under the offered load, and the throughput of the same requests
-    submitted at once through the continuous-batching server ("served") versus
-    one request at a time on one stream ("plain")."""
+    on the grids {256x128, 512x256, 1024x512} (records of 104/208/416 steps) with
+    16/32/64 shots, FP32 fields and BF16 checkpoints every 4 steps.  Reports
+    latency percentiles under the offered load; then the throughput of the same
+    requests, and of a stream of F, F* and H requests, submitted at once through
+    the continuous-batching server ("served": requests of one operator and shot
+    set share a background sweep) versus one request at a time on one stream
+    ("plain")."""
     import torch
 
     import fixtures as F
@@ -163,41 +165,56 @@ def serve_leg(seconds, rate=20.0, seed=13):
         groups[(nx, nz)] = g
     ex = GpuExecutor(shapes, lanes_per_shape=2)
 
-    def make_dm(r):
+    def make_x(r):
         w, c = shapes[r.shape]
+        if r.op == "Fadj":
+            return torch.from_numpy(F.bandlimited_data((len(r.shots), w.nt, w.nr), 1000 + r.rid, w.dt,
+                                                       w.f_peak)).cuda()
         return torch.from_numpy(F.wavepackets(w, c, 1000 + r.rid, max(1, w.model_cells // 4096))).cuda()
 
-    reqs = poisson_requests(rate, seconds, groups, F.SERVE_SHOTS, seed=seed, make_dm=make_dm)
-    # warm every lane once (allocations, code objects) with a one-shot request
+    # warm every lane once per operator (allocations, code objects)
     for lane in ex.lane_keys():
         w, c = shapes[lane[0]]
-        dm = torch.from_numpy(F.wavepackets(w, c, 999, 1)).cuda()
-        ex.lanes[lane]["problem"].apply_H_batch([dm], [[0]])
+        for op in ("H", "F", "Fadj"):
+            r0 = type("R", (), {"op": op, "shots": [0], "shape": lane[0], "rid": -1})()
+            ex.lanes[lane]["problem"].apply_batch(op, [make_x(r0)], [0])
     torch.cuda.synchronize()
-    srv = Server(ex, max_batch_shots=512)
+
+    def capacity(reqs):
+        for r in reqs:
+            r.arrival, r.finished = 0.0, None
+        srv = Server(ex, max_batch=16)
+        t0 = time.perf_counter()
+        srv.run(reqs)
+        torch.cuda.synchronize()
+        t_served = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for r in reqs:
+            ex.lanes[(r.shape, 0)]["problem"].apply_batch(r.op, [r.x], r.shots)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        cs = sum(r.cell_steps for r in reqs)
+        return {"requests": len(reqs), "batches": srv.nbatches,
+                "served_gcell_steps_per_s": round(cs / t_served / 1e9, 3),
+                "plain_gcell_steps_per_s": round(cs / t_plain / 1e9, 3),
+                "served_vs_plain": round(t_plain / t_served, 3)}
+
+    reqs = poisson_requests(rate, seconds, groups, F.SERVE_SHOTS, seed=seed, make_x=make_x)
+    srv = Server(ex, max_batch=16)
     done = srv.run(reqs)
     torch.cuda.synchronize()
     load = summarize(done, warmup=min(1.0, 0.1 * seconds))
-    # capacity: all requests at t = 0, batched, versus one at a time
-    for r in reqs:
-        r.arrival, r.finished = 0.0, None
-    srv2 = Server(ex, max_batch_shots=512)
-    t0 = time.perf_counter()
-    srv2.run(reqs)
-    torch.cuda.synchronize()
-    t_served = time.perf_counter() - t0
-    cs = sum(r.cell_steps for r in reqs)
-    t0 = time.perf_counter()
-    for r in reqs:
-        ex.lanes[(r.shape, 0)]["problem"].apply_H_batch([r.dm], [r.shots])
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    return {"requests": len(reqs), "rate_per_s": rate, "seconds": seconds, "batches": srv.nbatches,
-            "p50_ms": round(1e3 * load["p50_s"], 3), "p99_ms": round(1e3 * load["p99_s"], 3),
-            "offered_gcell_steps_per_s": round(load["gcell_steps_per_s"], 3),
-            "served_capacity_gcell_steps_per_s": round(cs / t_served / 1e9, 3),
-            "plain_capacity_gcell_steps_per_s": round(cs / t_plain / 1e9, 3),
-            "served_vs_plain": round(t_plain / t_served, 3)}
+    out = {"requests": len(reqs), "rate_per_s": rate, "seconds": seconds, "ops": "H",
+           "steps": {f"{nx}x{nz}": shapes[(nx, nz)][0].nt for (nx, nz) in F.SERVE_SHAPES},
+           "batches": srv.nbatches,
+           "p50_ms": round(1e3 * load["p50_s"], 3), "p99_ms": round(1e3 * load["p99_s"], 3),
+           "offered_gcell_steps_per_s": round(load["gcell_steps_per_s"], 3)}
+    out["capacity_H"] = capacity(reqs)
+    mix = poisson_requests(rate, seconds, groups, F.SERVE_SHOTS, seed=seed + 1, make_x=make_x,
+                           ops=("H", "F", "Fadj"))
+    out["capacity_F_Fadj_H"] = capacity(mix)
+    out["served_vs_plain"] = out["capacity_H"]["served_vs_plain"]
+    return out
 
 
 def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, dims):

@@ -143,8 +143,11 @@ SERVE_SHOTS = (16, 32, 64)
 
 
 def serve_steps(nx, nz):
-    """Step count scaled with the grid diagonal, 48 at 256 x 128."""
-    return int(round(48.0 * np.hypot(nx, nz) / np.hypot(256, 128)))
+    """Step count scaled with the grid diagonal: 104 at 256 x 128, the Ricker delay
+    1/f_peak = 83 ms at dt = 0.8 ms, so the wavelet's peak enters every grid (416
+    steps, 333 ms, at 1024 x 512).  Longer records would offer more work at 20
+    requests/s than one GPU serves."""
+    return int(round(104.0 * np.hypot(nx, nz) / np.hypot(256, 128)))
 
 
 def c4(nx=256, nz=128, ns=16, seed=10):

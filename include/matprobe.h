@@ -68,9 +68,12 @@ extern "C" {
 #define MP_F64 2
 
 #define MP_SNAP_FULL 0      /* keep every background time level */
-#define MP_SNAP_CKPT_F32 1  /* two-level checkpoints in the field precision every k steps, recompute
-                               (MP_EUNSUPPORTED for 3D grids with FP32 fields) */
+#define MP_SNAP_CKPT_F32 1  /* two-level checkpoints in the field precision every k steps, recompute */
 #define MP_SNAP_CKPT_BF16 2 /* BF16 checkpoints (level and increment) with FP32 scales */
+/* In the checkpoint modes F* (and the adjoint half of H) images with the recomputed
+ * background levels in the summed-by-parts form -sum_k u^k c^2 (L nu^{k+1} + R^T d^{k-1}),
+ * equal in exact arithmetic to -sum_k g^{k-1} nu^k (Sec. 1.1, F* as the transpose of F),
+ * so the checkpoint's rounding reaches the image without the Laplacian's amplification. */
 
 #define MP_OP_F 1
 #define MP_OP_FADJ 2
@@ -177,6 +180,29 @@ int mp_apply_H(mp_ctx* ctx, const void* dm_dev, void* out_dev, void* stream);
  * request in the order given).  Overwrites the resident background store. */
 int mp_apply_H_batch(mp_ctx* ctx, int nreq, const int* counts, const int* shots, const void* const* dm_dev,
                      void* const* out_dev, void* stream);
+
+/* Batched F, F* or H for serving, for requests that share one shot list (the
+ * operators of Sec. 1.1 restricted to those shots, Sec. 2): request r applies
+ * op to in_dev[r] and writes out_dev[r].
+ *   op MP_OP_F:    in = model perturbation (model layout), out = data
+ *                  [nshots][nt][nr] in the order of shots;
+ *   op MP_OP_FADJ: in = data [nshots][nt][nr], out = image (model layout);
+ *   op MP_OP_H:    in = model perturbation, out = sum over the shots of F_s* F_s in.
+ * shots: host int32 [nshots], acquisition indices (repeats allowed).  The
+ * background of each shot is propagated, and recomputed from its checkpoints,
+ * once for all nreq requests; their Born and adjoint fields run in the same
+ * launches.  Each result is bit-identical to the same request submitted alone
+ * (nreq = 1).  Device buffers are the caller's and must stay valid until the
+ * stream reaches the call's end.  All requests run in one wave: MP_ENOMEM (with
+ * the bytes needed in mp_last_error) if mp_footprint_batch exceeds the budget;
+ * MP_EINVAL for a bad op, count, shot index or null buffer; MP_ESTATE without a
+ * background.  Overwrites the resident background store. */
+int mp_apply_batch(mp_ctx* ctx, int op, int nreq, int nshots, const int* shots, const void* const* in_dev,
+                   void* const* out_dev, void* stream);
+
+/* Device bytes of mp_apply_batch for nreq requests over nshots shots, counting
+ * the context's resident state (admission control of a serving loop). */
+int mp_footprint_batch(const mp_ctx* ctx, int op, int nshots, int nreq, size_t* bytes);
 
 /* Drop the cached background wavefield and free the memory it holds. */
 int mp_release_cache(mp_ctx* ctx);

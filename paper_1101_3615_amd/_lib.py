@@ -30,7 +30,8 @@ SWEEP_KINDS = ("fused", "born", "background", "adjoint")
 
 EXPORTS = [
     "mp_create", "mp_destroy", "mp_set_background", "mp_footprint", "mp_apply_F", "mp_model",
-    "mp_apply_Fadj", "mp_apply_H", "mp_apply_H_batch", "mp_release_cache", "mp_basis_create",
+    "mp_apply_Fadj", "mp_apply_H", "mp_apply_H_batch", "mp_apply_batch", "mp_footprint_batch",
+    "mp_release_cache", "mp_basis_create",
     "mp_basis_destroy", "mp_probe_fit", "mp_apply_Hinv", "mp_last_stats", "mp_strerror",
     "mp_last_error", "mp_curvelet_create", "mp_curvelet_destroy", "mp_curvelet_wedges", "mp_curvelet_norms",
     "mp_illumination", "mp_curvelet_synthesis", "mp_curvelet_analysis", "mp_curvelet_sign_threshold",
@@ -111,6 +112,8 @@ def lib():
     L.mp_destroy.restype = None
     L.mp_set_background.argtypes = [vp, vp, vp]
     L.mp_footprint.argtypes = [vp, i, i, ctypes.POINTER(ctypes.c_size_t)]
+    L.mp_footprint_batch.argtypes = [vp, i, i, i, ctypes.POINTER(ctypes.c_size_t)]
+    L.mp_apply_batch.argtypes = [vp, i, i, i, ctypes.POINTER(ctypes.c_int), vp, vp, vp]
     L.mp_apply_H_batch.argtypes = [vp, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                    ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     for name in ("mp_apply_F", "mp_apply_Fadj", "mp_apply_H"):

@@ -128,10 +128,6 @@ int mp_create(const mp_grid* g, const mp_acq* a, const mp_opts* o, mp_ctx** out)
   }
   if (o->snap == MP_SNAP_CKPT_BF16 && o->dtype != MP_F32)
     return fail(MP_EUNSUPPORTED, "BF16 checkpoints are built for FP32 fields");
-  if (nd == 3 && o->snap == MP_SNAP_CKPT_F32 && o->dtype == MP_F32)
-    return fail(MP_EUNSUPPORTED,
-                "3D FP32 fields with FP32 checkpoints are switched off (their forward sweep gave "
-                "non-repeatable results on some runs); use BF16 checkpoints or the full history");
   {
     // The sweeps address one field slice and one model-grid image with 32-bit
     // buffer offsets whose out-of-grid values must stay past the end of the
@@ -228,6 +224,27 @@ int mp_apply_H_batch(mp_ctx* ctx, int nreq, const int* counts, const int* shots,
       if (shots[k] < 0 || shots[k] >= ctx->cfg.ns) return fail(MP_EINVAL, "shot index out of range");
   }
   return finish(ctx, ctx->eng->apply_H_batch(nreq, counts, shots, dm, out, (hipStream_t)stream));
+}
+
+int mp_footprint_batch(const mp_ctx* ctx, int op, int nshots, int nreq, size_t* bytes) {
+  if (!ctx || !bytes) return fail(MP_EINVAL, "null argument");
+  if (op != MP_OP_F && op != MP_OP_FADJ && op != MP_OP_H) return fail(MP_EINVAL, "op must be F, Fadj or H");
+  if (nshots < 1 || nreq < 1) return fail(MP_EINVAL, "nshots and nreq must be positive");
+  return ctx->eng->footprint_batch(op, nshots, nreq, bytes);
+}
+
+int mp_apply_batch(mp_ctx* ctx, int op, int nreq, int nshots, const int* shots, const void* const* in,
+                   void* const* out, void* stream) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (op != MP_OP_F && op != MP_OP_FADJ && op != MP_OP_H) return fail(MP_EINVAL, "op must be F, Fadj or H");
+  if (nreq < 1 || nshots < 1 || !shots || !in || !out) return fail(MP_EINVAL, "bad batch arguments");
+  if (!ctx->has_bg) return fail(MP_ESTATE, "no background set");
+  for (int i = 0; i < nshots; ++i)
+    if (shots[i] < 0 || shots[i] >= ctx->cfg.ns) return fail(MP_EINVAL, "shot index out of range");
+  for (int r = 0; r < nreq; ++r)
+    if (!in[r] || !out[r]) return fail(MP_EINVAL, "null request buffer");
+  return finish(ctx, ctx->eng->apply_batch(op, nreq, nshots, shots, in, out, (hipStream_t)stream));
 }
 
 int mp_apply_F(mp_ctx* ctx, const void* dm, void* d, void* stream) {

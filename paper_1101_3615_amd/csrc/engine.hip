@@ -221,6 +221,45 @@ class EngineT final : public Engine {
     }
     *W = w;
     whole_ = (w >= nb);
+    bgW_ = fW_ = w;
+    hmod_ = 0;
+    return MP_OK;
+  }
+
+  // Buffers of a shared-background batch: nbg background entries (one per shot
+  // of the common shot list, padded to whole groups) and nj = nreq * nbg
+  // wavefield entries, all in one wave.  Byte count only when dry.
+  size_t shared_bytes(int nbg, int nj, int nslots) const {
+    const size_t fslices = cfg_.ndim == 2 ? 4 * (size_t)nbg + 4 * (size_t)nj : 3 * (size_t)nbg + 2 * (size_t)nj;
+    size_t b = sizeof(T) * (size_t)nj * cfg_.nt * cfg_.nr + sizeof(double) * (size_t)(nj / gsz()) * L_.mstride +
+               sizeof(T) * (size_t)std::max(nslots, 1) * L_.fstride + 4 * sizeof(int) * (size_t)nj +
+               sizeof(T) * fslices * L_.fstride + sizeof(T) * (size_t)nbg * g_slots() * L_.mstride;
+    if (ckpt_mode()) b += (size_t)nbg * nck() * 2 * (ck_elem() * (size_t)cstride_ + sizeof(float));
+    return b;
+  }
+  int plan_shared(int nbg, int nj, int nslots) {
+    const size_t need = budget_->used - reserved_sweep() + shared_bytes(nbg, nj, nslots);
+    if (need > budget_->limit) {
+      set_error("shared-background batch needs " + std::to_string(need) + " bytes, budget " +
+                std::to_string(budget_->limit) + ": submit fewer requests at once");
+      return MP_ENOMEM;
+    }
+    const size_t fslices = cfg_.ndim == 2 ? 4 * (size_t)nbg + 4 * (size_t)nj : 3 * (size_t)nbg + 2 * (size_t)nj;
+    int rc;
+    if ((rc = data_.ensure(sizeof(T) * (size_t)nj * cfg_.nt * cfg_.nr, budget_, "data"))) return rc;
+    if ((rc = img_.ensure(sizeof(double) * (size_t)(nj / gsz()) * L_.mstride, budget_, "images"))) return rc;
+    if ((rc = dmbar_.ensure(sizeof(T) * (size_t)std::max(nslots, 1) * L_.fstride, budget_, "dm"))) return rc;
+    if ((rc = jtab_.ensure(4 * sizeof(int) * (size_t)nj, budget_, "job tables"))) return rc;
+    if ((rc = fields_.ensure(sizeof(T) * fslices * L_.fstride, budget_, "fields"))) return rc;
+    if ((rc = hist_.ensure(sizeof(T) * (size_t)nbg * g_slots() * L_.mstride, budget_, "g store"))) return rc;
+    if (ckpt_mode()) {
+      if ((rc = ck_.ensure(ck_elem() * (size_t)nbg * nck() * 2 * cstride_, budget_, "checkpoints"))) return rc;
+      if ((rc = cks_.ensure(sizeof(float) * (size_t)nbg * nck() * 2, budget_, "checkpoint scales"))) return rc;
+    }
+    bgW_ = nbg;
+    fW_ = nj;
+    hmod_ = nbg;
+    whole_ = false;
     return MP_OK;
   }
 
@@ -314,18 +353,21 @@ class EngineT final : public Engine {
       p.nwg = (int)(tiles * p.nchunks);
       p.nsh = nsh;
     }   // 2D: the launcher picks the z chunking per kernel
+    (void)W;
     T* f = fields_.as<T>();
-    const long long fs = (long long)W * L_.fstride;
+    const long long bs = (long long)bgW_ * L_.fstride, fs = (long long)fW_ * L_.fstride;
     p.u_cur = f;
-    p.u_next = f + fs;
-    p.u_inc = f + 2 * fs;
-    p.du_cur = f + 3 * fs;
-    p.du_prev = f + 4 * fs;
+    p.u_next = f + bs;
+    p.u_inc = f + 2 * bs;
+    p.du_cur = f + 3 * bs;
+    p.du_prev = f + 3 * bs + fs;
     p.in0 = p.in1 = p.out0 = p.out1 = nullptr;
     p.hist = hist_.as<T>();
     p.data = data_.as<T>();
     p.img = img_.as<double>();
     p.hstride = g_slots() * L_.mstride;
+    p.hist_u = 0;
+    p.hmod = hmod_;
     p.ck = ck_.get();
     p.ck_scale = cks_.as<float>();
     p.cstride = cstride_;
@@ -403,7 +445,9 @@ class EngineT final : public Engine {
   // ---- sweeps ----
   int zero_fields(int W, bool both) {
     (void)both;
-    fill(fields_.as<T>(), (long long)nslices() * W * L_.fstride, T(0), stream_);
+    (void)W;
+    const long long slices = cfg_.ndim == 2 ? 4LL * bgW_ + 4LL * fW_ : 3LL * bgW_ + 2LL * fW_;
+    fill(fields_.as<T>(), slices * L_.fstride, T(0), stream_);
     MP_CHECK_LAUNCH();
     return MP_OK;
   }
@@ -479,12 +523,13 @@ class EngineT final : public Engine {
     T* wf[4];   // level 0, level -1, level 1 out, level 2 out
   };
   Rot2 rot2(int W) {
+    (void)W;
     T* f = fields_.as<T>();
-    const long long fs = (long long)W * L_.fstride;
+    const long long bs = (long long)bgW_ * L_.fstride, fs = (long long)fW_ * L_.fstride;
     Rot2 r;
     for (int i = 0; i < 4; ++i) {
-      r.bg[i] = f + i * fs;
-      r.wf[i] = f + (4 + i) * fs;
+      r.bg[i] = f + i * bs;
+      r.wf[i] = f + 4 * bs + i * fs;
     }
     return r;
   }
@@ -529,8 +574,9 @@ class EngineT final : public Engine {
     p.rec_bg = model ? data : nullptr;
     Rot2 r = rot2(W);
     const int ck = model ? CK_NONE : ck_kind();
+    const int nbg = hmod_ > 0 ? hmod_ : nsh;   // background entries of the sweep
     if (ck == CK_BF16 && mode != 1) {
-      fill(cks_.as<float>(), (long long)nsh * nck() * 2, 0.0f, stream_);
+      fill(cks_.as<float>(), (long long)nbg * nck() * 2, 0.0f, stream_);
       MP_CHECK_LAUNCH();
     }
     const int kk = (ckpt_mode() && !model) ? cfg_.ckpt_every : cfg_.nt;
@@ -549,7 +595,7 @@ class EngineT final : public Engine {
           const int cm = (ck == CK_BF16 && n + ns == n0 + len && j + 1 < nck()) ? j + 1 : -1;
           const int hs1 = keep_g ? n - base : -1;
           const int hs2 = (keep_g && ns == 2) ? n + 1 - base : -1;
-          launch_bg(p, r, nsh, ns, ck, n, hs1, hs2, cs, cm);
+          launch_bg(p, r, nbg, ns, ck, n, hs1, hs2, cs, cm);
           n += ns;
         }
         if ((rc = span_end(sp))) return rc;
@@ -591,20 +637,24 @@ class EngineT final : public Engine {
       MP_CHECK_LAUNCH();
       return span_end(sp);
     }
-    // checkpoint modes: per segment (last first) recompute g from the checkpoint,
-    // then run the adjoint down through the segment
+    // checkpoint modes: per segment (last first) recompute the background levels
+    // u^{n0+1} .. u^{n0+len} from the checkpoint into the segment's slots, then run
+    // the adjoint down through the segment, imaging in the summed-by-parts form
+    // (the checkpoint's rounding then enters the image without the Laplacian)
     const int kk = cfg_.ckpt_every;
     const int ck = ck_kind();
+    const int nbg = hmod_ > 0 ? hmod_ : nsh;
+    p.hist_u = 1;
     for (int j = nck() - 1; j >= 0; --j) {
       const int n0 = j * kk;
       const int len = std::min(kk, cfg_.nt - n0);
       if ((rc = span_begin(MP_SWEEP_BACKGROUND, (len + 1) / 2, &sp, len))) return rc;
       p.u_cur = r.bg[0];
       p.u_inc = r.bg[1];
-      expand(p, nsh, ck, j, stream_);
+      expand(p, nbg, ck, j, stream_);
       for (int n = n0; n < n0 + len;) {
         const int ns = std::min(2, n0 + len - n);
-        launch_bg(p, r, nsh, ns, CK_NONE, n, n - n0, ns == 2 ? n + 1 - n0 : -1, -1, -1);
+        launch_bg(p, r, nbg, ns, CK_NONE, n, n - n0, ns == 2 ? n + 1 - n0 : -1, -1, -1);
         n += ns;
       }
       if ((rc = span_end(sp))) return rc;
@@ -637,8 +687,10 @@ class EngineT final : public Engine {
     p.data = model ? nullptr : data;
     p.rec_bg = model ? data : nullptr;
     const int ck = model ? CK_NONE : ck_kind();
+    const bool shared = hmod_ > 0;
+    const int nbg = shared ? hmod_ : nsh;
     if (ck == CK_BF16 && mode != 1) {
-      fill(cks_.as<float>(), (long long)nsh * nck() * 2, 0.0f, stream_);
+      fill(cks_.as<float>(), (long long)nbg * nck() * 2, 0.0f, stream_);
       MP_CHECK_LAUNCH();
     }
     Span* sp;
@@ -646,11 +698,23 @@ class EngineT final : public Engine {
                          cfg_.nt, &sp)))
       return rc;
     const int k = std::max(1, cfg_.ckpt_every);
+    // shared background: its own launch over the background entries (g of the
+    // step into a slot), then the Born field of every job entry from that slot
+    Step<T> pb = shared ? params(s0, nbg, W) : p;
     for (int n = 0; n < cfg_.nt; ++n) {
       const int cs = (ck != CK_NONE && n % k == 0) ? n / k : -1;
       const int cm = (ck == CK_BF16 && (n + 1) % k == 0 && (n + 1) / k < nck()) ? (n + 1) / k : -1;
+      if (shared) {
+        // g^n: slot n with a full history; while checkpointing only a Born sweep reads it
+        const int hs = (ck == CK_NONE) ? n : (mode == 0 ? n % k : -1);
+        step(M_BG, pb, n, hs, ck, cs, cm);
+        if (mode == 0) step(M_BORN, p, n, hs, CK_NONE, -1, -1);
+        std::swap(pb.u_cur, pb.u_next);
+        std::swap(p.du_cur, p.du_prev);
+        continue;
+      }
       // g is not stored while checkpointing, nor by modelling
-      const int hs = model ? -1 : (ck == CK_NONE) ? n : 0;
+      const int hs = model ? -1 : (ck == CK_NONE) ? n : -1;
       if (mode == 0) step(M_FUSED, p, n, hs, ck, cs, cm);
       else if (mode == 1) step(M_BORN, p, n, n, CK_NONE, -1, -1);
       else step(M_BG, p, n, hs, ck, cs, cm);
@@ -683,18 +747,24 @@ class EngineT final : public Engine {
       MP_CHECK_LAUNCH();
       return span_end(sp);
     }
-    // checkpoint modes: per segment (last first) recompute g from the checkpoint,
-    // then run the adjoint down through the segment
+    // checkpoint modes: per segment (last first) recompute the background levels
+    // u^{n0+1} .. u^{n0+len} from the checkpoint into the segment's slots, then run
+    // the adjoint down through the segment, imaging in the summed-by-parts form
+    // (the checkpoint's rounding then enters the image without the Laplacian)
     const int kk = cfg_.ckpt_every;
     const int ck = ck_kind();
+    const int nbg = hmod_ > 0 ? hmod_ : nsh;
+    p.hist_u = 1;
+    Step<T> pb = hmod_ > 0 ? params(s0, nbg, W) : p;   // the background entries' launches
+    pb.hist_u = 1;
     for (int j = nck() - 1; j >= 0; --j) {
       const int n0 = j * kk;
       const int len = std::min(kk, cfg_.nt - n0);
       if ((rc = span_begin(MP_SWEEP_BACKGROUND, len, &sp))) return rc;
-      expand(p, nsh, ck, j, stream_);
+      expand(pb, nbg, ck, j, stream_);
       for (int n = n0; n < n0 + len; ++n) {
-        step(M_BG, p, n, n - n0, CK_NONE, -1, -1);
-        std::swap(p.u_cur, p.u_next);
+        step(M_BG, pb, n, n - n0, CK_NONE, -1, -1);
+        std::swap(pb.u_cur, pb.u_next);
       }
       if ((rc = span_end(sp))) return rc;
       if ((rc = span_begin(MP_SWEEP_ADJOINT, len, &sp))) return rc;
@@ -853,6 +923,66 @@ class EngineT final : public Engine {
     return MP_OK;
   }
 
+  // Requests that share one shot list and one background: request r applies op
+  // (F, F* or H) over those shots to in[r].  The background of each shot is
+  // propagated (and recomputed from its checkpoints) once for all requests; the
+  // Born and adjoint fields run per (request, shot) from the shared g / level
+  // slots.  Every result is bit-identical to the same request submitted alone:
+  // the background launches do not depend on the number of requests, the other
+  // per-shot work is independent of it, and each request's image is stacked
+  // from its own groups.
+  int footprint_batch(int op, int nshots, int nreq, size_t* bytes) const override {
+    const int nbg = pad_group(nshots);
+    *bytes = budget_->used - reserved_sweep() + shared_bytes(nbg, nreq * nbg, op == MP_OP_FADJ ? 0 : nreq);
+    return MP_OK;
+  }
+
+  int apply_batch(int op, int nreq, int nshots, const int* shots, const void* const* in, void* const* out,
+                  hipStream_t s) override {
+    stream_ = s;
+    const int nbg = pad_group(nshots), nj = nreq * nbg;
+    int rc;
+    if ((rc = plan_shared(nbg, nj, op == MP_OP_FADJ ? 0 : nreq))) return rc;
+    std::vector<int> js(nj), jslot(nj);
+    for (int r = 0; r < nreq; ++r)
+      for (int i = 0; i < nbg; ++i) {
+        js[r * nbg + i] = i < nshots ? shots[i] : -1;
+        jslot[r * nbg + i] = op == MP_OP_FADJ ? 0 : r;
+      }
+    if ((rc = upload_job(js, jslot))) return rc;
+    cached_ = false;   // the stores now hold this job's shots
+    T* data = data_.as<T>();
+    const long long rec = (long long)cfg_.nt * cfg_.nr;   // samples per shot
+    if (op == MP_OP_FADJ) {
+      for (int r = 0; r < nreq; ++r)
+        MP_HIP(hipMemcpyAsync(data + (long long)r * nbg * rec, in[r], sizeof(T) * (size_t)nshots * rec,
+                              hipMemcpyDeviceToDevice, s));
+    } else {
+      for (int r = 0; r < nreq; ++r) {
+        put_dm(r, in[r], s);
+        MP_CHECK_LAUNCH();
+      }
+    }
+    const int mode = op == MP_OP_FADJ ? 2 : 0;
+    if ((rc = forward(mode, 0, nj, nj, data))) { hmod_ = 0; return rc; }
+    if (op != MP_OP_F && (rc = adjoint(0, nj, nj, data))) { hmod_ = 0; return rc; }
+    for (int r = 0; r < nreq; ++r) {
+      if (op == MP_OP_F) {
+        MP_HIP(hipMemcpyAsync(out[r], data + (long long)r * nbg * rec, sizeof(T) * (size_t)nshots * rec,
+                              hipMemcpyDeviceToDevice, s));
+      } else {
+        const int g0 = r * nbg / gsz(), ng = nbg / gsz();
+        stack(static_cast<T*>(out[r]), img_.as<double>() + L_.mxl + (long long)g0 * L_.mstride, ng, L_.mstride,
+              cfg_.nx, cfg_.ny, cfg_.nz, L_.mpitch, cfg_.ny, s);
+        MP_CHECK_LAUNCH();
+      }
+    }
+    hmod_ = 0;
+    bgW_ = fW_ = 0;
+    finish_stats(1, false, (long long)nreq * nshots);
+    return MP_OK;
+  }
+
   int release_cache() override {
     cached_ = false;
     hist_.release();
@@ -871,6 +1001,10 @@ class EngineT final : public Engine {
   Budget* budget_;
   Layout L_;
   int zc_target_ = 0;
+  // Field slices hold bgW_ background entries and fW_ wavefield entries; with
+  // hmod_ > 0 (a shared-background batch) job entry j takes the background, the
+  // g / level slots and the checkpoints of entry j % hmod_.
+  int bgW_ = 0, fW_ = 0, hmod_ = 0;
   int cu_count_ = 256;
   int cpitch_ = 0;
   long long cstride_ = 0;

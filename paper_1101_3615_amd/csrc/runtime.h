@@ -71,7 +71,10 @@ class Engine {
   virtual int apply_H(const void* dm, void* out, hipStream_t s) = 0;
   virtual int apply_H_batch(int nreq, const int* counts, const int* shots, const void* const* dm,
                             void* const* out, hipStream_t s) = 0;
+  virtual int apply_batch(int op, int nreq, int nshots, const int* shots, const void* const* in,
+                          void* const* out, hipStream_t s) = 0;
   virtual int footprint(int op, int nshots, size_t* bytes) const = 0;
+  virtual int footprint_batch(int op, int nshots, int nreq, size_t* bytes) const = 0;
   virtual int release_cache() = 0;
   virtual size_t reserved() const = 0;
   // Wait for the timing events of the last call and fold them into stats.

@@ -61,6 +61,11 @@ struct Step {
   T* du_prev;
   T* hist;                   // g store: [local shot][slot][model]
   long long hstride;         // elements per local shot in hist
+  int hmod;                  // > 0: local shot ls takes the slots of background entry ls % hmod
+                             // (requests sharing one background sweep); 0: its own
+  int hist_u;                // 1: slot n - n0 holds the background level u^{n+1} instead of g^n,
+                             // and the adjoint images in the summed-by-parts form
+                             // I -= u^k c^2 (L nu^{k+1} + R^T d^{k-1}) (checkpoint recomputation)
   T* data;                   // [shots of the job][nt][nr]
   T* rec_bg;                 // M_BG records u^{n+1}(x_r) into [shots of the job][nt][nr] when non-null
   double* img;               // [shots of the job][model] FP64 per-shot images
@@ -81,16 +86,18 @@ enum { M_FUSED = 0, M_BORN = 1, M_BG = 2, M_ADJ = 3 };
 // 2D: nsteps (1 or 2) time steps of every shot of a wave in one launch.
 // mode: M_BG, M_BORN or M_ADJ; n: first step (adjoint: k, the first level
 // computed is nu^k); hs1, hs2: g slots of the two steps (written by M_BG, -1 for
-// none; read by M_BORN and M_ADJ); ck: CK_* encoding of M_BG; ck_store:
-// checkpoint written from the launch's input level (u^n, D^n) or -1; ck_max:
-// checkpoint whose BF16 scales take the maxima of the launch's last level or -1;
+// none; read by M_BORN and M_ADJ; u^{n+1} instead of g^n when p.hist_u); ck:
+// CK_* encoding of M_BG; ck_store: checkpoint written from the launch's input
+// level (u^n, D^n) or -1; ck_max: checkpoint whose BF16 scales take the maxima
+// of the launch's last level or -1;
 // zc > 0 forces the z-chunk height.  nsh: shots in the wave.
 void sweep2d(int mode, int nsteps, int ck, const Step<float>& p, int nsh, int n, int hs1, int hs2, int ck_store,
              int ck_max, int zc, hipStream_t s);
 void sweep2d(int mode, int nsteps, int ck, const Step<double>& p, int nsh, int n, int hs1, int hs2, int ck_store,
              int ck_max, int zc, hipStream_t s);
 // 3D: one time step of every shot of a wave.  mode: M_*; n: step (adjoint: k);
-// hslot: g slot written (background modes) or read (Born, adjoint);
+// hslot: g slot written (background modes; -1: none) or read (Born, adjoint;
+// u^{n+1} instead of g^n when p.hist_u);
 // ck: CK_* encoding; ck_store: checkpoint written from (u^n, u^{n-1}) at this
 // step or -1; ck_max: checkpoint whose BF16 scales accumulate max |u^{n+1}| and
 // max |u^{n+1} - u^n| at this step or -1.

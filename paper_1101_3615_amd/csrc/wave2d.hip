@@ -27,6 +27,10 @@
 //   Born        du+ = a (2 du + kappa (L du - dm g)) - b du-          (Sec. 2)
 //   adjoint     nu  = a (2 nu' + kappa (L nu' + R^T d)) - b nu''      (exact transpose)
 //   imaging     I  -= g^{k-1} nu^k                                    (FP64, per group of 4 shots)
+//               or, with the background levels u^k in the slots (checkpoint recomputation),
+//               I  -= u^k c^2 (L nu^{k+1} + R^T d^{k-1}): the same sum over k taken by parts
+//               in time (u^0 = u^{-1} = 0 = nu^{nt+1} = nu^{nt+2}), in which the rounding
+//               of a stored level is not amplified by the Laplacian
 #include <algorithm>
 #include <cmath>
 
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
   const unsigned vo = (unsigned)(2 * lane) * (unsigned)sizeof(T);          // lane offset in a field row
   const unsigned vs = outl ? vo : OFF_NONE;                                  // ... for stores
   // model resources (g slots, image): nz rows of mpitch from model column 0
-  const long long hbase = (long long)ls * p.hstride;
+  const long long hbase = (long long)(p.hmod > 0 ? ls % p.hmod : ls) * p.hstride;
   const long long mbytes = (long long)nz * p.L.mpitch * (long long)sizeof(T);
   const int mxl = p.L.mxl;
   const Rsrc rH1 = rsrc(hs1 >= 0 ? p.hist + hbase + (long long)hs1 * p.L.mstride + mxl : p.hist, hs1 >= 0 ? mbytes : 0);
@@ -455,7 +459,7 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
 
   V2<T> q0[9], q1[9];   // level-0 rows, level-1 rows
   V2<T> e0[9], e1[9];   // their first differences along the march
-  V2<T> kq[9], mq[9];   // kappa and (Born) perturbation of the level-1 rows, reused by level 2
+  V2<T> kq[9], mq[9];   // kappa and (Born) perturbation / (adjoint) c^2 Lam of the level-1 rows, for level 2
   auto diff = [](const V2<T>& a, const V2<T>& b) {
     V2<T> r;
     r.v[0] = a.v[0] - b.v[0];
@@ -526,11 +530,15 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
         if (NS == 2) {
           q1[r] = nv;
           if (BG) dq[wv][r][lane] = nd;
+          if (MODE == M_ADJ) {   // c^2 (L nu^{k+1} + R^T d) of the row, imaged at level 2
+            mq[r].v[0] = rmul(rmul(cur.k1.v[0], lap[0]), p.inv_dt2);
+            mq[r].v[1] = rmul(rmul(cur.k1.v[1], lap[1]), p.inv_dt2);
+          }
         }
         if (out_row) {
           if (BG) {
             if (CK != CK_NONE && ck_store >= 0) ckstore(z, c0, cur.pv);
-            gst(rH1, z - nb, g);
+            gst(rH1, z - nb, p.hist_u ? nv.v : g);
             if (NS == 1) {
               bst2(nv, rO0, vs + so, 0u);
               bst2(nd, rO1, vs + so, 0u);
@@ -553,7 +561,9 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
               if (zm >= 0 && zm < nz) {   // uniform over the workgroup
                 V2<double> cw;
 #pragma unroll
-                for (int i = 0; i < 2; ++i) cw.v[i] = -((double)cur.g1.v[i] * (double)nv.v[i]);
+                for (int i = 0; i < 2; ++i)
+                  cw.v[i] = p.hist_u ? -((double)cur.g1.v[i] * (double)rmul(rmul(cur.k1.v[i], lap[i]), p.inv_dt2))
+                                     : -((double)cur.g1.v[i] * (double)nv.v[i]);
                 image(zm, cw, cur.im);
               }
             }
@@ -562,6 +572,7 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
       } else if (NS == 2) {
         q1[r] = zero2<T>();
         if (BG) dq[wv][r][lane] = zero2<T>();
+        if (MODE == M_ADJ) mq[r] = zero2<T>();
       }
       if (NS == 2) e1[(r + 8) % 9] = diff(q1[r], q1[(r + 8) % 9]);
 
@@ -600,7 +611,7 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
         if (BG) {
           bst2(nv, rO0, vs + so, 0u);
           bst2(nd, rO1, vs + so, 0u);
-          gst(rH2, y - nb, g);
+          gst(rH2, y - nb, p.hist_u ? nv.v : g);
           if (CK == CK_BF16 && ck_max >= 0) track(nv, nd);
           if (recrow && outl && live) {
             T* drow = recbg + ((long long)shot * p.nt + n + 1) * p.nr;
@@ -620,8 +631,13 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
               V2<double> cw;
 #pragma unroll
               for (int i = 0; i < 2; ++i) {
-                cw.v[i] = -((double)cur.g1.v[i] * (double)c1.v[i]);
-                cw.v[i] -= (double)cur.g2.v[i] * (double)nv.v[i];
+                if (p.hist_u) {   // u^k with level 1's c^2 Lam, u^{k-1} with level 2's
+                  cw.v[i] = -((double)cur.g1.v[i] * (double)mq[(r + 5) % 9].v[i]);
+                  cw.v[i] -= (double)cur.g2.v[i] * (double)rmul(rmul(kq[(r + 5) % 9].v[i], lap[i]), p.inv_dt2);
+                } else {
+                  cw.v[i] = -((double)cur.g1.v[i] * (double)c1.v[i]);
+                  cw.v[i] -= (double)cur.g2.v[i] * (double)nv.v[i];
+                }
               }
               image(zm, cw, cur.im);
             }

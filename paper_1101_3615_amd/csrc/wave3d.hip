@@ -14,7 +14,9 @@
 // outside the grid read zero from the hardware range check instead of branching.
 // Workgroups are persistent and walk their XCD's items pairs of shots fastest, so
 // the pairs of a tile share its kappa and perturbation through that XCD's L2.
-// The arithmetic per cell is that of the 2D kernel with the y axis added.
+// The arithmetic per cell is that of the 2D kernel with the y axis added,
+// including its two forms of the imaging condition (g^{k-1} nu^k, or u^k times
+// c^2 (L nu^{k+1} + R^T d) when the slots hold background levels).
 #include <algorithm>
 
 #include "common.h"
@@ -58,6 +60,13 @@ __device__ __forceinline__ V4<double> bld4(Rsrc3 r, unsigned vo, unsigned so, do
   o.v[3] = __longlong_as_double(((long long)b.w << 32) | b.z);
   return o;
 }
+// 16-byte stores take the uniform offset in the per-lane offset and a constant
+// zero SOFFSET: a VALU write to the data registers of a store wider than 8 bytes
+// right after it issues can change the data stored, and the compiler inserts the
+// wait states that prevent this only for stores with a constant SOFFSET.  (With
+// the plane offset in an SGPR SOFFSET, the field stores were seen to take such
+// later values.)  An inactive lane's OFF_NONE3 plus the plane offset stays past
+// the resource: a field slice is kept below 1 GiB when the context is created.
 template <int CP = 0>
 __device__ __forceinline__ void bst4(const V4<float>& a, Rsrc3 r, unsigned vo, unsigned so) {
   u32x4_3 v;
@@ -65,7 +74,7 @@ __device__ __forceinline__ void bst4(const V4<float>& a, Rsrc3 r, unsigned vo, u
   v.y = __float_as_uint(a.v[1]);
   v.z = __float_as_uint(a.v[2]);
   v.w = __float_as_uint(a.v[3]);
-  __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, CP);
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, vo + so, 0, CP);
 }
 template <int CP = 0>
 __device__ __forceinline__ void bst4(const V4<double>& a, Rsrc3 r, unsigned vo, unsigned so) {
@@ -80,8 +89,8 @@ __device__ __forceinline__ void bst4(const V4<double>& a, Rsrc3 r, unsigned vo, 
   v1.y = (unsigned)(b2 >> 32);
   v1.z = (unsigned)b3;
   v1.w = (unsigned)(b3 >> 32);
-  __builtin_amdgcn_raw_buffer_store_b128(v0, r, vo, so, CP);
-  __builtin_amdgcn_raw_buffer_store_b128(v1, r, vo + 16, so, CP);
+  __builtin_amdgcn_raw_buffer_store_b128(v0, r, vo + so, 0, CP);
+  __builtin_amdgcn_raw_buffer_store_b128(v1, r, vo + so + 16, 0, CP);
 }
 __device__ __forceinline__ int depth3(int i, int n, int nb) { return max(max(nb - i, i - (n + nb - 1)), 0); }
 // a = 1 / (1 + e), b = (1 - e) a with e = ec * dd (dd: sum of squared layer depths)
@@ -252,7 +261,7 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
   // model-grid resources (g slot of the shot, FP64 image of the shot): the plane
   // offset is added to the lane offset as an unsigned value, so planes above or
   // below the model wrap past the end of the resource and read zero
-  const long long hoff = (long long)ls * p.hstride + (long long)hslot * p.L.mstride;
+  const long long hoff = (long long)(p.hmod > 0 ? ls % p.hmod : ls) * p.hstride + (long long)hslot * p.L.mstride;
   const long long mbytes3 = p.L.mstride * (long long)sizeof(T);
   const Rsrc3 rG = rsrc3(hslot >= 0 ? p.hist + hoff : p.hist, hslot >= 0 ? mbytes3 : 0);
   const Rsrc3 rI = rsrc3(MODE == M_ADJ ? p.img + (long long)(shot >> 1) * p.L.mstride : p.img,
@@ -470,10 +479,10 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
           }
         }
 
-        if (CK == CK_NONE && BGM && zmod) {
+        if (hslot >= 0 && BGM && zmod) {   // g^n, or u^{n+1} for the summed-by-parts imaging
           V4<T> gg;
   #pragma unroll
-          for (int i = 0; i < 4; ++i) gg.v[i] = xmod[i] ? g[i] : T(0);   // model pad columns keep zero
+          for (int i = 0; i < 4; ++i) gg.v[i] = xmod[i] ? (p.hist_u ? anew.v[i] : g[i]) : T(0);   // model pad columns keep zero
           bst4<NT3>(gg, rG, gvo + (unsigned)zm * gplane, 0u);
         }
 
@@ -493,7 +502,10 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
         if (MODE == M_ADJ) {   // this half's contribution, added to the image one plane later
           V4<double> cw;
   #pragma unroll
-          for (int i = 0; i < 4; ++i) cw.v[i] = xmod[i] ? -((double)g[i] * (double)anew.v[i]) : 0.0;
+          for (int i = 0; i < 4; ++i) {
+            const double img = p.hist_u ? (double)(kap4.v[i] * lapA[i] * p.inv_dt2) : (double)anew.v[i];
+            cw.v[i] = xmod[i] ? -((double)g[i] * img) : 0.0;
+          }
           RED[half][z & 1][tid] = cw;
         }
       }

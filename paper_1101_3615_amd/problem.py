@@ -151,6 +151,47 @@ class Problem:
         self._keep = dms                     # inputs must outlive the enqueued work
         return outs
 
+    _BATCH_OPS = {"F": L.MP_OP_F, "Fadj": L.MP_OP_FADJ, "H": L.MP_OP_H}
+
+    def footprint_batch(self, op, nshots, nreq):
+        """Device bytes of apply_batch for nreq requests over nshots shots."""
+        b = ctypes.c_size_t()
+        L.check(self._lib.mp_footprint_batch(self._ctx, self._BATCH_OPS[op], int(nshots), int(nreq),
+                                             ctypes.byref(b)))
+        return b.value
+
+    def apply_batch(self, op, xs, shots, outs=None, stream=None):
+        """op in {"F", "Fadj", "H"} applied to every request xs[r] over the common shot
+        list `shots`, the background of each shot propagated once for all requests.
+        F: model -> data [len(shots)][nt][nr]; Fadj: such data -> image; H: model -> image."""
+        shots = np.ascontiguousarray(np.asarray(shots, dtype=np.int32).ravel())
+        ns = int(shots.size)
+        dshape = (ns, self.data_shape[1], self.data_shape[2])
+        if op == "Fadj":
+            ins = []
+            for x in xs:
+                t = x if isinstance(x, torch.Tensor) else torch.as_tensor(np.asarray(x))
+                t = t.to(device=self.device, dtype=self.torch_dtype).contiguous()
+                if tuple(t.shape) != dshape:
+                    raise ValueError(f"data has shape {tuple(t.shape)}, expected {dshape}")
+                ins.append(t)
+        else:
+            ins = [self._model(x, "dm") for x in xs]
+        oshape = dshape if op == "F" else self.model_shape
+        if outs is None:
+            outs = [torch.empty(oshape, dtype=self.torch_dtype, device=self.device) for _ in ins]
+        for o in outs:
+            if tuple(o.shape) != oshape or o.dtype != self.torch_dtype or not o.is_contiguous():
+                raise ValueError(f"outputs must be contiguous {self.torch_dtype} tensors of shape {oshape}")
+        n = len(ins)
+        ip = (ctypes.c_void_p * n)(*[t.data_ptr() for t in ins])
+        op_ = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        L.check(self._lib.mp_apply_batch(self._ctx, self._BATCH_OPS[op], n, ns,
+                                         shots.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ip, op_,
+                                         _stream(stream)))
+        self._keep = ins                     # inputs must outlive the enqueued work
+        return outs
+
     # ---- vector kernels of the solvers (FP64 accumulation, fixed order) ----
     def _vec(self, t, name):
         if not (isinstance(t, torch.Tensor) and t.device == self.device and t.dtype == self.torch_dtype

@@ -1,9 +1,9 @@
-"""Continuous batching of normal-operator requests on one GPU.
+"""Continuous batching of F, F* and H requests on one GPU.
 
-Requests (apply H = F*F to a model vector on one of several grid shapes, with
-a chosen set of shots) arrive over time.  The server keeps one resident
-context per (shape, lane): the background model, its damping tables and the
-wavefield/checkpoint stores stay on the device between requests.  A lane runs
+Requests (apply F, F* or H = F*F on one of several grid shapes, over one of the
+shape's shot sets) arrive over time.  The server keeps one resident context per
+(shape, lane): the background model, its damping tables and the wavefield,
+checkpoint and image stores stay on the device between requests.  A lane runs
 one batch at a time on its own HIP stream; lanes of different shapes (and
 several lanes of one shape) run concurrently, so work of requests that arrive
 while others are on the GPU overlaps on the device.
@@ -12,25 +12,26 @@ Scheduling loop (event driven, one host thread):
   * arrivals enter a FIFO queue;
   * finished batches are retired (completion time = when the host sees the
     batch's event complete) and their lanes freed;
-  * each idle lane takes the oldest queued requests of its shape, in arrival
-    order, while the batch's device footprint (wavefields plus checkpoints of
-    all its shots, from mp_footprint) fits the lane's share of the HBM budget
-    and the batch stays under max_batch_shots -- admission by footprint;
-  * the batch is one mp_apply_H_batch call: all its shots are propagated
-    together, one kernel launch per time step, and each request's image is
-    stacked from its own shots, so a request's result is bit-identical alone
-    and in any mix.
+  * each idle lane takes the oldest queued request of its shape and every
+    other queued request of the same operator and shot set, in arrival order,
+    while the batch's device footprint (mp_footprint_batch: the shared
+    background's fields, slots and checkpoints plus each request's wavefields,
+    data and images) fits the lane's share of the HBM budget and the batch
+    stays under max_batch -- admission by footprint;
+  * the batch is one mp_apply_batch call: the background of each shot is
+    propagated (and recomputed from its checkpoints) once for the whole batch,
+    the requests' Born and adjoint fields run in the same launches, and every
+    request's result is bit-identical alone and in any batch.
 
 The executor is pluggable so that the scheduling logic can be exercised on
 the CPU with simulated service times (tests); the GPU executor is the only
 one that computes.
 """
 import collections
-import heapq
 import math
 import time
-from dataclasses import dataclass, field
-from typing import Any, Dict, List, Optional
+from dataclasses import dataclass
+from typing import Any, List, Optional
 
 
 @dataclass
@@ -39,7 +40,8 @@ class Request:
     arrival: float                  # seconds since the start of the run
     shape: Any                      # key of the server's shapes
     shots: List[int]                # acquisition shot indices of the shape
-    dm: Any = None                  # model vector (device tensor)
+    op: str = "H"                   # "F", "Fadj" or "H"
+    x: Any = None                   # input (device tensor): model for F / H, data for Fadj
     cell_steps: float = 0.0
     admitted: Optional[float] = None
     started: Optional[float] = None
@@ -51,9 +53,14 @@ class Request:
     def latency(self):
         return None if self.finished is None else self.finished - self.arrival
 
+    @property
+    def key(self):
+        """Requests with equal keys share a background sweep."""
+        return (self.shape, self.op, tuple(self.shots))
+
 
 class GpuExecutor:
-    """Runs batches with mp_apply_H_batch on per-lane contexts and streams."""
+    """Runs batches with mp_apply_batch on per-lane contexts and streams."""
 
     def __init__(self, shapes, lanes_per_shape=2, budget_bytes=0, device="cuda:0"):
         import torch
@@ -76,8 +83,8 @@ class GpuExecutor:
     def lane_keys(self):
         return list(self.lanes.keys())
 
-    def footprint(self, lane, nshots):
-        return self.lanes[lane]["problem"].footprint("H", nshots)
+    def footprint(self, lane, op, nshots, nreq):
+        return self.lanes[lane]["problem"].footprint_batch(op, nshots, nreq)
 
     def lane_budget(self, lane):
         b = self.lanes[lane]["budget"]
@@ -91,8 +98,9 @@ class GpuExecutor:
         torch = self.torch
         L = self.lanes[lane]
         st = L["stream"]
+        r0 = reqs[0]
         with torch.cuda.stream(st):
-            outs = L["problem"].apply_H_batch([r.dm for r in reqs], [r.shots for r in reqs], stream=st)
+            outs = L["problem"].apply_batch(r0.op, [r.x for r in reqs], r0.shots, stream=st)
             ev = torch.cuda.Event()
             ev.record(st)
         for r, o in zip(reqs, outs):
@@ -107,9 +115,9 @@ class GpuExecutor:
 
 
 class Server:
-    def __init__(self, executor, max_batch_shots=256, clock=time.perf_counter, sleep=time.sleep):
+    def __init__(self, executor, max_batch=16, clock=time.perf_counter, sleep=time.sleep):
         self.ex = executor
-        self.max_batch_shots = max_batch_shots
+        self.max_batch = max_batch
         self.clock = clock
         self.sleep = sleep
         self.queue = collections.OrderedDict()       # rid -> Request
@@ -121,21 +129,19 @@ class Server:
     def _form_batch(self, lane, now):
         shape = lane[0]
         budget = self.ex.lane_budget(lane)
-        batch, nshots, njob = [], 0, 0
-        for r in list(self.queue.values()):
-            if r.shape != shape:
+        head = next((r for r in self.queue.values() if r.shape == shape), None)
+        if head is None:
+            return []
+        batch = [head]
+        for r in self.queue.values():
+            if r is head or r.key != head.key:
                 continue
-            n = nshots + len(r.shots)
-            # each request occupies whole image groups of job entries on the device
-            # (four shots in 2D, two in 3D; four bounds both)
-            nj = njob + -(-len(r.shots) // 4) * 4
-            if batch and n > self.max_batch_shots:
+            if len(batch) >= self.max_batch:
                 break
-            if batch and self.ex.footprint(lane, nj) > budget:
+            if self.ex.footprint(lane, r.op, len(r.shots), len(batch) + 1) > budget:
                 self.rejected_waits += 1
                 break
             batch.append(r)
-            nshots, njob = n, nj
         for r in batch:
             del self.queue[r.rid]
             r.admitted = now
@@ -179,9 +185,10 @@ class Server:
         return self.done
 
 
-def poisson_requests(rate, duration, shapes, shot_choices, seed, make_dm=None):
-    """Seeded open-loop Poisson arrivals: shape uniform over `shapes`, shot count
-    uniform over `shot_choices` (indices 0..n-1 of that shape's shot group)."""
+def poisson_requests(rate, duration, shapes, shot_choices, seed, make_x=None, ops=("H",)):
+    """Seeded open-loop Poisson arrivals: shape uniform over `shapes`, shot set
+    uniform over `shot_choices` (shapes[shape][n]: the shape's set of n shots),
+    operator uniform over `ops`; make_x(request) builds the request's input."""
     from fixtures.rng import Stream  # input generator, not method arithmetic
     st = Stream(seed)
     t, rid, out = 0.0, 0, []
@@ -192,9 +199,10 @@ def poisson_requests(rate, duration, shapes, shot_choices, seed, make_dm=None):
             break
         shape = keys[int(st.uniform(1)[0] * len(keys)) % len(keys)]
         ns = shot_choices[int(st.uniform(1)[0] * len(shot_choices)) % len(shot_choices)]
-        r = Request(rid=rid, arrival=t, shape=shape, shots=list(shapes[shape][ns]))
-        if make_dm is not None:
-            r.dm = make_dm(r)
+        op = ops[int(st.uniform(1)[0] * len(ops)) % len(ops)] if len(ops) > 1 else ops[0]
+        r = Request(rid=rid, arrival=t, shape=shape, shots=list(shapes[shape][ns]), op=op)
+        if make_x is not None:
+            r.x = make_x(r)
         out.append(r)
         rid += 1
     return out

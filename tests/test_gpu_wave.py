@@ -177,17 +177,18 @@ def _short_record(snap, k):
 
 @pytest.mark.parametrize("snap,k", [("ckpt_f32", 4), ("ckpt_f32", 7), ("ckpt_bf16", 4)])
 def test_checkpoint_modes(snap, k):
-    """Checkpoint + recompute: FP32 checkpoints reproduce the full-history sweep and the
-    oracle; in every mode F is exact (it never reads a checkpoint), F then F* reuses the
-    stored checkpoints, and shot waves give the same bits.  (The BF16 error against the
-    oracle on this short record is the next test.)"""
+    """Checkpoint + recompute: FP32 checkpoints agree with the full-history sweep and the
+    oracle at the FP32 bound (the recomputing adjoint images in the summed-by-parts form,
+    so it differs from the full-history sweep by rounding only); in every mode F is exact
+    (it never reads a checkpoint), F then F* reuses the stored checkpoints, and shot waves
+    give the same bits.  (The BF16 error against the oracle is the next test.)"""
     M, w, c, Pfull, P = _short_record(snap, k)
     O = Oracle(w, c)
     dm = F.wavepackets(w, c, 95, 6)
     got = P.apply_H(torch.from_numpy(dm)).cpu().numpy()
     if snap == "ckpt_f32":
         full = Pfull.apply_H(torch.from_numpy(dm)).cpu().numpy()
-        assert rel(got, full) <= 1e-6
+        assert rel(got, full) <= 1e-5
         assert rel(got, O.apply_H(dm)) <= 1e-5
     d = O.apply_F(F.wavepackets(w, c, 97, 6))
     dF = P.apply_F(torch.from_numpy(dm)).cpu().numpy()
@@ -209,13 +210,10 @@ def test_checkpoint_modes(snap, k):
     assert np.array_equal(again, whole)
 
 
-@pytest.mark.xfail(strict=False, reason=(
-    "BF16 checkpoints on a 160-step record exceed 1e-2: the rounding of the checkpointed level "
-    "is white noise that the recomputed c^2 L u amplifies by ~13/(kh)^2, and a short record "
-    "averages it over few segments (measured 1.2e-2 for H, 1.6e-2 to 2.5e-2 for F*); the "
-    "configured 4000-step record meets 1e-2 (test_gpu_c3_full.py)"))
 def test_bf16_checkpoints_short_record_precision():
-    """BF16 checkpoints every 4 steps against the FP64 oracle at the stated 1e-2 bound."""
+    """BF16 checkpoints every 4 steps on a 160-step record against the FP64 oracle at the
+    stated 1e-2 bound (measured 2.2e-3 for H, 1.4e-3 for F*: the recomputed background
+    levels enter the summed-by-parts image without the Laplacian's amplification)."""
     M, w, c, _, P = _short_record("ckpt_bf16", 4)
     O = Oracle(w, c)
     dm = F.wavepackets(w, c, 95, 6)

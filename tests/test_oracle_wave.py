@@ -252,6 +252,47 @@ def test_fused_H_equals_adjoint_of_born_data(small):
                                atol=1e-12 * np.max(np.abs(P.apply_H(a))))
 
 
+def _adjoint_by_parts(P, s, d, shift=0):
+    """The image of shot s summed by parts in time: -sum_k u^{k-shift} c^2 (L nu^{k+1} + R^T d^{k-1}).
+
+    The GPU path images in this form when it recomputes the background from
+    checkpoints (the rounding of a stored level then enters without the
+    Laplacian).  u^k are the oracle's own background levels, nu the adjoint
+    recurrence; shift=1 plants an off-by-one in the level index.
+    """
+    snaps = {}
+    P.background(s, keep_g=False, snapshots=snaps)
+    snaps[-1] = np.zeros(P.c_pad.shape)
+    nu1 = np.zeros(P.c_pad.shape)
+    nu2 = np.zeros(P.c_pad.shape)
+    img = np.zeros(P.w.model_shape)
+    for k in range(P.nt, 0, -1):
+        lam = laplacian(nu1, P.h, P.nd)
+        np.add.at(lam, P.rec, d[k - 1])
+        nu = P.a * (2.0 * nu1 + P.kappa * lam) - P.b * nu2
+        img -= P.restrict(snaps[k - shift] * P.csq * lam)
+        nu2, nu1 = nu1, nu
+    return img
+
+
+def test_adjoint_summed_by_parts_equals_the_transpose(small):
+    """-sum_k g^{k-1} nu^k = -sum_k u^k c^2 (L nu^{k+1} + R^T d^{k-1}) on the model grid.
+
+    Summation by parts of the second difference u^{k} - 2u^{k-1} + u^{k-2} = dt^2 g^{k-1}
+    (the model grid carries no damping), with u^0 = u^{-1} = 0 and nu^{nt+1} =
+    nu^{nt+2} = 0, turns one form into the other; a level index off by one fails.
+    """
+    P = small
+    d = F.normal_field((len(P.src), P.nt, len(P.rec[0])), 23).astype(np.float64)
+    for s in range(len(P.src)):
+        g, _ = P.background(s)
+        ref = P.adjoint(s, d[s], g)
+        byparts = _adjoint_by_parts(P, s, d[s])
+        assert np.linalg.norm(byparts - ref) <= 1e-12 * np.linalg.norm(ref)
+        off = _adjoint_by_parts(P, s, d[s], shift=1)
+        assert np.linalg.norm(off - ref) > 1e-2 * np.linalg.norm(ref)
+
+
 # ------------------------------------------------------- absorbing layer --
 #
 # The layer is defined (a reading: the paper names a PML of width .15N) as a

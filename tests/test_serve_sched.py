@@ -32,8 +32,8 @@ class FakeExecutor:
     def lane_keys(self):
         return list(self._lanes)
 
-    def footprint(self, lane, nshots):
-        return nshots * self.per_shot
+    def footprint(self, lane, op, nshots, nreq):
+        return nshots * nreq * self.per_shot
 
     def lane_budget(self, lane):
         return self.budget if self.budget is not None else float("inf")
@@ -51,19 +51,20 @@ class FakeExecutor:
         return self.clock() >= handle
 
 
-def _reqs(arrivals, shape="a", nshots=4):
-    return [Request(rid=i, arrival=t, shape=shape, shots=list(range(nshots))) for i, t in enumerate(arrivals)]
+def _reqs(arrivals, shape="a", nshots=4, op="H", rid0=0):
+    return [Request(rid=rid0 + i, arrival=t, shape=shape, shots=list(range(nshots)), op=op)
+            for i, t in enumerate(arrivals)]
 
 
 def test_requests_waiting_together_are_batched_in_arrival_order():
     clk = Clock()
     ex = FakeExecutor(clk, [("a", 0)], rate=4e8)          # 1 s per 4-shot request
-    srv = Server(ex, max_batch_shots=8, clock=clk, sleep=clk.sleep)
+    srv = Server(ex, max_batch=2, clock=clk, sleep=clk.sleep)
     done = srv.run(_reqs([0.0, 0.1, 0.2, 0.3]))
     assert len(done) == 4
     batches = [b for (_, _, b) in ex.launched]
     assert batches[0] == [0]                 # alone: nothing else had arrived
-    assert batches[1] == [1, 2]              # the next two, capped at 8 shots
+    assert batches[1] == [1, 2]              # the next two, capped at 2 requests
     assert batches[2] == [3]
     for r in done:
         assert r.finished >= r.started >= r.arrival
@@ -72,7 +73,7 @@ def test_requests_waiting_together_are_batched_in_arrival_order():
 def test_footprint_admission_limits_batch_size():
     clk = Clock()
     ex = FakeExecutor(clk, [("a", 0)], rate=4e8, budget=10.0, per_shot=1.0)  # 10 shots fit
-    srv = Server(ex, max_batch_shots=1000, clock=clk, sleep=clk.sleep)
+    srv = Server(ex, max_batch=1000, clock=clk, sleep=clk.sleep)
     srv.run(_reqs([0.0, 0.01, 0.02, 0.03, 0.04], nshots=4))
     sizes = [len(b) for (_, _, b) in ex.launched]
     assert max(sizes) * 4 <= 10 and srv.rejected_waits > 0
@@ -81,7 +82,7 @@ def test_footprint_admission_limits_batch_size():
 def test_lanes_run_concurrently_and_shapes_do_not_mix():
     clk = Clock()
     ex = FakeExecutor(clk, [("a", 0), ("a", 1), ("b", 0)], rate=4e8)
-    srv = Server(ex, max_batch_shots=4, clock=clk, sleep=clk.sleep)
+    srv = Server(ex, max_batch=1, clock=clk, sleep=clk.sleep)
     reqs = _reqs([0.0, 0.0, 0.0], "a") + [Request(rid=10, arrival=0.0, shape="b", shots=[0, 1, 2, 3])]
     done = srv.run(reqs)
     starts = {r.rid: r.started for r in done}
@@ -91,6 +92,25 @@ def test_lanes_run_concurrently_and_shapes_do_not_mix():
         assert shapes == {lane[0]}
 
 
+def test_only_requests_of_one_operator_and_shot_set_share_a_batch():
+    """A batch shares one background sweep: same shape, operator and shot set."""
+    clk = Clock()
+    ex = FakeExecutor(clk, [("a", 0)], rate=4e8)
+    reqs = (_reqs([0.0], op="H") + _reqs([0.01], op="F", rid0=1) + _reqs([0.02], op="H", nshots=8, rid0=2)
+            + _reqs([0.03, 0.04], op="H", rid0=3) + _reqs([0.05], op="Fadj", rid0=5))
+    srv = Server(ex, max_batch=16, clock=clk, sleep=clk.sleep)
+    done = srv.run(reqs)
+    assert len(done) == 6
+    batches = [b for (_, _, b) in ex.launched]
+    assert batches[0] == [0]                 # alone: nothing else had arrived
+    assert batches[1] == [1]                 # the oldest waiting request leads (F)
+    assert batches[2] == [2]                 # H over 8 shots: another shot set
+    assert batches[3] == [3, 4]              # H over the 4-shot set, together
+    assert batches[4] == [5]
+    for b in batches:
+        assert len({(reqs[i].op, tuple(reqs[i].shots)) for i in b}) == 1
+
+
 def test_poisson_stream_is_seeded_and_summary_percentiles():
     shapes = {"s": {16: list(range(16)), 32: list(range(16, 48))}}
     a = poisson_requests(20.0, 5.0, shapes, (16, 32), seed=13)
@@ -98,6 +118,8 @@ def test_poisson_stream_is_seeded_and_summary_percentiles():
     assert [r.arrival for r in a] == [r.arrival for r in b]
     assert 60 <= len(a) <= 140                            # ~100 expected
     assert all(len(r.shots) in (16, 32) for r in a)
+    m = poisson_requests(20.0, 5.0, shapes, (16, 32), seed=13, ops=("H", "F", "Fadj"))
+    assert {r.op for r in m} == {"H", "F", "Fadj"}
     for i, r in enumerate(a):
         r.finished = r.arrival + 0.01 * (i % 10 + 1)
         r.cell_steps = 1e9
