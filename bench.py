@@ -79,10 +79,11 @@ def kernel_bytes3d(kind, w, nsh):
     nsh shots (FP32 fields, FP64 image), P = propagation cells, M = model cells:
       fused:      per shot reads u, D, du, du^{n-1} and writes u, D, du^{n+1}
                   (28 B per cell); kappa and the perturbation once (8 B per cell);
-      background: per shot reads u, D and writes u, D (16 B per cell), writes g
-                  (4 B per model cell); kappa once;
-      adjoint:    per shot reads nu, nu^{k+2} and writes nu^k (12 B per cell), reads g
-                  (4 B per model cell), one FP64 image read-modify-write per pair of
+      background: per shot reads u, D and writes u, D (16 B per cell), writes its slot
+                  (the level u^{n+1} while recomputing from checkpoints; 4 B per model
+                  cell); kappa once;
+      adjoint:    per shot reads nu, nu^{k+2} and writes nu^k (12 B per cell), reads the
+                  slot (4 B per model cell), one FP64 image read-modify-write per pair of
                   shots (8 B per model cell and shot); kappa once.
     The BF16 checkpoint writes (4 B per cell every 8th step) and the receiver traffic
     are left out."""
@@ -782,11 +783,13 @@ def main():
     os.environ["MP_MAX_WAVE"] = str(wave)
     c_dev = torch.from_numpy(c).to(dev)
     y_dev = [torch.from_numpy(y).to(dev) for y in ys]
-    P = M.Problem.from_spec(w, timing=True)
-    P.set_background(c_dev)
     if args.full_record:
+        # one apply_H over the full 2000-step record, shot waves as the engine plans them
+        P = M.Problem.from_spec(w, timing=True)
+        P.set_background(c_dev)
         torch.cuda.synchronize()
         P.stats()
+        print(f"apply_H over {w.nt} steps, waves of {wave} shots", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         P.apply_H(y_dev[0])
         torch.cuda.synchronize()
@@ -798,6 +801,8 @@ def main():
                           "gcell_steps_per_s": round(w.cell_steps / wall / 1e9, 3),
                           "sweeps": sweep_table(st, bytes_of)}), flush=True)
         return
+    P = M.Problem.from_spec(w, timing=True)
+    P.set_background(c_dev)
     B = M.Basis(w.legendre, w.qs, w.ndim)
     xs = [torch.empty_like(y) for y in y_dev]
     out = torch.empty_like(y_dev[0])

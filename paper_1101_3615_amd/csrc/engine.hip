@@ -649,12 +649,12 @@ class EngineT final : public Engine {
       const int n0 = j * kk;
       const int len = std::min(kk, cfg_.nt - n0);
       if ((rc = span_begin(MP_SWEEP_BACKGROUND, (len + 1) / 2, &sp, len))) return rc;
-      p.u_cur = r.bg[0];
-      p.u_inc = r.bg[1];
-      expand(p, nbg, ck, j, stream_);
+      // the segment's first launch reads (u^{n0}, D^{n0}) from checkpoint j itself
+      const int ckl = ck == CK_BF16 ? CK_LBF16 : CK_LF32;
       for (int n = n0; n < n0 + len;) {
         const int ns = std::min(2, n0 + len - n);
-        launch_bg(p, r, nbg, ns, CK_NONE, n, n - n0, ns == 2 ? n + 1 - n0 : -1, -1, -1);
+        launch_bg(p, r, nbg, ns, n == n0 ? ckl : CK_NONE, n, n - n0, ns == 2 ? n + 1 - n0 : -1,
+                  n == n0 ? j : -1, -1);
         n += ns;
       }
       if ((rc = span_end(sp))) return rc;

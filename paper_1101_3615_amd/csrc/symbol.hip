@@ -463,21 +463,46 @@ __global__ __launch_bounds__(256) void k_cqr_pass(Small* W, int p, long long m, 
   }
 }
 
-// Columns 0..p-1 of A <- A M (M upper triangular, from the pass kernel).
+// Columns 0..p-1 of A <- A M (M upper triangular, from the pass kernel).  One row
+// per thread, its p values in registers: the column count is a template bound PB
+// (p rounded up to a multiple of 8) and the sum over the row runs over all PB
+// entries, so that every index into the row is a compile-time constant (a
+// runtime-indexed array would live in scratch memory).  M is held with zeros below
+// the diagonal and past p, and row entries past p read as zero: each output is the
+// sum over i <= j in increasing i followed by exact zeros, the same bits.
+template <int PB>
 __global__ __launch_bounds__(256) void k_qupdate(double* A, long long lda, long long nrows, int p, const Small* W) {
-  __shared__ double M[MAXP * MAXP];
-  for (int t = threadIdx.x; t < p * p; t += blockDim.x) M[t / p * MAXP + t % p] = W->M[t / p * MAXP + t % p];
+  __shared__ double M[PB * PB];
+  for (int t = threadIdx.x; t < PB * PB; t += blockDim.x) {
+    const int i = t / PB, j = t % PB;
+    M[t] = (i <= j && j < p) ? W->M[i * MAXP + j] : 0.0;
+  }
   __syncthreads();
   if (W->status) return;
   for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (long long)gridDim.x * blockDim.x) {
-    double a[MAXP];
-#pragma unroll 8
-    for (int i = 0; i < p; ++i) a[i] = A[(long long)i * lda + r];
-    for (int j = p - 1; j >= 0; --j) {
+    double a[PB];
+#pragma unroll
+    for (int i = 0; i < PB; ++i) a[i] = i < p ? A[(long long)i * lda + r] : 0.0;
+    for (int j = 0; j < p; ++j) {
       double s = 0.0;
-      for (int i = 0; i <= j; ++i) s += a[i] * M[i * MAXP + j];
+#pragma unroll
+      for (int i = 0; i < PB; ++i) s += a[i] * M[i * PB + j];
       A[(long long)j * lda + r] = s;
     }
+  }
+}
+
+static void qupdate(dim3 grid, hipStream_t s, double* A, long long lda, long long nrows, int p, const Small* W) {
+  const int pb = (p + 7) / 8 * 8;
+  switch (pb) {
+    case 8: hipLaunchKernelGGL(k_qupdate<8>, grid, dim3(256), 0, s, A, lda, nrows, p, W); break;
+    case 16: hipLaunchKernelGGL(k_qupdate<16>, grid, dim3(256), 0, s, A, lda, nrows, p, W); break;
+    case 24: hipLaunchKernelGGL(k_qupdate<24>, grid, dim3(256), 0, s, A, lda, nrows, p, W); break;
+    case 32: hipLaunchKernelGGL(k_qupdate<32>, grid, dim3(256), 0, s, A, lda, nrows, p, W); break;
+    case 40: hipLaunchKernelGGL(k_qupdate<40>, grid, dim3(256), 0, s, A, lda, nrows, p, W); break;
+    case 48: hipLaunchKernelGGL(k_qupdate<48>, grid, dim3(256), 0, s, A, lda, nrows, p, W); break;
+    case 56: hipLaunchKernelGGL(k_qupdate<56>, grid, dim3(256), 0, s, A, lda, nrows, p, W); break;
+    default: hipLaunchKernelGGL(k_qupdate<64>, grid, dim3(256), 0, s, A, lda, nrows, p, W); break;
   }
 }
 
@@ -944,12 +969,12 @@ static int fit_t(mp_ctx* ctx, const Basis& b, int T_, const void* const* y, cons
   SY_HIP(hipMemcpyAsync(W->G, ws->G0.get(), sizeof(double) * (p + 1) * (p + 1), hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(k_cqr_pass, dim3(1), dim3(256), 0, s, W, p, nrows, 0);
   SY_LAUNCH();
-  hipLaunchKernelGGL(k_qupdate, qgrid, dim3(256), 0, s, A, lda, nrows, p, W);
+  qupdate(qgrid, s, A, lda, nrows, p, W);
   SY_LAUNCH();
   if ((rc = gram(W->G))) return rc;
   hipLaunchKernelGGL(k_cqr_pass, dim3(1), dim3(256), 0, s, W, p, nrows, 1);
   SY_LAUNCH();
-  hipLaunchKernelGGL(k_qupdate, qgrid, dim3(256), 0, s, A, lda, nrows, p, W);
+  qupdate(qgrid, s, A, lda, nrows, p, W);
   SY_LAUNCH();
   if ((rc = gram(W->G))) return rc;
   hipLaunchKernelGGL(k_cqr_solve, dim3(1), dim3(256), 0, s, W, p);

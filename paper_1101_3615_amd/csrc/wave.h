@@ -78,8 +78,10 @@ struct Step {
   int nck;                   // checkpoints per shot
 };
 
-// Checkpoint encodings of the background sweep.
-enum { CK_NONE = 0, CK_F32 = 1, CK_BF16 = 2 };
+// Checkpoint encodings of the background sweep: written by the launch (CK_F32,
+// CK_BF16), or read as the launch's input levels (CK_LF32, CK_LBF16: 2D, the first
+// recomputed launch of a segment, in place of a separate expansion pass).
+enum { CK_NONE = 0, CK_F32 = 1, CK_BF16 = 2, CK_LF32 = 3, CK_LBF16 = 4 };
 // Sweep kernels.
 enum { M_FUSED = 0, M_BORN = 1, M_BG = 2, M_ADJ = 3 };
 
@@ -88,7 +90,7 @@ enum { M_FUSED = 0, M_BORN = 1, M_BG = 2, M_ADJ = 3 };
 // computed is nu^k); hs1, hs2: g slots of the two steps (written by M_BG, -1 for
 // none; read by M_BORN and M_ADJ; u^{n+1} instead of g^n when p.hist_u); ck:
 // CK_* encoding of M_BG; ck_store: checkpoint written from the launch's input
-// level (u^n, D^n) or -1; ck_max: checkpoint whose BF16 scales take the maxima
+// level (u^n, D^n) (CK_F32, CK_BF16), or read as that level (CK_LF32, CK_LBF16), or -1; ck_max: checkpoint whose BF16 scales take the maxima
 // of the launch's last level or -1;
 // zc > 0 forces the z-chunk height.  nsh: shots in the wave.
 void sweep2d(int mode, int nsteps, int ck, const Step<float>& p, int nsh, int n, int hs1, int hs2, int ck_store,

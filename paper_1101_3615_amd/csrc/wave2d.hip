@@ -356,6 +356,35 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
 
   // row offsets wrap to past the end of the resource for rows above the grid
   auto frow = [&](int z) -> unsigned { return vo + (unsigned)z * rowb; };
+  // Input levels (u^n, D^n): the field slices, or (CK_LF32 / CK_LBF16) checkpoint
+  // ck_store in its compact layout [z][cpitch], converted as the expansion pass
+  // would (same bits).  A lane outside [0, nxp) and rows outside [0, nzp) read zero
+  // through the range check; a pair never reaches past a compact row (x is even,
+  // and cpitch > nxp when nxp is odd).
+  constexpr bool LDCK = (CK == CK_LF32 || CK == CK_LBF16);
+  constexpr unsigned cesz = (CK == CK_LBF16) ? 2u : (unsigned)sizeof(T);
+  const long long lvl = ((long long)ls * p.nck + max(ck_store, 0)) * 2;
+  const Rsrc rC0 = rsrc(LDCK ? static_cast<char*>(p.ck) + lvl * p.cstride * cesz : static_cast<char*>(p.ck),
+                        LDCK ? p.cstride * (long long)cesz : 0);
+  const Rsrc rC1 = rsrc(LDCK ? static_cast<char*>(p.ck) + (lvl + 1) * p.cstride * cesz : static_cast<char*>(p.ck),
+                        LDCK ? p.cstride * (long long)cesz : 0);
+  const unsigned cvo = xin ? (unsigned)x * cesz : OFF_NONE;
+  const unsigned crow = (unsigned)p.cpitch * cesz;
+  float cs0 = 1.0f, cs1 = 1.0f;
+  if (CK == CK_LBF16) {
+    cs0 = p.ck_scale[lvl];
+    cs1 = p.ck_scale[lvl + 1];
+  }
+  auto in_row = [&](int lev, int z) -> V2<T> {
+    if (!LDCK) return bld2(lev ? rI1 : rI0, frow(z), 0u, T(0));
+    if (CK == CK_LF32) return bld2(lev ? rC1 : rC0, cvo + (unsigned)z * crow, 0u, T(0));
+    const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(lev ? rC1 : rC0, cvo + (unsigned)z * crow, 0u, 0);
+    const float sc = lev ? cs1 : cs0;
+    V2<T> r;
+    r.v[0] = (T)(bf16_to_f((unsigned short)(w & 0xffffu)) * sc);
+    r.v[1] = (T)(bf16_to_f((unsigned short)(w >> 16)) * sc);
+    return r;
+  };
   // g rows: a pair that ends past nx stores zero into the model row's pad column,
   // so loads of such a pair need no mask
   auto gld = [&](const Rsrc& r, unsigned vo_lane, int zm) -> V2<T> {
@@ -441,8 +470,8 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
   const int nit = (z1 - z0) + ((NS == 2) ? 8 : 0);          // level-1 rows of the march
   const int zs = (d > 0) ? ((NS == 2) ? z0 - 4 : z0) : ((NS == 2) ? z1 + 3 : z1 - 1);
   auto fetch = [&](int z, RowIn<T>& f) {
-    f.q = bld2(rI0, frow(z + 4 * d), 0u, T(0));
-    f.pv = bld2(rI1, frow(z), 0u, T(0));
+    f.q = in_row(0, z + 4 * d);
+    f.pv = in_row(1, z);
     f.k1 = bld2(rK, frow(z), 0u, T(0));
     if (MODE == M_BORN) {
       f.m1 = bld2(rM, frow(z), 0u, T(0));
@@ -470,7 +499,7 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
   // at the centre of level 2 (kept in LDS: each wave reads only its own entries)
   __shared__ V2<T> dq[(BG && NS == 2) ? GW2 : 1][9][(BG && NS == 2) ? LANES : 1];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) q0[s] = bld2(rI0, frow(zs + (s - 4) * d), 0u, T(0));
+  for (int s = 0; s < 8; ++s) q0[s] = in_row(0, zs + (s - 4) * d);
 #pragma unroll
   for (int s = 0; s < 7; ++s) e0[s] = diff(q0[s + 1], q0[s]);
   if (NS == 2) q1[8] = zero2<T>();
@@ -537,7 +566,7 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
         }
         if (out_row) {
           if (BG) {
-            if (CK != CK_NONE && ck_store >= 0) ckstore(z, c0, cur.pv);
+            if ((CK == CK_F32 || CK == CK_BF16) && ck_store >= 0) ckstore(z, c0, cur.pv);
             gst(rH1, z - nb, p.hist_u ? nv.v : g);
             if (NS == 1) {
               bst2(nv, rO0, vs + so, 0u);
@@ -766,6 +795,8 @@ template <typename T, int MODE, int NS>
 static void go_ck(int ck, const Step<T>& p, int nsh, int n, int hs1, int hs2, int cs, int cm, int zc, hipStream_t st) {
   if (MODE == M_BG && ck == CK_F32) go<T, MODE, NS, CK_F32>(p, nsh, n, hs1, hs2, cs, cm, zc, st);
   else if (MODE == M_BG && ck == CK_BF16) go<T, MODE, NS, CK_BF16>(p, nsh, n, hs1, hs2, cs, cm, zc, st);
+  else if (MODE == M_BG && ck == CK_LF32) go<T, MODE, NS, CK_LF32>(p, nsh, n, hs1, hs2, cs, -1, zc, st);
+  else if (MODE == M_BG && ck == CK_LBF16) go<T, MODE, NS, CK_LBF16>(p, nsh, n, hs1, hs2, cs, -1, zc, st);
   else go<T, MODE, NS, CK_NONE>(p, nsh, n, hs1, hs2, -1, -1, zc, st);
 }
 
