@@ -123,13 +123,14 @@ def _sha(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-TRAFFIC = {"2d": ("traffic.json", "wave2d.hip"), "3d": ("traffic_c5.json", "wave3d.hip")}
+TRAFFIC = {"2d": ("traffic.json", "wave2d.hip"), "3d": ("traffic_c5.json", "wave3d.hip"),
+           "c3": ("traffic_c3.json", "wave2d.hip")}
 
 
 def traffic_for(kind, w):
     """Measured HBM bytes per launch from the committed counter summary, if it was taken
     on this workload with the kernel source as it is now (else None)."""
-    rec_name, src_name = TRAFFIC["3d" if w.ndim == 3 else "2d"]
+    rec_name, src_name = TRAFFIC["3d" if w.ndim == 3 else "c3" if w.name.startswith("c3_") else "2d"]
     try:
         with open(os.path.join(ROOT, "profiles", rec_name)) as f:
             rec = json.load(f)
@@ -219,30 +220,35 @@ def serve_leg(seconds, rate=20.0, seed=13):
 
 
 def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, dims):
-    """profiles/traffic.json (2D, 512 x 256 workload) or profiles/traffic_c5.json (3D,
-    256^3 workload) from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this
-    benchmark and of the copy probe: per sweep kernel, HBM bytes per launch = mean counter
-    (KiB) x 1024 x (copy bytes / the copy kernel's reading of the same counter)."""
+    """profiles/traffic.json (dims 2d: the 512 x 256 workload), traffic_c3.json (c3: the
+    1024 x 512 checkpointed workload) or traffic_c5.json (3d: the 256^3 workload) from
+    two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of a run of that workload and of
+    the copy probe: per sweep kind, HBM bytes per launch = mean counter (KiB) x 1024 x
+    (copy bytes / the copy kernel's reading of the same counter), averaged over the
+    kind's kernel variants (e.g. background launches that store, read or skip
+    checkpoints) weighted by their launch counts."""
     import csv
     import glob
     import re
 
     import fixtures as F
 
-    def means(d):
+    def sums(d):
         f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
         acc = {}
         for r in csv.DictReader(open(f)):
-            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in acc.items()}
+            a = acc.setdefault(r["Kernel_Name"], [0.0, 0])
+            a[0] += float(r["Counter_Value"])
+            a[1] += 1
+        return acc
 
     copy_bytes = copy_mib * (1 << 20)
-    cf = [v for k, v in means(copy_fetch_dir).items() if "copyBuffer" in k][0]
-    cw = [v for k, v in means(copy_write_dir).items() if "copyBuffer" in k][0]
+    cf = [v[0] / v[1] for k, v in sums(copy_fetch_dir).items() if "copyBuffer" in k][0]
+    cw = [v[0] / v[1] for k, v in sums(copy_write_dir).items() if "copyBuffer" in k][0]
     f_fac = copy_bytes / (cf * 1024.0)
     w_fac = copy_bytes / (cw * 1024.0)
-    fe, wr = means(fetch_dir), means(write_dir)
-    kernels = {}
+    fe, wr = sums(fetch_dir), sums(write_dir)
+    acc = {}
     for name in fe:
         if dims == "3d":
             m = re.search(r"k_step3d<float, (\d), (\d)>", name)
@@ -252,11 +258,19 @@ def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_m
             ok = m is not None and m.group(2) == "2"
         if not ok or name not in wr:
             continue
-        kind = KIND_OF_MODE[m.group(1)]
-        kernels[kind] = {"kernel": name, "fetch_kib_raw": fe[name], "write_kib_raw": wr[name],
-                         "bytes_per_launch": fe[name] * 1024.0 * f_fac + wr[name] * 1024.0 * w_fac}
+        a = acc.setdefault(KIND_OF_MODE[m.group(1)], {"kernels": [], "fetch": 0.0, "write": 0.0, "launches": 0})
+        a["kernels"].append(name)
+        a["fetch"] += fe[name][0]
+        a["write"] += wr[name][0]
+        a["launches"] += fe[name][1]
+    kernels = {}
+    for kind, a in acc.items():
+        n = a["launches"]
+        kernels[kind] = {"kernel": a["kernels"][0] if len(a["kernels"]) == 1 else a["kernels"], "launches": n,
+                         "fetch_kib_raw": a["fetch"] / n, "write_kib_raw": a["write"] / n,
+                         "bytes_per_launch": (a["fetch"] * f_fac + a["write"] * w_fac) * 1024.0 / n}
     rec_name, src_name = TRAFFIC[dims]
-    rec = {"workload": (F.c5() if dims == "3d" else F.c2()).name,
+    rec = {"workload": {"3d": F.c5(), "c3": F.c3(), "2d": F.c2()}[dims].name,
            "source_sha256": _sha(os.path.join(ROOT, "paper_1101_3615_amd", "csrc", src_name)),
            "fetch_scale": f_fac, "write_scale": w_fac, "copy_probe_bytes": copy_bytes, "kernels": kernels}
     with open(os.path.join(ROOT, "profiles", rec_name), "w") as f:
@@ -635,6 +649,8 @@ def c2_leg(steps, copy_gbs):
     bytes_of = lambda k, sl: kernel_bytes(k, w, round(sl))
     res = {"workload": w.name, "value": round(len(ys) * w.cell_steps / wall / 1e9, 3), "unit": "Gcell-steps/s",
            "ms_per_step": round(1e3 * wall, 2), "steps": steps, "dtype": "f32", "snapshots": "fp32 full g history",
+           "value_is": "apply_H cell-steps of both trials per second of the pass; the first application "
+                       "computes and keeps the g history, the second reuses it (no background sweep)",
            "roofline": roofline_of(st, w, bytes_of, copy_gbs), "sweeps": sweep_table(st, bytes_of)}
     P.close()
     return res
@@ -716,8 +732,8 @@ def main():
                     help="length of the Poisson serving run (0: skip the serving leg)")
     ap.add_argument("--ingest-counters", nargs=5,
                     metavar=("DIMS", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
-                    help="DIMS = 2d or 3d: write profiles/traffic.json or traffic_c5.json from rocprofv3 --pmc "
-                         "output folders and exit")
+                    help="DIMS = 2d, c3 or 3d: write profiles/traffic.json, traffic_c3.json or traffic_c5.json "
+                         "from rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
     if args.ingest_counters:
         dims, *dirs = args.ingest_counters

@@ -761,9 +761,10 @@ class EngineT final : public Engine {
       const int n0 = j * kk;
       const int len = std::min(kk, cfg_.nt - n0);
       if ((rc = span_begin(MP_SWEEP_BACKGROUND, len, &sp))) return rc;
-      expand(pb, nbg, ck, j, stream_);
+      // the segment's first step reads (u^{n0}, D^{n0}) from checkpoint j itself
+      const int ckl = ck == CK_BF16 ? CK_LBF16 : CK_LF32;
       for (int n = n0; n < n0 + len; ++n) {
-        step(M_BG, pb, n, n - n0, CK_NONE, -1, -1);
+        step(M_BG, pb, n, n - n0, n == n0 ? ckl : CK_NONE, n == n0 ? j : -1, -1);
         std::swap(pb.u_cur, pb.u_next);
       }
       if ((rc = span_end(sp))) return rc;

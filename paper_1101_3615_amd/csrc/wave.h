@@ -53,7 +53,7 @@ struct Step {
   T* in1;                    // background increment D^n / field level -1
   T* out0;                   // background u^{n+NS} / field level 1
   T* out1;                   // background D^{n+NS} / field level 2
-  // 3D sweeps (one step per launch) and checkpoint expansion
+  // 3D sweeps (one step per launch)
   T* u_cur;                  // background level n (read)
   T* u_next;                 // background level n+1 (written)
   T* u_inc;                  // background increment u^n - u^{n-1}, updated in place
@@ -79,7 +79,7 @@ struct Step {
 };
 
 // Checkpoint encodings of the background sweep: written by the launch (CK_F32,
-// CK_BF16), or read as the launch's input levels (CK_LF32, CK_LBF16: 2D, the first
+// CK_BF16), or read as the launch's input levels (CK_LF32, CK_LBF16: the first
 // recomputed launch of a segment, in place of a separate expansion pass).
 enum { CK_NONE = 0, CK_F32 = 1, CK_BF16 = 2, CK_LF32 = 3, CK_LBF16 = 4 };
 // Sweep kernels.
@@ -89,24 +89,21 @@ enum { M_FUSED = 0, M_BORN = 1, M_BG = 2, M_ADJ = 3 };
 // mode: M_BG, M_BORN or M_ADJ; n: first step (adjoint: k, the first level
 // computed is nu^k); hs1, hs2: g slots of the two steps (written by M_BG, -1 for
 // none; read by M_BORN and M_ADJ; u^{n+1} instead of g^n when p.hist_u); ck:
-// CK_* encoding of M_BG; ck_store: checkpoint written from the launch's input
-// level (u^n, D^n) (CK_F32, CK_BF16), or read as that level (CK_LF32, CK_LBF16), or -1; ck_max: checkpoint whose BF16 scales take the maxima
-// of the launch's last level or -1;
-// zc > 0 forces the z-chunk height.  nsh: shots in the wave.
+// CK_* encoding of M_BG; ck_store: the checkpoint written from the launch's input
+// level (u^n, D^n) (CK_F32, CK_BF16) or read as that level (CK_LF32, CK_LBF16),
+// or -1; ck_max: checkpoint whose BF16 scales take the maxima of the launch's
+// last level or -1; zc > 0 forces the z-chunk height.  nsh: shots in the wave.
 void sweep2d(int mode, int nsteps, int ck, const Step<float>& p, int nsh, int n, int hs1, int hs2, int ck_store,
              int ck_max, int zc, hipStream_t s);
 void sweep2d(int mode, int nsteps, int ck, const Step<double>& p, int nsh, int n, int hs1, int hs2, int ck_store,
              int ck_max, int zc, hipStream_t s);
 // 3D: one time step of every shot of a wave.  mode: M_*; n: step (adjoint: k);
 // hslot: g slot written (background modes; -1: none) or read (Born, adjoint;
-// u^{n+1} instead of g^n when p.hist_u);
-// ck: CK_* encoding; ck_store: checkpoint written from (u^n, u^{n-1}) at this
-// step or -1; ck_max: checkpoint whose BF16 scales accumulate max |u^{n+1}| and
-// max |u^{n+1} - u^n| at this step or -1.
+// u^{n+1} instead of g^n when p.hist_u); ck: CK_* encoding; ck_store: the
+// checkpoint written from (u^n, u^{n-1}) at this step (CK_F32, CK_BF16) or read
+// as that level (CK_LF32, CK_LBF16), or -1; ck_max: checkpoint whose BF16 scales
+// accumulate max |u^{n+1}| and max |u^{n+1} - u^n| at this step or -1.
 void step3d(int mode, const Step<float>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
 void step3d(int mode, const Step<double>& p, int n, int hslot, int ck, int ck_store, int ck_max, hipStream_t s);
-// u_cur <- u^{jk}, u_inc <- u^{jk} - u^{jk-1} from checkpoint j for the wave's shots
-void expand(const Step<float>& p, int nshots, int ck, int j, hipStream_t s);
-void expand(const Step<double>& p, int nshots, int ck, int j, hipStream_t s);
 
 }  // namespace mp

@@ -690,40 +690,6 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
   }
 }
 
-// u_cur <- u^{jk}, u_inc <- u^{jk} - u^{jk-1} on the propagation cells of every
-// local shot (2D and 3D layouts).
-template <typename T, int CK>
-__global__ void k_expand(Step<T> p, int nshots, int j) {
-  const long long cells = (long long)p.L.nzp * p.L.nyp * p.L.nxp;
-  const long long total = cells * nshots;
-  const int gy = (p.L.ndim == 3) ? GY : 0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
-    const int ls = (int)(i / cells);
-    const long long c = i % cells;
-    const int x = (int)(c % p.L.nxp);
-    const long long t = c / p.L.nxp;
-    const int y = (int)(t % p.L.nyp);
-    const int z = (int)(t / p.L.nyp);
-    const long long fo = (long long)ls * p.L.fstride + SLACK + (long long)(z + GZ) * p.L.plane +
-                         (long long)(y + gy) * p.L.pitch + XL + x;
-    const long long lv = ((long long)ls * p.nck + j) * 2;
-    const long long co = ((long long)z * p.L.nyp + y) * p.cpitch + x;
-    T un, ui;
-    if (CK == CK_F32) {
-      const T* c0 = static_cast<const T*>(p.ck) + lv * p.cstride + co;
-      un = c0[0];
-      ui = c0[p.cstride];
-    } else {
-      const unsigned short* c0 = static_cast<const unsigned short*>(p.ck) + lv * p.cstride + co;
-      const float s0 = p.ck_scale[lv], s1 = p.ck_scale[lv + 1];
-      un = (T)(bf16_to_f(c0[0]) * s0);
-      ui = (T)(bf16_to_f(c0[p.cstride]) * s1);
-    }
-    p.u_cur[fo] = un;
-    p.u_inc[fo] = ui;
-  }
-}
-
 // ---- host side ----
 
 static int device_cus() {
@@ -815,15 +781,6 @@ static void sweep_t(int mode, int nsteps, int ck, const Step<T>& p, int nsh, int
   }
 }
 
-template <typename T>
-static void expand_t(const Step<T>& p, int nshots, int ck, int j, hipStream_t st) {
-  const long long total = (long long)p.L.nzp * p.L.nyp * p.L.nxp * nshots;
-  long long b = (total + 255) / 256;
-  if (b > 65536) b = 65536;
-  if (ck == CK_F32) hipLaunchKernelGGL((k_expand<T, CK_F32>), dim3((unsigned)b), dim3(256), 0, st, p, nshots, j);
-  else hipLaunchKernelGGL((k_expand<T, CK_BF16>), dim3((unsigned)b), dim3(256), 0, st, p, nshots, j);
-}
-
 void sweep2d(int mode, int nsteps, int ck, const Step<float>& p, int nsh, int n, int hs1, int hs2, int cs, int cm,
              int zc, hipStream_t s) {
   sweep_t(mode, nsteps, ck, p, nsh, n, hs1, hs2, cs, cm, zc, s);
@@ -832,7 +789,5 @@ void sweep2d(int mode, int nsteps, int ck, const Step<double>& p, int nsh, int n
              int zc, hipStream_t s) {
   sweep_t(mode, nsteps, ck, p, nsh, n, hs1, hs2, cs, cm, zc, s);
 }
-void expand(const Step<float>& p, int ns, int ck, int j, hipStream_t s) { expand_t(p, ns, ck, j, s); }
-void expand(const Step<double>& p, int ns, int ck, int j, hipStream_t s) { expand_t(p, ns, ck, j, s); }
 
 }  // namespace mp

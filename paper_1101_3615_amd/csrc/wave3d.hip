@@ -10,8 +10,9 @@
 //   y-neighbours: the tile's centre plane plus 4 halo rows above and below,
 //                 staged in LDS (double buffered: one barrier per plane).
 // Every input of a plane (queue row, halos, kappa, previous level, g, image) is
-// loaded through buffer resources at the start of the plane; lanes and planes
-// outside the grid read zero from the hardware range check instead of branching.
+// loaded through buffer resources one plane ahead (FP32 sweeps), so its latency
+// overlaps the work on the plane before; lanes and planes outside the grid read
+// zero from the hardware range check instead of branching.
 // Workgroups are persistent and walk their XCD's items pairs of shots fastest, so
 // the pairs of a tile share its kappa and perturbation through that XCD's L2.
 // The arithmetic per cell is that of the 2D kernel with the y axis added,
@@ -286,11 +287,45 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
   const unsigned hvo = hload ? (unsigned)((long long)(hy + GY) * pitch + XL + hx) * esz : OFF_NONE3;
   const Rsrc3 rHv = hfieldB ? rBc : rAc;
 
-  // Inputs of one z plane, loaded at the start of the plane (the loads of a plane
-  // are independent, so they are all in flight together).  Loading them one plane
-  // ahead instead gave wrong, non-repeatable fields for the odd shot of a pair
-  // once a launch held two or more pairs, even with a full wait before the
-  // prefetched plane was used; it is not used (3 % slower at 256^3).
+  // CK_LF32 / CK_LBF16 (background recomputation, first step of a segment): the
+  // input level u^n and increment D^n come from checkpoint ck_store in its compact
+  // layout [z][y][cpitch], converted as the expansion pass would (same bits), in
+  // place of the field slices; the same lane masks apply, and planes outside
+  // [0, nzp) wrap past the resource.
+  constexpr bool LDCK = (CK == CK_LF32 || CK == CK_LBF16);
+  constexpr unsigned cesz = (CK == CK_LBF16) ? 2u : (unsigned)sizeof(T);
+  const long long clv = ((long long)ls * p.nck + max(ck_store, 0)) * 2;
+  const Rsrc3 rC0 = rsrc3(LDCK ? static_cast<char*>(p.ck) + clv * p.cstride * cesz : static_cast<char*>(p.ck),
+                          LDCK ? p.cstride * (long long)cesz : 0);
+  const Rsrc3 rC1 = rsrc3(LDCK ? static_cast<char*>(p.ck) + (clv + 1) * p.cstride * cesz : static_cast<char*>(p.ck),
+                          LDCK ? p.cstride * (long long)cesz : 0);
+  const unsigned clvo = act ? (unsigned)((long long)y * p.cpitch + x) * cesz : OFF_NONE3;
+  const unsigned cxvo = hl_in   ? (unsigned)((long long)y * p.cpitch + x - 4) * cesz
+                        : hr_in ? (unsigned)((long long)y * p.cpitch + x + 4) * cesz
+                                : OFF_NONE3;
+  const unsigned chvo = hload ? (unsigned)((long long)hy * p.cpitch + hx) * cesz : OFF_NONE3;
+  const unsigned cplane = (unsigned)((long long)nyp * p.cpitch * cesz);
+  float cs0 = 1.0f, cs1 = 1.0f;
+  if (CK == CK_LBF16) {
+    cs0 = p.ck_scale[clv];
+    cs1 = p.ck_scale[clv + 1];
+  }
+  auto ldck = [&](int lev, unsigned lo, int zz) -> V4<T> {
+    const unsigned off = lo + (unsigned)zz * cplane;
+    if (CK == CK_LF32) return bld4(lev ? rC1 : rC0, off, 0u, T(0));
+    const u32x2_3 w = __builtin_amdgcn_raw_buffer_load_b64(lev ? rC1 : rC0, off, 0u, 0);
+    const float sc = lev ? cs1 : cs0;
+    V4<T> r;
+    r.v[0] = (T)(bf16_to_f((unsigned short)(w.x & 0xffffu)) * sc);
+    r.v[1] = (T)(bf16_to_f((unsigned short)(w.x >> 16)) * sc);
+    r.v[2] = (T)(bf16_to_f((unsigned short)(w.y & 0xffffu)) * sc);
+    r.v[3] = (T)(bf16_to_f((unsigned short)(w.y >> 16)) * sc);
+    return r;
+  };
+
+  // Inputs of one z plane.  FP32 sweeps load them one plane ahead (a second set of
+  // registers); FP64 sweeps (small test grids, twice the registers) at the start
+  // of the plane.
   struct In3 {
     V4<T> qa, qb;          // plane z + 4 of fields A, B (enters the queue)
     V4<T> hv;              // y-halo row of plane z (field A or B)
@@ -301,19 +336,27 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
   };
   auto fetch = [&](int z, In3& f) {
     const unsigned s = soff(z);
-    f.qa = bld4(rAc, lvo, soff(z + 4), T(0));
+    if (LDCK) {
+      f.qa = ldck(0, clvo, z + 4);
+      f.hv = ldck(0, chvo, z);
+      f.xa = ldck(0, cxvo, z);
+      f.ap = ldck(1, clvo, z);
+    } else {
+      f.qa = bld4(rAc, lvo, soff(z + 4), T(0));
+      f.hv = bld4(rHv, hvo, s, T(0));
+      f.xa = bld4(rAc, xvo, s, T(0));
+      f.ap = bld4<NT3>(rAp, lvo, s, T(0));
+    }
     if (TWO) f.qb = bld4(rBc, lvo, soff(z + 4), T(0));
-    f.hv = bld4(rHv, hvo, s, T(0));
-    f.xa = bld4(rAc, xvo, s, T(0));
     if (TWO) f.xb = bld4(rBc, xvo, s, T(0));
     f.kap = bld4(rK, lvo, s, T(0));
-    f.ap = bld4<NT3>(rAp, lvo, s, T(0));
     if (TWO) f.bp = bld4<NT3>(rBp, lvo, s, T(0));
     if (TWO || MODE == M_BORN) f.dm = bld4<NT3>(rM, lvo, s, T(0));
     const unsigned zm = (unsigned)(z - nb);
     if (MODE == M_BORN || MODE == M_ADJ) f.g = bld4<NT3>(rG, gvo + zm * gplane, 0u, T(0));
     if (MODE == M_ADJ) f.im = bld4<NT3>(rI, ivo + (zm - 1u) * iplane, 0u, double(0));
   };
+  constexpr bool PF3 = sizeof(T) == 4;
 
   // Image of plane zz for the pair: old + (even half's + odd half's contribution),
   // written by the even half (the contributions were put in LDS before a barrier)
@@ -332,17 +375,19 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
   V4<T> qa[9], qb[9];
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
-    qa[s] = bld4(rAc, lvo, soff(z0 - 4 + s), T(0));
+    qa[s] = LDCK ? ldck(0, clvo, z0 - 4 + s) : bld4(rAc, lvo, soff(z0 - 4 + s), T(0));
     if (TWO) qb[s] = bld4(rBc, lvo, soff(z0 - 4 + s), T(0));
   }
-  In3 cur;
+  In3 cur, nxt;
+  if (PF3) fetch(z0, cur);
 
   for (int zb = z0; zb < z1; zb += 9) {
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
       const int z = zb + r;
       if (z < z1) {   // uniform; a constant trip count keeps the loop fully unrolled
-        fetch(z, cur);
+        if (PF3) fetch(min(z + 1, z1 - 1), nxt);   // the last plane reloads itself
+        else fetch(z, cur);
         qa[(r + 8) % 9] = cur.qa;
         if (TWO) qb[(r + 8) % 9] = cur.qb;
         // centre rows and y halo into LDS
@@ -438,7 +483,7 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
           bst4<NT3>(bnew, rBp, lvo, sz_);
         }
 
-        if (CK != CK_NONE && BGM && ck_store >= 0 && act) {
+        if ((CK == CK_F32 || CK == CK_BF16) && BGM && ck_store >= 0 && act) {
           const long long co = ((long long)z * nyp + y) * p.cpitch + x;
           const long long lv = ((long long)ls * p.nck + ck_store) * 2;
           if (CK == CK_F32) {
@@ -508,6 +553,7 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
           }
           RED[half][z & 1][tid] = cw;
         }
+        if (PF3) cur = nxt;
       }
     }
   }
@@ -566,6 +612,8 @@ static void launch3(int mode, const Step<T>& p, int n, int hs, int ck, int cs, i
     case M_BG:
       if (ck == CK_F32) go3<T, M_BG, CK_F32>(p, n, hs, cs, cm, st);
       else if (ck == CK_BF16) go3<T, M_BG, CK_BF16>(p, n, hs, cs, cm, st);
+      else if (ck == CK_LF32) go3<T, M_BG, CK_LF32>(p, n, hs, cs, -1, st);
+      else if (ck == CK_LBF16) go3<T, M_BG, CK_LBF16>(p, n, hs, cs, -1, st);
       else go3<T, M_BG, CK_NONE>(p, n, hs, -1, -1, st);
       break;
     case M_BORN: go3<T, M_BORN, CK_NONE>(p, n, hs, -1, -1, st); break;

@@ -38,10 +38,9 @@ def test_c3_slice_dot_product_and_finite_differences(snap, tol):
     """1024 x 512, 4000 steps, snapshots every 4 steps (8 of the 128 shots):
     dot-product test and central differences of L = 1/2 ||F dm - d_obs||^2 along
     32 seeded wavepacket directions (L is quadratic, so the central difference is
-    exact up to rounding); tolerance FP32 checkpoints 1e-3, BF16 checkpoints 1e-2 on the
-    relative L2 error of the 32 directional derivatives taken together (a single
-    direction nearly orthogonal to the gradient has a large relative error of its own,
-    so the median and the maximum per direction are printed, not bounded)."""
+    exact up to rounding); tolerance FP32 checkpoints 1e-3, BF16 checkpoints 1e-2, on the
+    relative L2 error of the 32 directional derivatives taken together and on each
+    direction's own relative error (measured worst 3.1e-5 and 5.2e-3)."""
     M, born = _gpu()
     w = _c3_slice(snap)
     c = F.medium(w)
@@ -84,3 +83,4 @@ def test_c3_slice_dot_product_and_finite_differences(snap, tol):
           f"relative L2 {err_all:.3e}, per direction median {np.median(errs):.3e}, max {errs.max():.3e}")
     assert dot_err <= tol
     assert err_all <= tol
+    assert errs.max() <= tol
