@@ -211,7 +211,10 @@ def serve_leg(seconds, rate=20.0, seed=13):
            "batches": srv.nbatches,
            "p50_ms": round(1e3 * load["p50_s"], 3), "p99_ms": round(1e3 * load["p99_s"], 3),
            "offered_gcell_steps_per_s": round(load["gcell_steps_per_s"], 3)}
+    out["admission_waits"] = srv.rejected_waits
     out["capacity_H"] = capacity(reqs)
+    # offered load over the served capacity of the same requests
+    out["rho"] = round(out["offered_gcell_steps_per_s"] / out["capacity_H"]["served_gcell_steps_per_s"], 3)
     mix = poisson_requests(rate, seconds, groups, F.SERVE_SHOTS, seed=seed + 1, make_x=make_x,
                            ops=("H", "F", "Fadj"))
     out["capacity_F_Fadj_H"] = capacity(mix)

@@ -54,7 +54,7 @@ constexpr int MAXP = 64;          // basis terms
 constexpr int GT = 16;            // MFMA tile
 constexpr int GCOL = MAXP + GT;   // padded column count of [A b]
 constexpr int GRB = 64;           // rows per LDS stage of the Gram kernel
-constexpr int GROWS = 4096;       // rows per Gram workgroup
+constexpr int GROWS = 32768;      // rows per Gram workgroup
 
 // ---------------------------------------------------------------- FFT --
 
@@ -301,14 +301,30 @@ __global__ __launch_bounds__(256) void k_gram(const double* A, long long lda, lo
   const long long r0 = (long long)blockIdx.x * GROWS;
   const long long r1 = min(r0 + GROWS, nrows);
   const int ncolp = nt * GT;
-  for (long long rb = r0; rb < r1; rb += GRB) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < ncolp * GRB; t += 256) {
+  // the next stage's rows are loaded into registers while the MFMAs consume the
+  // current one (a fixed count per thread, so that the register array is indexed
+  // by constants)
+  constexpr int LPT = GCOL * GRB / 256;
+  double nx[LPT];
+  auto load = [&](long long rb) {
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int t = (int)threadIdx.x + q * 256;
       const int c = t / GRB, r = t % GRB;
       const long long row = rb + r;
-      tile[c][r] = (c < ncol && row < r1) ? A[(long long)c * lda + row] : 0.0;
+      nx[q] = (t < ncolp * GRB && c < ncol && row < r1) ? A[(long long)c * lda + row] : 0.0;
+    }
+  };
+  load(r0);
+  for (long long rb = r0; rb < r1; rb += GRB) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int t = (int)threadIdx.x + q * 256;
+      if (t < ncolp * GRB) tile[t / GRB][t % GRB] = nx[q];
     }
     __syncthreads();
+    if (rb + GRB < r1) load(rb + GRB);
     for (int k = 0; k < mine; ++k) {
       const int ci = pi[k] * GT + (lane & 15);
       const int cj = pj[k] * GT + (lane & 15);
