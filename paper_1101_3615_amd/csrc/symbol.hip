@@ -278,33 +278,32 @@ __global__ void k_column_copy(double* A, long long lda, int col, long long row0,
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// Partial Gram of the columns [0, ncol) of A over rows [wg*GROWS, ...):
-// part[wg][i][j] for 16x16 tiles with tj >= ti.  One MFMA consumes a 16x4
-// block of rows of column tile ti and of column tile tj.
+// Partial Gram of the columns [0, ncol) of A (NT 16-column tiles) over the GRB-row
+// blocks wg, wg + nwg, wg + 2 nwg, ... (nwg workgroups): part[wg][i][j] for the
+// 16x16 tiles with tj >= ti.  One MFMA consumes a 16x4 block of rows of column
+// tile ti and of column tile tj.  Each wave takes a quarter of the rows of every
+// block for all NT (NT + 1) / 2 tile pairs (accumulators indexed by constants,
+// NP independent MFMA chains per wave, the same work on every SIMD); the four
+// waves' sums are added in a fixed order at the end.  The workgroups of a launch
+// sweep the rows together, so the rows in use at any time lie in one narrow band
+// of each column (few pages, long contiguous runs), not in nwg bands far apart.
+template <int NT>
 __global__ __launch_bounds__(256) void k_gram(const double* A, long long lda, long long nrows, int ncol, double* part) {
-  __shared__ double tile[GCOL][GRB + 1];
+  constexpr int NP = NT * (NT + 1) / 2;
+  constexpr int NCP = NT * GT;                 // padded column count
+  constexpr int TILE = NCP * (GRB + 1);        // LDS stage [NCP][GRB + 1]
+  constexpr int RED = 2 * NP * 256;            // two waves' accumulators
+  __shared__ double lds[TILE > RED ? TILE : RED];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int nt = (ncol + GT - 1) / GT;
-  const int npairs = nt * (nt + 1) / 2;
-  dbl4 acc[4];
-  int pi[4], pj[4];
-  int mine = 0;
-  for (int pr = wv, k = 0; pr < npairs && k < 4; pr += 4, ++k) {
-    int ti = 0, rem = pr;
-    while (rem >= nt - ti) { rem -= nt - ti; ++ti; }
-    pi[k] = ti;
-    pj[k] = ti + rem;
-    acc[k] = (dbl4){0.0, 0.0, 0.0, 0.0};
-    mine = k + 1;
-  }
-  const long long r0 = (long long)blockIdx.x * GROWS;
-  const long long r1 = min(r0 + GROWS, nrows);
-  const int ncolp = nt * GT;
-  // the next stage's rows are loaded into registers while the MFMAs consume the
-  // current one (a fixed count per thread, so that the register array is indexed
-  // by constants)
-  constexpr int LPT = GCOL * GRB / 256;
+  dbl4 acc[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) acc[k] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  const long long step = (long long)gridDim.x * GRB;   // rows between this workgroup's blocks
+  const long long r0 = (long long)blockIdx.x * GRB;
+  // the next block's rows are loaded into registers while the MFMAs consume the
+  // current one: thread t loads rows t % GRB of columns t / GRB + 4 q
+  constexpr int LPT = NCP * GRB / 256;
   double nx[LPT];
   auto load = [&](long long rb) {
 #pragma unroll
@@ -312,50 +311,116 @@ __global__ __launch_bounds__(256) void k_gram(const double* A, long long lda, lo
       const int t = (int)threadIdx.x + q * 256;
       const int c = t / GRB, r = t % GRB;
       const long long row = rb + r;
-      nx[q] = (t < ncolp * GRB && c < ncol && row < r1) ? A[(long long)c * lda + row] : 0.0;
+      nx[q] = (c < ncol && row < nrows) ? A[(long long)c * lda + row] : 0.0;
     }
   };
   load(r0);
-  for (long long rb = r0; rb < r1; rb += GRB) {
+  constexpr int KW = GRB / 4;   // rows of a block per wave
+  for (long long rb = r0; rb < nrows; rb += step) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int t = (int)threadIdx.x + q * 256;
-      if (t < ncolp * GRB) tile[t / GRB][t % GRB] = nx[q];
+      lds[(t / GRB) * (GRB + 1) + t % GRB] = nx[q];
     }
     __syncthreads();
-    if (rb + GRB < r1) load(rb + GRB);
-    for (int k = 0; k < mine; ++k) {
-      const int ci = pi[k] * GT + (lane & 15);
-      const int cj = pj[k] * GT + (lane & 15);
-#pragma unroll 4
-      for (int kk = 0; kk < GRB; kk += 4) {
-        const double a = tile[ci][kk + (lane >> 4)];
-        const double b = tile[cj][kk + (lane >> 4)];
-        acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[k], 0, 0, 0);
-      }
+    if (rb + step < nrows) load(rb + step);
+#pragma unroll
+    for (int kk = wv * KW; kk < (wv + 1) * KW; kk += 4) {
+      double av[NT];
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti) av[ti] = lds[(ti * GT + (lane & 15)) * (GRB + 1) + kk + (lane >> 4)];
+      int k = 0;
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < NT; ++tj, ++k) acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], av[tj], acc[k], 0, 0, 0);
     }
   }
-  // f64 16x16x4 accumulator layout (checked on gfx950): element v of lane l holds
-  // D[row = l/16 + 4 v][col = l % 16] of tile (ti, tj) = sum_r A[ti*16+row][r] A[tj*16+col][r]
-  double* out = part + (long long)blockIdx.x * GCOL * GCOL;
-  for (int k = 0; k < mine; ++k) {
-    for (int v = 0; v < 4; ++v) {
-      const int i = pi[k] * GT + (lane >> 4) + 4 * v;
-      const int j = pj[k] * GT + (lane & 15);
-      out[i * GCOL + j] = acc[k][v];
-    }
+  // waves 2, 3 hand their sums to waves 0, 1 (w0 + w2, w1 + w3), then wave 1 to
+  // wave 0: G_part = (w0 + w2) + (w1 + w3)
+  __syncthreads();
+  auto put = [&](int slot) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lds[((slot * NP + k) * 4 + v) * 64 + lane] = acc[k][v];
+  };
+  auto add = [&](int slot) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[k][v] += lds[((slot * NP + k) * 4 + v) * 64 + lane];
+  };
+  if (wv >= 2) put(wv - 2);
+  __syncthreads();
+  if (wv < 2) add(wv);
+  __syncthreads();
+  if (wv == 1) put(0);
+  __syncthreads();
+  if (wv == 0) {
+    add(0);
+    // f64 16x16x4 accumulator layout (checked on gfx950): element v of lane l holds
+    // D[row = l/16 + 4 v][col = l % 16] of tile (ti, tj) = sum_r A[ti*16+row][r] A[tj*16+col][r]
+    double* out = part + (long long)blockIdx.x * GCOL * GCOL;
+    int k = 0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int tj = ti; tj < NT; ++tj, ++k)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = ti * GT + (lane >> 4) + 4 * v;
+          const int j = tj * GT + (lane & 15);
+          out[i * GCOL + j] = acc[k][v];
+        }
   }
 }
 
-// G = sum over workgroups of the partial Grams, in workgroup order; symmetrised.
-__global__ void k_gram_reduce(const double* part, int nwg, int ncol, double* G) {
-  for (int t = threadIdx.x + blockIdx.x * blockDim.x; t < ncol * ncol; t += gridDim.x * blockDim.x) {
+static void gram_partials(dim3 grid, hipStream_t s, const double* A, long long lda, long long nrows, int ncol,
+                          double* part) {
+  switch ((ncol + GT - 1) / GT) {
+    case 1: hipLaunchKernelGGL(k_gram<1>, grid, dim3(256), 0, s, A, lda, nrows, ncol, part); break;
+    case 2: hipLaunchKernelGGL(k_gram<2>, grid, dim3(256), 0, s, A, lda, nrows, ncol, part); break;
+    case 3: hipLaunchKernelGGL(k_gram<3>, grid, dim3(256), 0, s, A, lda, nrows, ncol, part); break;
+    case 4: hipLaunchKernelGGL(k_gram<4>, grid, dim3(256), 0, s, A, lda, nrows, ncol, part); break;
+    default: hipLaunchKernelGGL(k_gram<5>, grid, dim3(256), 0, s, A, lda, nrows, ncol, part); break;
+  }
+}
+
+// G = sum over workgroups of the partial Grams, symmetrised.  A block of RDW
+// waves takes 64 consecutive entries of G (lane = entry, so every load of a
+// wave reads consecutive partial entries); wave k sums the k-th of RDW equal
+// ranges of workgroups in order, and the RDW range sums are added in order
+// (a fixed order: the result does not depend on timing).
+constexpr int RDW = 16;
+__global__ __launch_bounds__(64 * RDW) void k_gram_reduce(const double* part, int nwg, int ncol, double* G) {
+  __shared__ double q[RDW][64];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + lane;
+  const int nn = ncol * ncol;
+  double s = 0.0;
+  if (t < nn) {
     int i = t / ncol, j = t % ncol;
-    if (i / GT > j / GT) { const int s = i; i = j; j = s; }
-    double s = 0.0;
-    for (int w = 0; w < nwg; ++w) s += part[(long long)w * GCOL * GCOL + i * GCOL + j];
-    G[(t / ncol) * ncol + (t % ncol)] = s;
+    if (i / GT > j / GT) {   // only tiles with tj >= ti were accumulated
+      const int x = i;
+      i = j;
+      j = x;
+    }
+    const double* src = part + i * GCOL + j;
+    const int per = (nwg + RDW - 1) / RDW;
+    const int w0 = wv * per, w1 = min(nwg, w0 + per);
+#pragma unroll 8
+    for (int w = w0; w < w1; ++w) s += src[(long long)w * GCOL * GCOL];
+  }
+  q[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && t < nn) {
+    double g = q[0][lane];
+#pragma unroll
+    for (int k = 1; k < RDW; ++k) g += q[k][lane];
+    G[t] = g;
   }
 }
 
@@ -973,9 +1038,10 @@ static int fit_t(mp_ctx* ctx, const Basis& b, int T_, const void* const* y, cons
   }
   Small* W = ws->small.as<Small>();
   auto gram = [&](double* Gdst) -> int {
-    hipLaunchKernelGGL(k_gram, dim3(nwg), dim3(256), 0, s, A, lda, nrows, p + 1, ws->part.as<double>());
+    gram_partials(dim3(nwg), s, A, lda, nrows, p + 1, ws->part.as<double>());
     SY_LAUNCH();
-    hipLaunchKernelGGL(k_gram_reduce, dim3(8), dim3(256), 0, s, ws->part.as<double>(), nwg, p + 1, Gdst);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(((p + 1) * (p + 1) + 63) / 64), dim3(64 * RDW), 0, s, ws->part.as<double>(), nwg,
+                       p + 1, Gdst);
     SY_LAUNCH();
     return MP_OK;
   };
