@@ -5,18 +5,36 @@
 
 namespace mp {
 
+// Fill with 16-byte stores: the body runs from the first 16-byte aligned element;
+// the head before it and the tail after it (under 16 bytes each) are stored
+// element by element.  p is aligned to sizeof(T).
 template <typename T>
 __global__ void k_fill(T* p, long long n, T v) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int V = 16 / (int)sizeof(T);
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long step = (long long)gridDim.x * blockDim.x;
-  for (; i < n; i += step) p[i] = v;
+  long long head = (long long)((16u - ((unsigned)(unsigned long long)p & 15u)) & 15u) / (long long)sizeof(T);
+  if (head > n) head = n;
+  const long long nv = (n - head) / V;
+  union {
+    T e[V];
+    uint4 u;
+  } pat;
+#pragma unroll
+  for (int k = 0; k < V; ++k) pat.e[k] = v;
+  uint4* q = reinterpret_cast<uint4*>(p + head);
+  for (long long i = tid; i < nv; i += step) q[i] = pat.u;
+  const long long t0 = head + nv * V;
+  if (tid < head) p[tid] = v;
+  if (tid < n - t0) p[t0 + tid] = v;
 }
 
 template <typename T>
 static void fill_t(T* p, long long n, T v, hipStream_t s) {
   if (n <= 0) return;
-  long long blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
+  constexpr long long V = 16 / (long long)sizeof(T);
+  long long blocks = (n / V + 255) / 256 + 1;   // covers the head and tail lanes too
+  if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
 }
 void fill(float* p, long long n, float v, hipStream_t s) { fill_t(p, n, v, s); }
