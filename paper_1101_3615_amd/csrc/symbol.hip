@@ -54,7 +54,7 @@ constexpr int MAXP = 64;          // basis terms
 constexpr int GT = 16;            // MFMA tile
 constexpr int GCOL = MAXP + GT;   // padded column count of [A b]
 constexpr int GRB = 64;           // rows per LDS stage of the Gram kernel
-constexpr int GROWS = 32768;      // rows per Gram workgroup
+constexpr int GROWS = 32768;      // rows per Gram workgroup (sets the workgroup count; each takes every nwg-th block)
 
 // ---------------------------------------------------------------- FFT --
 
