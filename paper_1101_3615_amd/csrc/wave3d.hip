@@ -34,7 +34,8 @@ typedef unsigned int u32x2_3 __attribute__((ext_vector_type(2)));
 constexpr unsigned OFF_NONE3 = 0x80000000u;
 // cache policy of the data that no other workgroup rereads soon (outputs, the
 // cell's own previous level, g, image): non-temporal, so that L2 keeps the field
-// rows that neighbouring tiles read as halos
+// rows that neighbouring tiles read as halos and the kappa and perturbation rows
+// that the other pairs of shots on the tile read
 constexpr int NT3 = 2;
 __device__ __forceinline__ Rsrc3 rsrc3(const void* base, long long bytes) {
   const int n = bytes >= 0xffffffffLL ? -1 : (int)(unsigned)bytes;
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int
     if (TWO) f.xb = bld4(rBc, xvo, s, T(0));
     f.kap = bld4(rK, lvo, s, T(0));
     if (TWO) f.bp = bld4<NT3>(rBp, lvo, s, T(0));
-    if (TWO || MODE == M_BORN) f.dm = bld4<NT3>(rM, lvo, s, T(0));
+    if (TWO || MODE == M_BORN) f.dm = bld4(rM, lvo, s, T(0));
     const unsigned zm = (unsigned)(z - nb);
     if (MODE == M_BORN || MODE == M_ADJ) f.g = bld4<NT3>(rG, gvo + zm * gplane, 0u, T(0));
     if (MODE == M_ADJ) f.im = bld4<NT3>(rI, ivo + (zm - 1u) * iplane, 0u, double(0));
