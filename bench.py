@@ -127,9 +127,15 @@ TRAFFIC = {"2d": ("traffic.json", "wave2d.hip"), "3d": ("traffic_c5.json", "wave
            "c3": ("traffic_c3.json", "wave2d.hip")}
 
 
-def traffic_for(kind, w):
+# shots per launch of the runs the counter summaries are taken on: the 512 x 256 leg (one
+# wave of 64), the 1024 x 512 leg (waves of 64) and the 256^3 benchmark (waves of 8)
+LAUNCH_SHOTS = {"2d": 64, "c3": 64, "3d": 8}
+
+
+def traffic_for(kind, w, nsh):
     """Measured HBM bytes per launch from the committed counter summary, if it was taken
-    on this workload with the kernel source as it is now (else None)."""
+    on this workload, with launches of nsh shots and with the kernel source as it is now
+    (else None)."""
     rec_name, src_name = TRAFFIC["3d" if w.ndim == 3 else "c3" if w.name.startswith("c3_") else "2d"]
     try:
         with open(os.path.join(ROOT, "profiles", rec_name)) as f:
@@ -138,7 +144,8 @@ def traffic_for(kind, w):
         return None
     digest = _sha(os.path.join(ROOT, "paper_1101_3615_amd", "csrc", src_name))
     k = rec.get("kernels", {}).get(kind)
-    if not k or rec.get("source_sha256", rec.get("wave2d_sha256")) != digest or rec.get("workload") != w.name:
+    if (not k or rec.get("source_sha256", rec.get("wave2d_sha256")) != digest or rec.get("workload") != w.name
+            or rec.get("launch_shots") != nsh):
         return None
     return k.get("bytes_per_launch")
 
@@ -273,7 +280,7 @@ def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_m
                          "fetch_kib_raw": a["fetch"] / n, "write_kib_raw": a["write"] / n,
                          "bytes_per_launch": (a["fetch"] * f_fac + a["write"] * w_fac) * 1024.0 / n}
     rec_name, src_name = TRAFFIC[dims]
-    rec = {"workload": {"3d": F.c5(), "c3": F.c3(), "2d": F.c2()}[dims].name,
+    rec = {"workload": {"3d": F.c5(), "c3": F.c3(), "2d": F.c2()}[dims].name, "launch_shots": LAUNCH_SHOTS[dims],
            "source_sha256": _sha(os.path.join(ROOT, "paper_1101_3615_amd", "csrc", src_name)),
            "fetch_scale": f_fac, "write_scale": w_fac, "copy_probe_bytes": copy_bytes, "kernels": kernels}
     with open(os.path.join(ROOT, "profiles", rec_name), "w") as f:
@@ -580,15 +587,16 @@ def sweep_table(st, bytes_of):
     return out
 
 
-def roofline_of(st, w, bytes_of, copy_gbs):
+def roofline_of(st, w, bytes_of, copy_gbs, nsh):
     """The sweep kind with the most device time: algorithmic bytes per launch over its
-    average launch time (HIP events on the call's stream), against the 8 TB/s peak."""
+    average launch time (HIP events on the call's stream), against the 8 TB/s peak; nsh:
+    shots per launch."""
     kind = max(st["ms_sweep"], key=lambda k: st["ms_sweep"][k])
     avg_s, spl = per_launch(st, kind)
     alg = bytes_of(kind, spl)
     achieved = alg / avg_s / 1e9
     r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-         "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for(kind, w), "kernel": kind,
+         "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for(kind, w, nsh), "kernel": kind,
          "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 3), "steps_per_launch": round(spl, 3)}
     if copy_gbs:
         r.update(copy_GBs=round(copy_gbs, 1), frac_of_copy=round(achieved / copy_gbs, 4))
@@ -654,7 +662,7 @@ def c2_leg(steps, copy_gbs):
            "ms_per_step": round(1e3 * wall, 2), "steps": steps, "dtype": "f32", "snapshots": "fp32 full g history",
            "value_is": "apply_H cell-steps of both trials per second of the pass; the first application "
                        "computes and keeps the g history, the second reuses it (no background sweep)",
-           "roofline": roofline_of(st, w, bytes_of, copy_gbs), "sweeps": sweep_table(st, bytes_of)}
+           "roofline": roofline_of(st, w, bytes_of, copy_gbs, w.ns), "sweeps": sweep_table(st, bytes_of)}
     P.close()
     return res
 
@@ -690,7 +698,7 @@ def c3_leg(nt, copy_gbs):
     res = {"workload": w.name, "value": round(w.cell_steps / wall / 1e9, 3), "unit": "Gcell-steps/s",
            "record_steps": F.c3().nt, "steps": nt, "waves": waves, "dtype": "f32",
            "snapshots": "bf16 checkpoints every 4 steps",
-           "roofline": roofline_of(st, w, bytes_of, copy_gbs), "sweeps": sweep_table(st, bytes_of)}
+           "roofline": roofline_of(st, w, bytes_of, copy_gbs, nsh), "sweeps": sweep_table(st, bytes_of)}
     P.close()
     return res
 
@@ -714,6 +722,9 @@ def main():
     ap.add_argument("--volume-steps", type=int, default=0,
                     help="only run apply_H on the 256^3 workload (32 shots, BF16 checkpoints) with this "
                          "many time steps and print its sweep times (3D measurement and profiling)")
+    ap.add_argument("--leg", choices=("c2", "c3"), default=None,
+                    help="run one extra leg alone (the 512x256 pass or the 1024x512 application) and print its "
+                         "JSON: the command the counter and trace summaries of those workloads are taken on")
     ap.add_argument("--checkpointed-steps", type=int, default=0,
                     help="only run apply_H on the 1024x512 workload (128 shots, BF16 checkpoints every 4 steps) "
                          "with this many time steps and print its sweep times")
@@ -756,6 +767,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}))
+        return
+    if args.leg:
+        import torch
+        copy_gbs = copy_rate(torch.device("cuda:0"))
+        print(json.dumps(c2_leg(1, copy_gbs) if args.leg == "c2" else c3_leg(400, copy_gbs)))
         return
     if args.checkpointed_steps:
         print(json.dumps(checkpointed_run(args.checkpointed_steps)))
@@ -886,7 +902,7 @@ def main():
                    "image": "fp64", "apply_H_cell_steps_per_step": cell_steps,
                    "value_is": f"apply_H rate over {w.nt} of the {w_full.nt} record steps per application, "
                                "extrapolated to the full record (same launches per step)"},
-        "roofline": roofline_of(st, w, bytes_of, copy_gbs),
+        "roofline": roofline_of(st, w, bytes_of, copy_gbs, wave),
         "cpu_baseline": cpu,
         "serving": serving,
         "sweeps": sweep_table(st, bytes_of),

@@ -54,7 +54,7 @@ constexpr int MAXP = 64;          // basis terms
 constexpr int GT = 16;            // MFMA tile
 constexpr int GCOL = MAXP + GT;   // padded column count of [A b]
 constexpr int GRB = 64;           // rows per LDS stage of the Gram kernel
-constexpr int GROWS = 32768;      // rows per Gram workgroup (sets the workgroup count; each takes every nwg-th block)
+constexpr int GWGMAX = 2048;      // Gram workgroups at most (each takes every nwg-th block, at least 8 blocks)
 
 // ---------------------------------------------------------------- FFT --
 
@@ -999,7 +999,7 @@ static int fit_t(mp_ctx* ctx, const Basis& b, int T_, const void* const* y, cons
   if ((rc = ws->cx0.ensure(sizeof(Cx<double>) * n, &ctx->budget, "fft work"))) return rc;
   if ((rc = ws->cx1.ensure(sizeof(Cx<double>) * n, &ctx->budget, "fft work"))) return rc;
   if ((rc = ws->A.ensure(sizeof(double) * (size_t)(p + 1) * lda, &ctx->budget, "fit columns"))) return rc;
-  const int nwg = (int)((nrows + GROWS - 1) / GROWS);
+  const int nwg = (int)std::min<long long>(GWGMAX, std::max<long long>(1, (nrows + 8 * GRB - 1) / (8 * GRB)));
   if ((rc = ws->part.ensure(sizeof(double) * (size_t)std::max(nwg * GCOL * GCOL, 4096), &ctx->budget, "partials")))
     return rc;
   if ((rc = ws->G0.ensure(sizeof(double) * GCOL * GCOL, &ctx->budget, "gram"))) return rc;
