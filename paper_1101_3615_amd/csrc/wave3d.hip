@@ -151,8 +151,12 @@ __device__ __forceinline__ void lap_row(const V4<T>* qa, int r, const V4<T>& xh,
 // step (one barrier per plane serves both), so the second read of kappa and the
 // perturbation hits in cache, and the adjoint images the pair into one FP64 image
 // (the pair's contributions summed in shot order in LDS, one read-modify-write).
+// The background sweeps that store no checkpoint (the recomputation) are held to
+// four waves per SIMD (128 VGPRs), so that two workgroups share a CU; the others
+// would spill at that bound.
 template <typename T, int MODE, int CK>
-__global__ __launch_bounds__(512) void k_step3d(Step<T> p, int n, int hslot, int ck_store, int ck_max) {
+__global__ __launch_bounds__(512, (MODE == M_BG && CK != CK_F32 && CK != CK_BF16) ? 4 : 1) void k_step3d(
+    Step<T> p, int n, int hslot, int ck_store, int ck_max) {
   constexpr bool TWO = (MODE == M_FUSED);
   // LDS plane per half and field: the tile's rows plus four halo rows above and
   // below (double buffered: one barrier per plane)
