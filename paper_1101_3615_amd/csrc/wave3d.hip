@@ -13,8 +13,9 @@
 // loaded through buffer resources one plane ahead (FP32 sweeps), so its latency
 // overlaps the work on the plane before; lanes and planes outside the grid read
 // zero from the hardware range check instead of branching.
-// Workgroups are persistent and walk their XCD's items pairs of shots fastest, so
-// the pairs of a tile share its kappa and perturbation through that XCD's L2.
+// Workgroups are persistent and walk their XCD's items tiles fastest, so the
+// workgroups of a round hold a block of neighbouring tiles of one pair of shots and
+// each tile's halo rows come from that XCD's L2.
 // The arithmetic per cell is that of the 2D kernel with the y axis added,
 // including its two forms of the imaging condition (g^{k-1} nu^k, or u^k times
 // c^2 (L nu^{k+1} + R^T d) when the slots hold background levels).
@@ -182,17 +183,20 @@ __global__ __launch_bounds__(512, (MODE == M_BG && CK != CK_F32 && CK != CK_BF16
   for (int k = (int)(blockIdx.x >> 3); k < per; k += spx) {
   const int item = xcd * per + k;
   if (item >= p.nwg) break;
-  // pairs of shots fastest, then x tiles, y tiles and z chunks: the workgroups
-  // that run together on one XCD carry every pair of a few neighbouring tiles, so
-  // kappa and the perturbation of a tile come from HBM once and reach the other
-  // pairs from that XCD's L2 (marching in step)
+  // x tiles fastest, then y tiles, pairs of shots and z chunks: the workgroups that
+  // run together on one XCD carry one pair over a block of neighbouring tiles, so the
+  // x and y halo rows a tile reads are the rows its neighbours are loading at the
+  // same plane, from that XCD's L2 (marching in step).  (Pairs fastest, which
+  // shares kappa and the perturbation of a tile between the pairs instead, moved
+  // more bytes: halo rows are a third of the reads.)
   const int npair = p.nsh >> 1;
-  const int ls = (item % npair) * 2 + half;
-  int rest = item / npair;
-  const int tx = rest % p.L.nstrips;
-  rest /= p.L.nstrips;
-  const int ty = rest % p.L.nytiles;
-  const int chunk = rest / p.L.nytiles;
+  const int ntile = p.L.nstrips * p.L.nytiles;
+  const int tile = item % ntile;
+  int rest = item / ntile;
+  const int tx = tile % p.L.nstrips;
+  const int ty = tile / p.L.nstrips;
+  const int ls = (rest % npair) * 2 + half;
+  const int chunk = rest / npair;
   const int z0 = chunk * p.zc;
   const int z1 = min(z0 + p.zc, p.L.nzp);
 
