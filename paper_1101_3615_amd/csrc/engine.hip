@@ -725,6 +725,21 @@ class EngineT final : public Engine {
     return span_end(sp);
   }
 
+  // 3D reverse sweeps (background recomputation, adjoint): twice the forward z-chunk
+  // count, unless a height is forced.  Shorter items keep the workgroups of a round
+  // in step through the planes, so more of their halo rows meet in L2; the fused
+  // forward sweep, with the most bytes per plane, loses more to the extra chunk
+  // boundaries than it gains.
+  void rechunk_reverse3d(Step<T>& p) const {
+    if (zc_target_ > 0) return;
+    const int nch = p.nchunks * 2;
+    const int zc = (L_.nzp + nch - 1) / nch;
+    if (zc < 32) return;
+    p.nchunks = (L_.nzp + zc - 1) / zc;
+    p.zc = (L_.nzp + p.nchunks - 1) / p.nchunks;
+    p.nwg = (int)((long long)(p.nsh / 2) * L_.nstrips * L_.nytiles * p.nchunks);
+  }
+
   int adjoint(int s0, int nsh, int W, const T* data) {
     if (cfg_.ndim == 2) return adjoint2d(s0, nsh, W, data);
     int rc;
@@ -736,6 +751,7 @@ class EngineT final : public Engine {
     fill(img_.as<double>() + (long long)(s0 / gsz()) * L_.mstride, (long long)(nsh / gsz()) * L_.mstride, 0.0,
          stream_);
     Step<T> p = params(s0, nsh, W);
+    rechunk_reverse3d(p);
     p.data = const_cast<T*>(data);
     Span* sp;
     if (!ckpt_mode()) {
@@ -755,7 +771,11 @@ class EngineT final : public Engine {
     const int ck = ck_kind();
     const int nbg = hmod_ > 0 ? hmod_ : nsh;
     p.hist_u = 1;
-    Step<T> pb = hmod_ > 0 ? params(s0, nbg, W) : p;   // the background entries' launches
+    Step<T> pb = p;   // the background entries' launches
+    if (hmod_ > 0) {
+      pb = params(s0, nbg, W);
+      rechunk_reverse3d(pb);
+    }
     pb.hist_u = 1;
     for (int j = nck() - 1; j >= 0; --j) {
       const int n0 = j * kk;
