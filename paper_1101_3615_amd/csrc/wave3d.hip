@@ -199,6 +199,14 @@ __global__ __launch_bounds__(512, (MODE == M_BG && CK != CK_F32 && CK != CK_BF16
   const int chunk = rest / npair;
   const int z0 = chunk * p.zc;
   const int z1 = min(z0 + p.zc, p.L.nzp);
+  // odd chunks march down (z1 - 1 .. z0), even chunks up, so that two neighbouring
+  // chunks reach the planes around their shared boundary together (both at the end
+  // or both at the start of their march) and the second read of those planes finds
+  // them in the last-level cache; the Laplacian sums each symmetric pair of planes
+  // commutatively, so the direction changes no result bit
+  const int dz3 = (chunk & 1) ? -1 : 1;
+  const int zs = dz3 > 0 ? z0 : z1 - 1;
+  const int nit = z1 - z0;
 
   const int pitch = p.L.pitch;
   const long long plane = p.L.plane;
@@ -336,34 +344,34 @@ __global__ __launch_bounds__(512, (MODE == M_BG && CK != CK_F32 && CK != CK_BF16
   // registers); FP64 sweeps (small test grids, twice the registers) at the start
   // of the plane.
   struct In3 {
-    V4<T> qa, qb;          // plane z + 4 of fields A, B (enters the queue)
+    V4<T> qa, qb;          // plane z + 4d of fields A, B (enters the queue; d = march direction)
     V4<T> hv;              // y-halo row of plane z (field A or B)
     V4<T> xa, xb;          // x halos of plane z
     V4<T> kap, ap, bp, dm; // kappa, A increment / level n-1, B level n-1, perturbation
     V4<T> g;               // Born / adjoint: g of plane z
-    V4<double> im;         // adjoint: the pair's image on plane z - 1 (even half)
+    V4<double> im;         // adjoint: the pair's image on the previous plane z - d (even half)
   };
   auto fetch = [&](int z, In3& f) {
     const unsigned s = soff(z);
     if (LDCK) {
-      f.qa = ldck(0, clvo, z + 4);
+      f.qa = ldck(0, clvo, z + 4 * dz3);
       f.hv = ldck(0, chvo, z);
       f.xa = ldck(0, cxvo, z);
       f.ap = ldck(1, clvo, z);
     } else {
-      f.qa = bld4(rAc, lvo, soff(z + 4), T(0));
+      f.qa = bld4(rAc, lvo, soff(z + 4 * dz3), T(0));
       f.hv = bld4(rHv, hvo, s, T(0));
       f.xa = bld4(rAc, xvo, s, T(0));
       f.ap = bld4<NT3>(rAp, lvo, s, T(0));
     }
-    if (TWO) f.qb = bld4(rBc, lvo, soff(z + 4), T(0));
+    if (TWO) f.qb = bld4(rBc, lvo, soff(z + 4 * dz3), T(0));
     if (TWO) f.xb = bld4(rBc, xvo, s, T(0));
     f.kap = bld4(rK, lvo, s, T(0));
     if (TWO) f.bp = bld4<NT3>(rBp, lvo, s, T(0));
     if (TWO || MODE == M_BORN) f.dm = bld4(rM, lvo, s, T(0));
     const unsigned zm = (unsigned)(z - nb);
     if (MODE == M_BORN || MODE == M_ADJ) f.g = bld4<NT3>(rG, gvo + zm * gplane, 0u, T(0));
-    if (MODE == M_ADJ) f.im = bld4<NT3>(rI, ivo + (zm - 1u) * iplane, 0u, double(0));
+    if (MODE == M_ADJ) f.im = bld4<NT3>(rI, ivo + (zm - (unsigned)dz3) * iplane, 0u, double(0));
   };
   constexpr bool PF3 = sizeof(T) == 4;
 
@@ -384,18 +392,19 @@ __global__ __launch_bounds__(512, (MODE == M_BG && CK != CK_F32 && CK != CK_BF16
   V4<T> qa[9], qb[9];
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
-    qa[s] = LDCK ? ldck(0, clvo, z0 - 4 + s) : bld4(rAc, lvo, soff(z0 - 4 + s), T(0));
-    if (TWO) qb[s] = bld4(rBc, lvo, soff(z0 - 4 + s), T(0));
+    qa[s] = LDCK ? ldck(0, clvo, zs + (s - 4) * dz3) : bld4(rAc, lvo, soff(zs + (s - 4) * dz3), T(0));
+    if (TWO) qb[s] = bld4(rBc, lvo, soff(zs + (s - 4) * dz3), T(0));
   }
   In3 cur, nxt;
-  if (PF3) fetch(z0, cur);
+  if (PF3) fetch(zs, cur);
 
-  for (int zb = z0; zb < z1; zb += 9) {
+  for (int tb = 0; tb < nit; tb += 9) {
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
-      const int z = zb + r;
-      if (z < z1) {   // uniform; a constant trip count keeps the loop fully unrolled
-        if (PF3) fetch(min(z + 1, z1 - 1), nxt);   // the last plane reloads itself
+      const int t = tb + r;
+      const int z = zs + t * dz3;
+      if (t < nit) {   // uniform; a constant trip count keeps the loop fully unrolled
+        if (PF3) fetch(t + 1 < nit ? z + dz3 : z, nxt);   // the last plane reloads itself
         else fetch(z, cur);
         qa[(r + 8) % 9] = cur.qa;
         if (TWO) qb[(r + 8) % 9] = cur.qb;
@@ -409,7 +418,7 @@ __global__ __launch_bounds__(512, (MODE == M_BG && CK != CK_F32 && CK != CK_BF16
         lap_row(qa, r, cur.xa, PL[half][0][buf], yl, c * 4, p, lapA);
         if (TWO) lap_row(qb, r, cur.xb, PL[half][NB - 1][buf], yl, c * 4, p, lapB);
         buf ^= 1;
-        if (MODE == M_ADJ && z > z0) pair_image(z - 1, cur.im);
+        if (MODE == M_ADJ && t > 0) pair_image(z - dz3, cur.im);
         const unsigned sz_ = soff(z);
 
         if ((MODE == M_FUSED || MODE == M_BG) && z == sz && y == sy) {
@@ -568,7 +577,8 @@ __global__ __launch_bounds__(512, (MODE == M_BG && CK != CK_F32 && CK != CK_BF16
   }
   if (MODE == M_ADJ) {   // the item's last plane
     lds_barrier();
-    pair_image(z1 - 1, bld4<NT3>(rI, ivo + (unsigned)(z1 - 1 - nb) * iplane, 0u, double(0)));
+    const int zl = zs + (nit - 1) * dz3;
+    pair_image(zl, bld4<NT3>(rI, ivo + (unsigned)(zl - nb) * iplane, 0u, double(0)));
   }
   if (CK == CK_BF16 && (MODE == M_FUSED || MODE == M_BG) && ck_max >= 0) {
     for (int o = 32; o > 0; o >>= 1) {
