@@ -84,6 +84,14 @@ __device__ __forceinline__ unsigned short bf16_rne(float f) {
   return (unsigned short)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+// A BF16 code times its level's scale, rounded on its own: the pragma keeps the
+// compiler from fusing the product into a later add (which it may do at some
+// unrolled copies of a march body and not at others), so a decoded value does not
+// depend on where it is decoded.
+__device__ __forceinline__ float bf16_scaled(unsigned short h, float s) {
+#pragma clang fp contract(off)
+  return bf16_to_f(h) * s;
+}
 
 template <typename T>
 __device__ __forceinline__ V4<T> ld4(const T* p) {

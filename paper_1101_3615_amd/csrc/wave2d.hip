@@ -130,8 +130,17 @@ __device__ __forceinline__ double mov_shl1<double>(double v) {
 }
 // Products and fused multiply-adds with the rounding spelled out, so that the
 // damped and undamped forms of the update below give the same bits where a = b = 1.
-__device__ __forceinline__ float rmul(float a, float b) { return __fmul_rn(a, b); }
-__device__ __forceinline__ double rmul(double a, double b) { return __dmul_rn(a, b); }
+// A product is rounded on its own: the pragma keeps the compiler from fusing it
+// into a later add (which it may do with a plain product, at some unrolled copies
+// of the march body and not at others).
+__device__ __forceinline__ float rmul(float a, float b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+__device__ __forceinline__ double rmul(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
 __device__ __forceinline__ float rfma(float a, float b, float c) { return __fmaf_rn(a, b, c); }
 __device__ __forceinline__ double rfma(double a, double b, double c) { return __fma_rn(a, b, c); }
 
@@ -381,8 +390,8 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
     const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(lev ? rC1 : rC0, cvo + (unsigned)z * crow, 0u, 0);
     const float sc = lev ? cs1 : cs0;
     V2<T> r;
-    r.v[0] = (T)(bf16_to_f((unsigned short)(w & 0xffffu)) * sc);
-    r.v[1] = (T)(bf16_to_f((unsigned short)(w >> 16)) * sc);
+    r.v[0] = (T)bf16_scaled((unsigned short)(w & 0xffffu), sc);
+    r.v[1] = (T)bf16_scaled((unsigned short)(w >> 16), sc);
     return r;
   };
   // g rows: a pair that ends past nx stores zero into the model row's pad column,

@@ -333,10 +333,10 @@ __global__ __launch_bounds__(512, (MODE == M_BG && CK != CK_F32 && CK != CK_BF16
     const u32x2_3 w = __builtin_amdgcn_raw_buffer_load_b64(lev ? rC1 : rC0, off, 0u, 0);
     const float sc = lev ? cs1 : cs0;
     V4<T> r;
-    r.v[0] = (T)(bf16_to_f((unsigned short)(w.x & 0xffffu)) * sc);
-    r.v[1] = (T)(bf16_to_f((unsigned short)(w.x >> 16)) * sc);
-    r.v[2] = (T)(bf16_to_f((unsigned short)(w.y & 0xffffu)) * sc);
-    r.v[3] = (T)(bf16_to_f((unsigned short)(w.y >> 16)) * sc);
+    r.v[0] = (T)bf16_scaled((unsigned short)(w.x & 0xffffu), sc);
+    r.v[1] = (T)bf16_scaled((unsigned short)(w.x >> 16), sc);
+    r.v[2] = (T)bf16_scaled((unsigned short)(w.y & 0xffffu), sc);
+    r.v[3] = (T)bf16_scaled((unsigned short)(w.y >> 16), sc);
     return r;
   };
 

@@ -258,3 +258,33 @@ def test_zero_inputs_give_exact_zeros(dtype):
     assert not torch.any(P.apply_H(zm).cpu())
     assert not torch.any(P.apply_F(zm).cpu())
     assert not torch.any(P.apply_Fadj(torch.zeros((w.ns, w.nt, w.nr))).cpu())
+
+
+@pytest.mark.parametrize("snap,k", [("full", 0), ("ckpt_bf16", 4), ("ckpt_bf16", 7)])
+def test_z_chunk_heights_give_the_same_bits(snap, k, monkeypatch):
+    """Forced z-chunk heights on the 110-row propagation grid: 4 rows (28 chunks), 12
+    (10 chunks, the last one, marching down, two rows) and 110 (one chunk) against the
+    launcher's own choice.  Neighbouring chunks march in opposite directions and the
+    BF16 checkpoint scales take maxima over every chunk (segments of 7 steps end on a
+    one-step launch); none of this may change a bit of F, F* or H.  The one-chunk F
+    matches the oracle."""
+    w = ragged("f32", nt=60)
+    M = _gpu()
+    c = F.medium(w)
+    dm = torch.from_numpy(F.wavepackets(w, c, 95, 6))
+    d = torch.from_numpy(F.normal_field((w.ns, w.nt, w.nr), 96))
+    outs = {}
+    for zc in (None, 4, 12, 110):
+        if zc is None:
+            monkeypatch.delenv("MP_ZC", raising=False)
+        else:
+            monkeypatch.setenv("MP_ZC", str(zc))
+        P = M.Problem.from_spec(w, snap=snap, ckpt_every=k)
+        P.set_background(torch.from_numpy(c))
+        outs[zc] = [P.apply_F(dm).cpu().numpy(), P.apply_Fadj(d).cpu().numpy(), P.apply_H(dm).cpu().numpy()]
+        P.close()
+    monkeypatch.delenv("MP_ZC", raising=False)
+    for zc in (None, 4, 12):
+        for name, a, b in zip(("F", "F*", "H"), outs[zc], outs[110]):
+            assert np.array_equal(a, b), f"{name} with chunk height {zc} differs from one chunk"
+    assert rel(outs[110][0], Oracle(w, c).apply_F(dm.numpy())) <= 1e-5

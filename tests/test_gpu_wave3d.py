@@ -297,3 +297,26 @@ def test_c5_full_shape_sampled_shot_against_oracle():
         print(f"256^3 workload, waves of 8, shot {s}, {snap}: apply_F {err_F:.3e}, apply_Fadj {err_A:.3e}")
         assert err_F <= 1e-5
         assert err_A <= tol
+
+
+@pytest.mark.parametrize("snap,k", [("full", 0), ("ckpt_bf16", 8)])
+def test_3d_z_chunk_heights_give_the_same_bits(snap, k):
+    """Forced z-chunk heights on the 34-plane propagation grid of the cube: 4 planes (9
+    chunks, the last two planes), 6 (6 chunks, the last one, marching down, four planes)
+    and 9 (4 chunks, the last marching down) against one chunk per tile: odd chunks march
+    down and even ones up, and no bit of F, F* or H may depend on it."""
+    M = _gpu()
+    w = cube("f32", nt=40, snap=snap, k=k)
+    c = F.medium(w)
+    dm = torch.from_numpy(F.normal_field(w.model_shape, 57))
+    d = torch.from_numpy(F.normal_field((w.ns, w.nt, w.nr), 58))
+    outs = {}
+    for zc in (4, 6, 9, 34):
+        with _env(MP_ZC=zc):
+            P = M.Problem.from_spec(w)
+        P.set_background(torch.from_numpy(c))
+        outs[zc] = [P.apply_F(dm).cpu().numpy(), P.apply_Fadj(d).cpu().numpy(), P.apply_H(dm).cpu().numpy()]
+        P.close()
+    for zc in (4, 6, 9):
+        for name, a, b in zip(("F", "F*", "H"), outs[zc], outs[34]):
+            assert np.array_equal(a, b), f"{name} with chunk height {zc} differs from one chunk"
