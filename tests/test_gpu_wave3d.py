@@ -299,7 +299,7 @@ def test_c5_full_shape_sampled_shot_against_oracle():
         assert err_A <= tol
 
 
-@pytest.mark.parametrize("snap,k", [("full", 0), ("ckpt_bf16", 8)])
+@pytest.mark.parametrize("snap,k", [("full", 0), ("ckpt_bf16", 8), ("ckpt_f32", 1)])
 def test_3d_z_chunk_heights_give_the_same_bits(snap, k):
     """Forced z-chunk heights on the 34-plane propagation grid of the cube: 4 planes (9
     chunks, the last two planes), 6 (6 chunks, the last one, marching down, four planes)
