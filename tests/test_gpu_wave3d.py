@@ -320,3 +320,30 @@ def test_3d_z_chunk_heights_give_the_same_bits(snap, k):
     for zc in (4, 6, 9):
         for name, a, b in zip(("F", "F*", "H"), outs[zc], outs[34]):
             assert np.array_equal(a, b), f"{name} with chunk height {zc} differs from one chunk"
+
+
+@pytest.mark.parametrize("snap,k", [("full", 0), ("ckpt_bf16", 8)])
+def test_3d_wave_sizes_give_the_same_bits(snap, k):
+    """Six shots in waves of 2, 4 (4 + 2) and 6: the job's images are stacked per pair
+    of shots and summed in one fixed order, so no bit of F, F* or H may depend on how
+    the shots are split into waves; the three-wave F* matches the oracle."""
+    M = _gpu()
+    w = cube("f32", nt=40, snap=snap, k=k)
+    w = w.with_(src=np.array([[3, 5, 0], [w.nx - 2, w.ny // 2, 2], [50, 11, 9], [20, 3, 4], [70, 18, 1],
+                              [90, 7, 12]], np.int32))
+    c = F.medium(w)
+    dm = torch.from_numpy(F.normal_field(w.model_shape, 71))
+    d = torch.from_numpy(F.normal_field((w.ns, w.nt, w.nr), 72))
+    outs = {}
+    for wave in (2, 4, 6):
+        with _env(MP_MAX_WAVE=wave):
+            P = M.Problem.from_spec(w)
+            P.set_background(torch.from_numpy(c))
+            outs[wave] = [P.apply_F(dm).cpu().numpy(), P.apply_Fadj(d).cpu().numpy(), P.apply_H(dm).cpu().numpy()]
+            assert P.stats()["waves"] == 6 // wave + (6 % wave > 0)
+            P.close()
+    for wave in (2, 4):
+        for name, a, b in zip(("F", "F*", "H"), outs[wave], outs[6]):
+            assert np.array_equal(a, b), f"{name} in waves of {wave} differs from one wave"
+    tol = 1e-5 if snap == "full" else 1e-2
+    assert rel(outs[2][1], Oracle(w, c).apply_Fadj(d.numpy())) <= tol
