@@ -470,7 +470,7 @@ __global__ __launch_bounds__(64 * GW2) void k_sweep2d(Step<T> p, int n, int hs1,
       }
     }
   };
-  // March direction: even chunks go down (z increasing), odd chunks up, so that
+  // March direction: even chunks with z increasing, odd chunks with z decreasing, so that
   // two neighbouring chunks reach the rows around their shared boundary at the
   // same time and the second reads of those rows hit in L2.  The queue holds rows
   // in march order; the Laplacian sums each symmetric pair commutatively, so the

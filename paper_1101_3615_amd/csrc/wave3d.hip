@@ -199,7 +199,7 @@ __global__ __launch_bounds__(512, (MODE == M_BG && CK != CK_F32 && CK != CK_BF16
   const int chunk = rest / npair;
   const int z0 = chunk * p.zc;
   const int z1 = min(z0 + p.zc, p.L.nzp);
-  // odd chunks march down (z1 - 1 .. z0), even chunks up, so that two neighbouring
+  // odd chunks march with z decreasing (z1 - 1 .. z0), even chunks with z increasing, so that two neighbouring
   // chunks reach the planes around their shared boundary together (both at the end
   // or both at the start of their march) and the second read of those planes finds
   // them in the last-level cache; the Laplacian sums each symmetric pair of planes

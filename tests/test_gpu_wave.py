@@ -264,7 +264,7 @@ def test_zero_inputs_give_exact_zeros(dtype):
                                           ("f32", "ckpt_f32", 7), ("f64", "full", 0)])
 def test_z_chunk_heights_give_the_same_bits(dtype, snap, k, monkeypatch):
     """Forced z-chunk heights on the 110-row propagation grid: 4 rows (28 chunks), 12
-    (10 chunks, the last one, marching down, two rows) and 110 (one chunk) against the
+    (10 chunks, the last one, with z decreasing, two rows) and 110 (one chunk) against the
     launcher's own choice.  Neighbouring chunks march in opposite directions and the
     BF16 checkpoint scales take maxima over every chunk (segments of 7 steps end on a
     one-step launch); none of this may change a bit of F, F* or H.  The one-chunk F

@@ -302,9 +302,9 @@ def test_c5_full_shape_sampled_shot_against_oracle():
 @pytest.mark.parametrize("snap,k", [("full", 0), ("ckpt_bf16", 8), ("ckpt_f32", 1)])
 def test_3d_z_chunk_heights_give_the_same_bits(snap, k):
     """Forced z-chunk heights on the 34-plane propagation grid of the cube: 4 planes (9
-    chunks, the last two planes), 6 (6 chunks, the last one, marching down, four planes)
-    and 9 (4 chunks, the last marching down) against one chunk per tile: odd chunks march
-    down and even ones up, and no bit of F, F* or H may depend on it."""
+    chunks, the last two planes), 6 (6 chunks, the last one, with z decreasing, four planes)
+    and 9 (4 chunks, the last with z decreasing) against one chunk per tile: odd chunks
+    march with z decreasing and even ones with z increasing, and no bit of F, F* or H may depend on it."""
     M = _gpu()
     w = cube("f32", nt=40, snap=snap, k=k)
     c = F.medium(w)
